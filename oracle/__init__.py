@@ -1,0 +1,127 @@
+"""Reference oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, double-precision CPU reconstruction (``oracle.c``, built with
+gcc) plus the CPU reference of the surrogate network (``conv.py``).  Only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_2412_11639_amd``) and never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+FSR = 1
+SSR = 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+P_u8 = ctypes.POINTER(ctypes.c_uint8)
+P_i32 = ctypes.POINTER(ctypes.c_int32)
+P_f64 = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = True, src: str = _SRC, out: str = _LIB_PATH) -> str:
+    """Compile oracle.c with gcc into a shared library."""
+    if not force and os.path.exists(out):
+        return out
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", src,
+                           "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
+def _bind(lib):
+    lib.spk_oracle_segment_intervals.restype = ctypes.c_int32
+    lib.spk_oracle_segment_intervals.argtypes = [P_i32, ctypes.c_int32, ctypes.c_int32, P_i32]
+    lib.spk_oracle_reconstruct.restype = ctypes.c_int32
+    lib.spk_oracle_reconstruct.argtypes = [
+        P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P_i32,
+        ctypes.c_int32, ctypes.c_int32, P_f64, P_i32, P_i32, P_i32, ctypes.c_int32]
+    lib.spk_oracle_segments.restype = ctypes.c_int32
+    lib.spk_oracle_segments.argtypes = [
+        P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+        P_i32, P_i32, P_i32, P_i32, ctypes.c_int32]
+    return lib
+
+
+def load(path: str | None = None):
+    """Load the oracle library (building it if absent); ``path`` loads another
+    build of the same source, e.g. a deliberately broken copy in a test."""
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _nthreads(n):
+    return int(n if n is not None else min(16, os.cpu_count() or 1))
+
+
+def segment_intervals(x, order: int = FSR, lib=None) -> list:
+    """Segment an interval stream S1 directly; returns the list of segment
+    start indices (0-based interval indices)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    start = np.zeros(max(1, len(x)), dtype=np.int32)
+    n = lib.spk_oracle_segment_intervals(_ptr(x, P_i32), len(x), order, _ptr(start, P_i32))
+    if n < 0:
+        raise ValueError("bad arguments")
+    return start[:n].tolist()
+
+
+def reconstruct(stream, H, W, T, theta, t_out, order=FSR, windows=False, nthreads=None,
+                lib=None):
+    """Intensity per output time and pixel, [n_out, H, W] float64.  With
+    ``windows`` also returns (first, last, n) int32 arrays of the same shape."""
+    lib = lib or load()
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    t_out = np.ascontiguousarray(t_out, dtype=np.int32)
+    n_out = len(t_out)
+    out = np.zeros((n_out, H, W), dtype=np.float64)
+    wf = wl = wn = None
+    if windows:
+        wf = np.zeros((n_out, H, W), dtype=np.int32)
+        wl = np.zeros((n_out, H, W), dtype=np.int32)
+        wn = np.zeros((n_out, H, W), dtype=np.int32)
+    rc = lib.spk_oracle_reconstruct(_ptr(stream, P_u8), H, W, T, float(theta),
+                                    _ptr(t_out, P_i32), n_out, order, _ptr(out, P_f64),
+                                    _ptr(wf, P_i32), _ptr(wl, P_i32), _ptr(wn, P_i32),
+                                    _nthreads(nthreads))
+    if rc != 0:
+        raise ValueError("spk_oracle_reconstruct: bad arguments")
+    return (out, wf, wl, wn) if windows else out
+
+
+def segments(stream, H, W, T, order=FSR, cap=64, nthreads=None, lib=None):
+    """All segments per pixel: (first, last, n) each [cap, H*W] int32, and
+    the total count per pixel [H*W]."""
+    lib = lib or load()
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    hw = H * W
+    sf = np.full((cap, hw), -1, dtype=np.int32)
+    sl = np.full((cap, hw), -1, dtype=np.int32)
+    sn = np.zeros((cap, hw), dtype=np.int32)
+    cnt = np.zeros(hw, dtype=np.int32)
+    rc = lib.spk_oracle_segments(_ptr(stream, P_u8), H, W, T, order, cap, _ptr(sf, P_i32),
+                                 _ptr(sl, P_i32), _ptr(sn, P_i32), _ptr(cnt, P_i32),
+                                 _nthreads(nthreads))
+    if rc != 0:
+        raise ValueError("spk_oracle_segments: bad arguments")
+    return sf, sl, sn, cnt

@@ -1,0 +1,356 @@
+/*
+ * Reference oracle for spike-stream reconstruction -- TEST INFRASTRUCTURE.
+ *
+ * A plain, slow, obviously correct CPU implementation of what the GPU
+ * library computes, in double precision.  Only the tests, the smoke check and
+ * the benchmark's CPU-baseline leg may build, load or call it; the product
+ * path never does.  It shares no code with the GPU library.
+ *
+ * Paper: "High-speed and High-quality Vision Reconstruction of Spike Camera
+ * with Spike Stability Theorem" (arXiv 2412.11639).  Notation follows it:
+ * S0 is a pixel's binary stream, S1 = {T0(1), T0(2), ...} its inter-spike
+ * intervals (Def. 2, Eq. 4), S2 the interval streams of S1 (Eq. 5).
+ *
+ * Steps per pixel (each function cites the passage it follows):
+ *   O-1 spikes        frames whose bit is set                     (Eq. 2)
+ *   O-2 intervals     T0(i) = tau(i+1) - tau(i)                   (Def. 2, Eq. 4)
+ *   O-3 FSR           greedy cut where S1 leaves zero-order stability
+ *                                                    (Sec. III-B; Sec. III-C module)
+ *   O-4 SSR           inside each FSR segment, cut where the S2 stream of
+ *                     either interval value leaves zero-order stability
+ *                                                    (Sec. III-B, Fig. 1 caption)
+ *   O-6 output time   the segment holding the interval in progress at t
+ *   O-7 intensity     I = theta * N / sum_i T0(i)                 (Eq. 6)
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes of the repository):
+ *   - zero-order stable == the values span at most 1 (max - min <= 1);
+ *   - a violating interval closes the open segment and starts the next one;
+ *   - SSR is a second stage applied inside each FSR segment; its S2 state
+ *     starts empty at every FSR or SSR cut; an empty S2 is stable;
+ *   - fewer than two spikes: output 0, window (-1, -1, 0);
+ *   - output time t uses interval m(t) = clamp(#{spikes at frames < t}, 1, K-1)
+ *     (1-based), i.e. the interval whose integration covers frame t; frames
+ *     before the first spike use the first interval, after the last spike
+ *     the last one;
+ *   - theta scales Eq. 6 (theta = 255 gives the paper's 8-bit scale).
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_FSR 1
+#define ORACLE_SSR 2
+
+/* ---- O-1: spike frames of pixel p (Eq. 2: P(n) = 1 marks a spike) ------ */
+static int32_t spikes_of_pixel(const uint8_t *stream, size_t fb, int32_t T, int64_t p,
+                               int32_t *tau)
+{
+    int32_t K = 0;
+    for (int32_t t = 0; t < T; t++) {
+        uint8_t byte = stream[(size_t)t * fb + (size_t)(p >> 3)];
+        if ((byte >> (p & 7)) & 1) tau[K++] = t;
+    }
+    return K;
+}
+
+/* ---- zero-order stability of a value set given by its extremes (Def. 2):
+ * one value, or two values that differ by exactly 1 -------------------- */
+static int zero_order_stable(int32_t lo, int32_t hi)
+{
+    return hi - lo <= 1;
+}
+
+/* ---- O-3: FSR (Sec. III-B "break the S1 when its elements violate the
+ * zero-order stability rule"; Sec. III-C stability module: a new element that
+ * keeps (e1, e2) stable is appended, one that violates pops the segment and
+ * resets (e1, e2) and the sum with itself).
+ * x[0..n-1] is S1; writes the first interval index of every segment to
+ * start[], returns the number of segments. */
+static int32_t fsr_segments(const int32_t *x, int32_t n, int32_t *start)
+{
+    if (n <= 0) return 0;
+    int32_t nseg = 0;
+    start[nseg++] = 0;
+    int32_t lo = x[0], hi = x[0];
+    for (int32_t m = 1; m < n; m++) {
+        int32_t nlo = x[m] < lo ? x[m] : lo;
+        int32_t nhi = x[m] > hi ? x[m] : hi;
+        if (zero_order_stable(nlo, nhi)) {
+            lo = nlo;
+            hi = nhi;
+        } else {
+            start[nseg++] = m;
+            lo = hi = x[m];
+        }
+    }
+    return nseg;
+}
+
+/* S2 bookkeeping for one interval value inside the current SSR piece: the
+ * index of its latest occurrence and the extremes of the gaps between its
+ * consecutive occurrences (that gap list is S2 for this value, Eq. 5). */
+typedef struct {
+    int32_t value;
+    int32_t last;
+    int32_t gap_lo, gap_hi;
+    int32_t has_gap;
+} s2_track;
+
+/* ---- O-4: SSR inside one FSR segment [s, e] (Sec. III-B: compute S2 of the
+ * segmented S1 for both firing-value choices and break where they violate the
+ * zero-order rule).  Appends piece starts to start[], returns the count. */
+static int32_t ssr_refine(const int32_t *x, int32_t s, int32_t e, int32_t *start)
+{
+    int32_t nseg = 0;
+    s2_track tr[2];
+    int32_t ntr = 0;
+    start[nseg++] = s;
+    for (int32_t m = s; m <= e; m++) {
+        int32_t v = x[m];
+        int32_t j = -1;
+        for (int32_t k = 0; k < ntr; k++)
+            if (tr[k].value == v) j = k;
+        if (j >= 0) {
+            int32_t d = m - tr[j].last; /* a new element of S2 for value v */
+            int32_t glo = tr[j].has_gap && tr[j].gap_lo < d ? tr[j].gap_lo : d;
+            int32_t ghi = tr[j].has_gap && tr[j].gap_hi > d ? tr[j].gap_hi : d;
+            if (!zero_order_stable(glo, ghi)) {
+                /* cut before interval m: it opens the next piece, whose S2
+                 * state starts empty */
+                start[nseg++] = m;
+                ntr = 0;
+                tr[ntr++] = (s2_track){v, m, 0, 0, 0};
+                continue;
+            }
+            tr[j].gap_lo = glo;
+            tr[j].gap_hi = ghi;
+            tr[j].has_gap = 1;
+            tr[j].last = m;
+        } else {
+            /* inside an FSR segment there are at most two distinct values */
+            if (ntr >= 2) abort();
+            tr[ntr++] = (s2_track){v, m, 0, 0, 0};
+        }
+    }
+    return nseg;
+}
+
+/* Segment S1 (n intervals) by the given order; writes segment starts,
+ * returns the number of segments. work[] holds n ints. */
+static int32_t segment_intervals(const int32_t *x, int32_t n, int32_t order, int32_t *start,
+                                 int32_t *work)
+{
+    int32_t nf = fsr_segments(x, n, order == ORACLE_FSR ? start : work);
+    if (order == ORACLE_FSR) return nf;
+    int32_t ns = 0;
+    for (int32_t i = 0; i < nf; i++) {
+        int32_t s = work[i];
+        int32_t e = (i + 1 < nf ? work[i + 1] : n) - 1;
+        ns += ssr_refine(x, s, e, start + ns);
+    }
+    return ns;
+}
+
+/* Exported: segment an interval list directly (tests). */
+int32_t spk_oracle_segment_intervals(const int32_t *x, int32_t n, int32_t order,
+                                     int32_t *start)
+{
+    if (n < 0 || (n > 0 && (!x || !start)) || (order != ORACLE_FSR && order != ORACLE_SSR))
+        return -1;
+    int32_t *work = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!work) return -2;
+    int32_t r = segment_intervals(x, n, order, start, work);
+    free(work);
+    return r;
+}
+
+/* ---- per-pixel driver --------------------------------------------------- */
+
+typedef struct {
+    int32_t *tau, *x, *start, *work, *seg_of;
+} scratch_t;
+
+typedef struct {
+    const uint8_t *stream;
+    int32_t H, W, T;
+    size_t fb;
+    double theta;
+    const int32_t *t_out;
+    int32_t n_out;
+    int32_t order;
+    double *out;
+    int32_t *win_first, *win_last, *win_n;
+    /* segments mode */
+    int32_t cap;
+    int32_t *seg_first, *seg_last, *seg_n, *count;
+    int64_t p0, p1;
+} task_t;
+
+/* number of spikes at frames < t (tau ascending) */
+static int32_t spikes_before(const int32_t *tau, int32_t K, int32_t t)
+{
+    int32_t lo = 0, hi = K;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) / 2;
+        if (tau[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+static void pixel_task(const task_t *tk, scratch_t *sc, int64_t p)
+{
+    int64_t hw = (int64_t)tk->H * tk->W;
+    int32_t K = spikes_of_pixel(tk->stream, tk->fb, tk->T, p, sc->tau); /* O-1 */
+    int32_t n = K >= 2 ? K - 1 : 0;
+    for (int32_t i = 0; i < n; i++) sc->x[i] = sc->tau[i + 1] - sc->tau[i]; /* O-2 */
+    int32_t nseg = segment_intervals(sc->x, n, tk->order, sc->start, sc->work); /* O-3/4 */
+
+    if (tk->count) {
+        tk->count[p] = nseg;
+        for (int32_t s = 0; s < nseg && s < tk->cap; s++) {
+            int32_t a = sc->start[s];
+            int32_t b = (s + 1 < nseg ? sc->start[s + 1] : n) - 1;
+            tk->seg_first[(int64_t)s * hw + p] = sc->tau[a];
+            tk->seg_last[(int64_t)s * hw + p] = sc->tau[b + 1];
+            tk->seg_n[(int64_t)s * hw + p] = b - a + 1;
+        }
+        return;
+    }
+
+    for (int32_t s = 0; s < nseg; s++) {
+        int32_t b = (s + 1 < nseg ? sc->start[s + 1] : n);
+        for (int32_t i = sc->start[s]; i < b; i++) sc->seg_of[i] = s;
+    }
+    for (int32_t k = 0; k < tk->n_out; k++) {
+        double I = 0.0;
+        int32_t first = -1, last = -1, cnt = 0;
+        if (K >= 2) {
+            /* O-6: interval in progress at t (1-based m, clamped to [1, K-1]) */
+            int32_t m = spikes_before(sc->tau, K, tk->t_out[k]);
+            if (m < 1) m = 1;
+            if (m > K - 1) m = K - 1;
+            int32_t s = sc->seg_of[m - 1];
+            int32_t a = sc->start[s];
+            int32_t b = (s + 1 < nseg ? sc->start[s + 1] : n) - 1;
+            first = sc->tau[a];
+            last = sc->tau[b + 1];
+            cnt = b - a + 1;
+            /* O-7, Eq. 6: 255 / ((1/N) sum T0(i)) with 255 -> theta; the
+             * intervals of the segment sum to last - first */
+            I = (tk->theta * (double)cnt) / (double)(last - first);
+        }
+        int64_t o = (int64_t)k * hw + p;
+        if (tk->out) tk->out[o] = I;
+        if (tk->win_first) tk->win_first[o] = first;
+        if (tk->win_last) tk->win_last[o] = last;
+        if (tk->win_n) tk->win_n[o] = cnt;
+    }
+}
+
+static void *task_run(void *arg)
+{
+    task_t *tk = (task_t *)arg;
+    size_t T1 = (size_t)tk->T + 1;
+    scratch_t sc;
+    sc.tau = (int32_t *)malloc(sizeof(int32_t) * T1);
+    sc.x = (int32_t *)malloc(sizeof(int32_t) * T1);
+    sc.start = (int32_t *)malloc(sizeof(int32_t) * T1);
+    sc.work = (int32_t *)malloc(sizeof(int32_t) * T1);
+    sc.seg_of = (int32_t *)malloc(sizeof(int32_t) * T1);
+    if (sc.tau && sc.x && sc.start && sc.work && sc.seg_of)
+        for (int64_t p = tk->p0; p < tk->p1; p++) pixel_task(tk, &sc, p);
+    else
+        abort();
+    free(sc.tau);
+    free(sc.x);
+    free(sc.start);
+    free(sc.work);
+    free(sc.seg_of);
+    return NULL;
+}
+
+static void run_all(task_t *base, int32_t nthreads)
+{
+    int64_t hw = (int64_t)base->H * base->W;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > hw) nthreads = (int32_t)hw;
+    task_t tasks[256];
+    pthread_t th[256];
+    for (int32_t i = 0; i < nthreads; i++) {
+        tasks[i] = *base;
+        tasks[i].p0 = hw * i / nthreads;
+        tasks[i].p1 = hw * (i + 1) / nthreads;
+    }
+    for (int32_t i = 1; i < nthreads; i++) pthread_create(&th[i], NULL, task_run, &tasks[i]);
+    task_run(&tasks[0]);
+    for (int32_t i = 1; i < nthreads; i++) pthread_join(th[i], NULL);
+}
+
+static size_t frame_bytes(int32_t H, int32_t W)
+{
+    return (((size_t)H * (size_t)W + 127) / 128) * 16;
+}
+
+/* Intensity (and window) per output time per pixel.  out/win_* are
+ * [n_out][H*W]; any may be NULL.  Returns 0, or -1 on a bad argument. */
+int32_t spk_oracle_reconstruct(const uint8_t *stream, int32_t H, int32_t W, int32_t T,
+                               double theta, const int32_t *t_out, int32_t n_out,
+                               int32_t order, double *out, int32_t *win_first,
+                               int32_t *win_last, int32_t *win_n, int32_t nthreads)
+{
+    if (!stream || H <= 0 || W <= 0 || T <= 0 || n_out < 0 || (n_out > 0 && !t_out) ||
+        (order != ORACLE_FSR && order != ORACLE_SSR))
+        return -1;
+    for (int32_t k = 0; k < n_out; k++)
+        if (t_out[k] < 0 || t_out[k] >= T) return -1;
+    task_t tk;
+    memset(&tk, 0, sizeof(tk));
+    tk.stream = stream;
+    tk.H = H;
+    tk.W = W;
+    tk.T = T;
+    tk.fb = frame_bytes(H, W);
+    tk.theta = theta;
+    tk.t_out = t_out;
+    tk.n_out = n_out;
+    tk.order = order;
+    tk.out = out;
+    tk.win_first = win_first;
+    tk.win_last = win_last;
+    tk.win_n = win_n;
+    run_all(&tk, nthreads);
+    return 0;
+}
+
+/* Every segment of every pixel: (first spike frame, last spike frame, number
+ * of intervals) in [cap][H*W] arrays, total count per pixel in count[H*W]
+ * (segments beyond cap are counted but not stored). */
+int32_t spk_oracle_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T,
+                            int32_t order, int32_t cap, int32_t *seg_first,
+                            int32_t *seg_last, int32_t *seg_n, int32_t *count,
+                            int32_t nthreads)
+{
+    if (!stream || H <= 0 || W <= 0 || T <= 0 || cap < 0 || !count ||
+        (cap > 0 && (!seg_first || !seg_last || !seg_n)) ||
+        (order != ORACLE_FSR && order != ORACLE_SSR))
+        return -1;
+    task_t tk;
+    memset(&tk, 0, sizeof(tk));
+    tk.stream = stream;
+    tk.H = H;
+    tk.W = W;
+    tk.T = T;
+    tk.fb = frame_bytes(H, W);
+    tk.order = order;
+    tk.cap = cap;
+    tk.seg_first = seg_first;
+    tk.seg_last = seg_last;
+    tk.seg_n = seg_n;
+    tk.count = count;
+    run_all(&tk, nthreads);
+    return 0;
+}
