@@ -1,0 +1,105 @@
+/*
+ * spk -- spike-camera reconstruction on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  Method: "High-speed and High-quality Vision
+ * Reconstruction of Spike Camera with Spike Stability Theorem"
+ * (arXiv 2412.11639).  Each pixel's binary spike stream S0 (the discrete
+ * integrate-and-fire of Eq. 2) is turned into its inter-spike interval
+ * stream S1 (Def. 2, Eq. 4); S1 is cut into segments that stay zero-order
+ * stable (values span at most 1), at first order (FSR) or additionally at
+ * second order (SSR, the S2 streams of Eq. 5), Sec. III-B; each segment's
+ * intensity is theta * N / sum of its N intervals (Eq. 6, with the paper's
+ * 8-bit scale 255 replaced by theta).
+ *
+ * Common conventions
+ *   stream   device pointer to T packed binary frames, frame-major: frame t
+ *            starts at byte t * spk_frame_bytes(H, W); pixel p = y * W + x
+ *            is bit (p & 7) of byte (p >> 3), least significant bit first;
+ *            padding bits must be zero.  Frames are 16-byte aligned.
+ *   t_out    host pointer to n_out output frame indices, 0 <= t < T, in any
+ *            order, duplicates allowed; output plane k is for t_out[k].
+ *   out      device pointer, float32 [n_out][H][W].
+ *   order    SPK_FSR or SPK_SSR.
+ *   hip_stream  a hipStream_t (NULL = the default stream); all device work is
+ *            enqueued on it and the call returns without synchronising.
+ *   Output time t uses the segment holding the interval in progress at t:
+ *            m(t) = clamp(#spikes at frames < t, 1, K - 1) (1-based), so
+ *            frames up to the first spike use the first interval and frames
+ *            after the last spike the last one.  A pixel with fewer than two
+ *            spikes outputs 0 and the window (-1, -1, 0).
+ *   Ownership: the caller owns every buffer it passes.  The library keeps a
+ *            small per-device workspace (sorted output times) that lives until
+ *            process exit; plans own their device tables until destroyed.
+ *   Errors:  arguments are checked on the host before anything is enqueued;
+ *            on error nothing is written and a negative code is returned.
+ *            A failed launch returns SPK_EHIP; faults inside kernels surface
+ *            at the caller's next synchronisation.  Calls on one device are
+ *            safe from one host thread at a time.
+ */
+#ifndef SPK_H
+#define SPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SPK_OK = 0,
+    SPK_EINVAL = -1,      /* bad argument                                  */
+    SPK_ENOMEM = -2,      /* device or host allocation failed              */
+    SPK_EHIP = -3,        /* a HIP runtime call or launch failed           */
+    SPK_EUNSUPPORTED = -4 /* no usable gfx950 device                       */
+};
+
+enum { SPK_FSR = 1, SPK_SSR = 2 };
+
+/* Bytes per packed frame: ceil(H*W / 128) * 16.  0 if H or W <= 0. */
+size_t spk_frame_bytes(int32_t H, int32_t W);
+
+/* Human-readable text for an error code (static storage). */
+const char *spk_strerror(int code);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int spk_version(void);
+
+/*
+ * Reconstruct intensity at the requested frames (Sec. III-B segmentation,
+ * Eq. 6 intensity).  theta: finite and > 0 (255 reproduces Eq. 6's 8-bit
+ * scale).  The intensity is computed as (double)theta * N / D and rounded
+ * once to float.  n_out == 0 is a no-op.
+ */
+int spk_reconstruct(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
+                    const int32_t *t_out, int32_t n_out, float *out, int32_t order,
+                    void *hip_stream);
+
+/*
+ * As spk_reconstruct, and also the window of the segment used for each
+ * output: first and last spike frame and the number of intervals N (so the
+ * duration is last - first).  Each of out, win_first, win_last, win_n is a
+ * device pointer [n_out][H][W] or NULL (not written).
+ */
+int spk_reconstruct_windows(const uint8_t *stream, int32_t H, int32_t W, int32_t T,
+                            float theta, const int32_t *t_out, int32_t n_out, float *out,
+                            int32_t *win_first, int32_t *win_last, int32_t *win_n,
+                            int32_t order, void *hip_stream);
+
+/*
+ * Every segment of every pixel (the full segmentation of Sec. III-B).
+ * seg_first/seg_last/seg_n: device int32 [cap][H*W]: segment s of pixel p
+ * at s * H*W + p (first spike frame, last spike frame, number of intervals).
+ * count: device int32 [H*W], the total number of segments of each pixel
+ * (segments past cap are counted but not stored).  cap >= 0; with cap == 0
+ * the seg_* pointers may be NULL.
+ */
+int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
+                 int32_t cap, int32_t *seg_first, int32_t *seg_last, int32_t *seg_n,
+                 int32_t *count, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPK_H */

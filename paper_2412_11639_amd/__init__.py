@@ -1,0 +1,104 @@
+"""Spike-camera reconstruction on MI355X (gfx950): Python binding of libspk.
+
+Thin argument marshalling over the C ABI in ``include/spk.h``: every step of
+the reconstruction runs in the library's HIP kernels.  PyTorch supplies
+device memory and the current HIP stream only.
+
+Method: arXiv 2412.11639 -- inter-spike intervals cut into zero-order stable
+segments at first (FSR) or second (SSR) order, intensity theta*N/duration
+per segment (Eq. 6).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SpkError
+
+FSR = 1
+SSR = 2
+
+__all__ = ["FSR", "SSR", "SpkError", "frame_bytes", "reconstruct", "reconstruct_windows",
+           "segments", "version"]
+
+
+def frame_bytes(H: int, W: int) -> int:
+    """Bytes per packed frame: ceil(H*W/128)*16."""
+    return int(_lib.load().spk_frame_bytes(H, W))
+
+
+def version() -> int:
+    return int(_lib.load().spk_version())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check_stream_tensor(stream_t, H, W, T):
+    if not isinstance(stream_t, torch.Tensor) or not stream_t.is_cuda:
+        raise TypeError("stream must be a device tensor")
+    if stream_t.dtype != torch.uint8 or not stream_t.is_contiguous():
+        raise TypeError("stream must be contiguous uint8")
+    if stream_t.numel() < T * frame_bytes(H, W):
+        raise ValueError("stream holds fewer than T frames")
+
+
+def _host_times(t_out):
+    t = np.ascontiguousarray(np.asarray(t_out, dtype=np.int32).reshape(-1))
+    return t, t.ctypes.data
+
+
+def reconstruct(stream_t: torch.Tensor, H: int, W: int, T: int, theta: float, t_out,
+                order: int = FSR, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Intensity at each output frame: float32 [n_out, H, W] on the device.
+
+    ``stream_t``: device uint8 tensor of T packed frames; ``t_out``: host
+    sequence of frame indices (any order, duplicates allowed)."""
+    _check_stream_tensor(stream_t, H, W, T)
+    t, tp = _host_times(t_out)
+    n_out = len(t)
+    if out is None:
+        out = torch.empty((n_out, H, W), dtype=torch.float32, device=stream_t.device)
+    assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n_out * H * W
+    rc = _lib.load().spk_reconstruct(stream_t.data_ptr(), H, W, T, float(theta), tp, n_out,
+                                     out.data_ptr(), order, _stream_handle(stream))
+    _lib.check("spk_reconstruct", rc)
+    return out
+
+
+def reconstruct_windows(stream_t, H, W, T, theta, t_out, order=FSR, stream=None):
+    """Intensity plus the window of the segment used for each output:
+    (out float32, first int32, last int32, n int32), each [n_out, H, W]."""
+    _check_stream_tensor(stream_t, H, W, T)
+    t, tp = _host_times(t_out)
+    n_out = len(t)
+    dev = stream_t.device
+    out = torch.empty((n_out, H, W), dtype=torch.float32, device=dev)
+    wf, wl, wn = (torch.empty((n_out, H, W), dtype=torch.int32, device=dev) for _ in range(3))
+    rc = _lib.load().spk_reconstruct_windows(stream_t.data_ptr(), H, W, T, float(theta), tp,
+                                             n_out, out.data_ptr(), wf.data_ptr(),
+                                             wl.data_ptr(), wn.data_ptr(), order,
+                                             _stream_handle(stream))
+    _lib.check("spk_reconstruct_windows", rc)
+    return out, wf, wl, wn
+
+
+def segments(stream_t, H, W, T, order=FSR, cap=64, stream=None):
+    """Every segment of every pixel: (first, last, n) int32 [cap, H*W] and
+    the per-pixel total count int32 [H*W]."""
+    _check_stream_tensor(stream_t, H, W, T)
+    dev = stream_t.device
+    hw = H * W
+    sf = torch.full((cap, hw), -1, dtype=torch.int32, device=dev)
+    sl = torch.full((cap, hw), -1, dtype=torch.int32, device=dev)
+    sn = torch.zeros((cap, hw), dtype=torch.int32, device=dev)
+    cnt = torch.zeros(hw, dtype=torch.int32, device=dev)
+    rc = _lib.load().spk_segments(stream_t.data_ptr(), H, W, T, order, cap, sf.data_ptr(),
+                                  sl.data_ptr(), sn.data_ptr(), cnt.data_ptr(),
+                                  _stream_handle(stream))
+    _lib.check("spk_segments", rc)
+    return sf, sl, sn, cnt

@@ -1,0 +1,246 @@
+// C-ABI entry points of the spike reconstruction library (declared in
+// include/spk.h): argument checks, the per-device table of sorted output
+// times, and kernel launches on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "spk.h"
+#include "spk_internal.h"
+
+namespace {
+
+// Device tables derived from one t_out list: cnt_le[t] = number of output
+// times <= t (t in [0, T)) and the sorted-index -> plane map (absent when
+// t_out is already strictly increasing).  Kept in a small per-device cache
+// so repeated calls with the same output times upload nothing; a slot is
+// only overwritten after the device has drained (hipDeviceSynchronize), so
+// a kernel still reading it on another stream is never disturbed.
+struct TableSlot {
+    int dev = -1;
+    int32_t T = 0;
+    std::vector<int32_t> key;  // the t_out list as given
+    int32_t *d_buf = nullptr;  // [T] cnt_le followed by [n_out] plane map
+    int32_t *h_buf = nullptr;  // pinned staging of the same
+    size_t cap = 0;            // ints allocated in both buffers
+    bool identity = true;
+    uint64_t stamp = 0;
+};
+
+constexpr int kSlots = 8;
+std::mutex g_mu;
+TableSlot g_slots[kSlots];
+uint64_t g_clock = 0;
+int g_dev_ok[64];  // 0 unknown, 1 gfx950, -1 unsupported
+
+int check_device(int *dev_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SPK_EHIP;
+    if (dev < 0 || dev >= 64) return SPK_EUNSUPPORTED;
+    if (g_dev_ok[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return SPK_EHIP;
+        g_dev_ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    }
+    if (g_dev_ok[dev] < 0) return SPK_EUNSUPPORTED;
+    *dev_out = dev;
+    return SPK_OK;
+}
+
+// Returns the slot holding the tables of (T, t_out) on device dev, uploading
+// them on the caller's stream if needed.
+int get_tables(int dev, int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
+               TableSlot **out)
+{
+    for (auto &s : g_slots) {
+        if (s.dev == dev && s.T == T && (int32_t)s.key.size() == n_out &&
+            std::equal(s.key.begin(), s.key.end(), t_out)) {
+            s.stamp = ++g_clock;
+            *out = &s;
+            return SPK_OK;
+        }
+    }
+    TableSlot *victim = &g_slots[0];
+    for (auto &s : g_slots)
+        if (s.stamp < victim->stamp) victim = &s;
+    if (victim->dev >= 0) {
+        // the slot may still be read by queued kernels on its device
+        int cur = dev;
+        if (hipSetDevice(victim->dev) != hipSuccess) return SPK_EHIP;
+        hipError_t e = hipDeviceSynchronize();
+        if (hipSetDevice(cur) != hipSuccess || e != hipSuccess) return SPK_EHIP;
+    }
+    const size_t need = (size_t)T + (size_t)n_out;
+    if (victim->cap < need || victim->dev != dev) {
+        if (victim->d_buf) {
+            int cur = dev;
+            hipSetDevice(victim->dev);
+            hipFree(victim->d_buf);
+            hipHostFree(victim->h_buf);
+            hipSetDevice(cur);
+        }
+        victim->d_buf = nullptr;
+        victim->h_buf = nullptr;
+        victim->cap = 0;
+        victim->dev = -1;
+        if (hipMalloc((void **)&victim->d_buf, need * sizeof(int32_t)) != hipSuccess)
+            return SPK_ENOMEM;
+        if (hipHostMalloc((void **)&victim->h_buf, need * sizeof(int32_t), 0) != hipSuccess) {
+            hipFree(victim->d_buf);
+            victim->d_buf = nullptr;
+            return SPK_ENOMEM;
+        }
+        victim->cap = need;
+    }
+    // sort output indices by time (stable: duplicates keep their order)
+    std::vector<int32_t> order(n_out);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return t_out[a] < t_out[b]; });
+    bool identity = true;
+    for (int32_t k = 0; k < n_out; k++) {
+        if (order[k] != k) identity = false;
+        if (k > 0 && t_out[order[k]] == t_out[order[k - 1]]) identity = false;
+    }
+    int32_t *cnt = victim->h_buf, *plane = victim->h_buf + T;
+    int32_t k = 0;
+    for (int32_t t = 0; t < T; t++) {
+        while (k < n_out && t_out[order[k]] <= t) k++;
+        cnt[t] = k;
+    }
+    for (int32_t j = 0; j < n_out; j++) plane[j] = order[j];
+    if (hipMemcpyAsync(victim->d_buf, victim->h_buf, need * sizeof(int32_t),
+                       hipMemcpyHostToDevice, stream) != hipSuccess)
+        return SPK_EHIP;
+    victim->dev = dev;
+    victim->T = T;
+    victim->key.assign(t_out, t_out + n_out);
+    victim->identity = identity;
+    victim->stamp = ++g_clock;
+    *out = victim;
+    return SPK_OK;
+}
+
+int check_common(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order)
+{
+    if (!stream || H <= 0 || W <= 0 || T <= 0) return SPK_EINVAL;
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
+    if (order != SPK_FSR && order != SPK_SSR) return SPK_EINVAL;
+    const size_t fb = spk_frame_bytes(H, W);
+    if ((size_t)T > SIZE_MAX / fb) return SPK_EINVAL;
+    return SPK_OK;
+}
+
+int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
+                     const int32_t *t_out, int32_t n_out, float *out, int32_t *wf,
+                     int32_t *wl, int32_t *wn, int32_t order, void *hip_stream)
+{
+    int rc = check_common(stream, H, W, T, order);
+    if (rc) return rc;
+    if (!std::isfinite(theta) || !(theta > 0.0f) || n_out < 0) return SPK_EINVAL;
+    if (n_out == 0) return SPK_OK;
+    if (!t_out) return SPK_EINVAL;
+    if ((int64_t)n_out * (int64_t)H * (int64_t)W > ((int64_t)1 << 60)) return SPK_EINVAL;
+    for (int32_t k = 0; k < n_out; k++)
+        if (t_out[k] < 0 || t_out[k] >= T) return SPK_EINVAL;
+    if (!out && !wf && !wl && !wn) return SPK_OK;
+    std::lock_guard<std::mutex> lock(g_mu);
+    int dev = 0;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    TableSlot *slot = nullptr;
+    rc = get_tables(dev, T, t_out, n_out, st, &slot);
+    if (rc) return rc;
+    spk::ReconParams p{};
+    p.stream = stream;
+    p.fb = (int64_t)spk_frame_bytes(H, W);
+    p.T = T;
+    p.HW = H * W;
+    p.theta = (double)theta;
+    p.cnt_le = slot->d_buf;
+    p.plane = slot->identity ? nullptr : slot->d_buf + T;
+    p.n_out = n_out;
+    p.out = out;
+    p.win_first = wf;
+    p.win_last = wl;
+    p.win_n = wn;
+    return spk::launch_recon(p, order, spk::MODE_RECON, st) == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t spk_frame_bytes(int32_t H, int32_t W)
+{
+    if (H <= 0 || W <= 0) return 0;
+    return (((size_t)H * (size_t)W + 127) / 128) * 16;
+}
+
+const char *spk_strerror(int code)
+{
+    switch (code) {
+    case SPK_OK: return "ok";
+    case SPK_EINVAL: return "invalid argument";
+    case SPK_ENOMEM: return "out of memory";
+    case SPK_EHIP: return "HIP runtime error";
+    case SPK_EUNSUPPORTED: return "unsupported device (needs gfx950)";
+    default: return "unknown error";
+    }
+}
+
+int spk_version(void) { return 100; }
+
+int spk_reconstruct(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
+                    const int32_t *t_out, int32_t n_out, float *out, int32_t order,
+                    void *hip_stream)
+{
+    if (n_out > 0 && !out) return SPK_EINVAL;
+    return reconstruct_impl(stream, H, W, T, theta, t_out, n_out, out, nullptr, nullptr,
+                            nullptr, order, hip_stream);
+}
+
+int spk_reconstruct_windows(const uint8_t *stream, int32_t H, int32_t W, int32_t T,
+                            float theta, const int32_t *t_out, int32_t n_out, float *out,
+                            int32_t *win_first, int32_t *win_last, int32_t *win_n,
+                            int32_t order, void *hip_stream)
+{
+    return reconstruct_impl(stream, H, W, T, theta, t_out, n_out, out, win_first, win_last,
+                            win_n, order, hip_stream);
+}
+
+int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
+                 int32_t cap, int32_t *seg_first, int32_t *seg_last, int32_t *seg_n,
+                 int32_t *count, void *hip_stream)
+{
+    int rc = check_common(stream, H, W, T, order);
+    if (rc) return rc;
+    if (cap < 0 || !count) return SPK_EINVAL;
+    if (cap > 0 && (!seg_first || !seg_last || !seg_n)) return SPK_EINVAL;
+    if ((int64_t)cap * (int64_t)H * (int64_t)W > ((int64_t)1 << 60)) return SPK_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mu);
+    int dev = 0;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    spk::ReconParams p{};
+    p.stream = stream;
+    p.fb = (int64_t)spk_frame_bytes(H, W);
+    p.T = T;
+    p.HW = H * W;
+    p.cap = cap;
+    p.seg_first = seg_first;
+    p.seg_last = seg_last;
+    p.seg_n = seg_n;
+    p.count = count;
+    return spk::launch_recon(p, order, spk::MODE_SEGMENTS, (hipStream_t)hip_stream) ==
+                   hipSuccess
+               ? SPK_OK
+               : SPK_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,37 @@
+// Internal interface between the C-ABI glue and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spk {
+
+// What one launch of the reconstruction kernel works on.  Device pointers
+// unless stated.
+struct ReconParams {
+    const uint8_t *stream;   // [T][fb] packed frames
+    int64_t fb;              // bytes per frame (multiple of 16)
+    int32_t T;
+    int32_t HW;
+    double theta;
+    const int32_t *cnt_le;   // [T]: number of sorted output times <= t
+    const int32_t *plane;    // [n_out]: sorted output index -> output plane (NULL = identity)
+    int32_t n_out;
+    float *out;              // [n_out][HW] or NULL
+    int32_t *win_first;      // [n_out][HW] or NULL
+    int32_t *win_last;
+    int32_t *win_n;
+    // segment listing mode
+    int32_t cap;
+    int32_t *seg_first;      // [cap][HW]
+    int32_t *seg_last;
+    int32_t *seg_n;
+    int32_t *count;          // [HW]
+};
+
+enum Mode { MODE_RECON = 0, MODE_SEGMENTS = 1 };
+
+// Enqueue the plain FSR/SSR reconstruction (or segment listing) on stream.
+hipError_t launch_recon(const ReconParams &p, int order, Mode mode, hipStream_t stream);
+
+}  // namespace spk

@@ -1,0 +1,92 @@
+"""The C-ABI library on the CPU: it loads, exports every declared entry point,
+and rejects bad arguments on the host before touching any device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(spk_\w+)\s*\(", text, re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2412_11639_amd import _lib
+    return _lib.load()
+
+
+def test_headers_declare_entry_points():
+    names = declared_functions()
+    for n in ["spk_frame_bytes", "spk_strerror", "spk_version", "spk_reconstruct",
+              "spk_reconstruct_windows", "spk_segments"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(os.path.join(ROOT, "paper_2412_11639_amd", "libspk.so"))
+    missing = [n for n in declared_functions() if not hasattr(raw, n)]
+    assert missing == []
+
+
+def test_frame_bytes(lib):
+    assert lib.spk_frame_bytes(250, 400) == 12512
+    assert lib.spk_frame_bytes(1000, 1000) == 125008
+    assert lib.spk_frame_bytes(1, 1) == 16
+    assert lib.spk_frame_bytes(0, 5) == 0
+    for H, W in [(1, 128), (1, 129), (3, 43), (720, 1280)]:
+        fb = lib.spk_frame_bytes(H, W)
+        assert fb % 16 == 0 and fb * 8 >= H * W and (fb - 16) * 8 < H * W
+
+
+def test_strerror(lib):
+    assert lib.spk_strerror(0) == b"ok"
+    assert b"invalid" in lib.spk_strerror(-1)
+
+
+FAKE = 4096  # a non-null pointer value; validation must fail before any use
+
+
+@pytest.mark.parametrize("args", [
+    dict(stream=0),
+    dict(H=0), dict(W=-1), dict(T=0),
+    dict(theta=0.0), dict(theta=-1.0), dict(theta=float("nan")), dict(theta=float("inf")),
+    dict(n_out=-1),
+    dict(t_out=[5, 10]),          # 10 >= T
+    dict(t_out=[-1]),
+    dict(order=0), dict(order=3),
+    dict(out=0),
+    dict(H=65536, W=65536),       # H*W overflows int32
+])
+def test_reconstruct_rejects_bad_arguments(lib, args):
+    a = dict(stream=FAKE, H=4, W=4, T=10, theta=1.0, t_out=[0, 5], n_out=None, out=FAKE,
+             order=1)
+    a.update(args)
+    t = (ctypes.c_int32 * max(1, len(a["t_out"])))(*a["t_out"])
+    n_out = len(a["t_out"]) if a["n_out"] is None else a["n_out"]
+    rc = lib.spk_reconstruct(a["stream"], a["H"], a["W"], a["T"], a["theta"],
+                             ctypes.addressof(t), n_out, a["out"], a["order"], None)
+    assert rc == -1
+
+
+def test_segments_rejects_bad_arguments(lib):
+    assert lib.spk_segments(FAKE, 4, 4, 10, 1, -1, FAKE, FAKE, FAKE, FAKE, None) == -1
+    assert lib.spk_segments(FAKE, 4, 4, 10, 1, 4, 0, FAKE, FAKE, FAKE, None) == -1
+    assert lib.spk_segments(FAKE, 4, 4, 10, 1, 4, FAKE, FAKE, FAKE, 0, None) == -1
+    assert lib.spk_segments(FAKE, 4, 4, 10, 5, 4, FAKE, FAKE, FAKE, FAKE, None) == -1
+
+
+def test_zero_outputs_is_noop(lib):
+    # n_out == 0 returns before any device work
+    assert lib.spk_reconstruct(FAKE, 4, 4, 10, 1.0, None, 0, None, 1, None) == 0

@@ -1,0 +1,160 @@
+"""Parity of the HIP reconstruction (through the C ABI) with the FP64 oracle.
+
+Spike times, windows (first/last spike frame, interval count) and segment
+lists must match bit for bit.  Intensities must agree within 1e-6 relative;
+both sides evaluate theta*N/D in double precision and the library rounds it
+once to float32, so they are in fact expected to be equal to the float32
+rounding of the oracle's value.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import spkgen
+from test_oracle_pins import _read_golden, worked_example_stream
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def spk():
+    import paper_2412_11639_amd as m
+    assert torch.cuda.is_available(), "no GPU"
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_recon(spk, s, H, W, T, t_out, order, theta=1.0):
+    print("recon H=%d W=%d T=%d n_out=%d order=%d" % (H, W, T, len(t_out), order), flush=True)
+    ds = dev(s)
+    out, wf, wl, wn = spk.reconstruct_windows(ds, H, W, T, theta, t_out, order=order)
+    out2 = spk.reconstruct(ds, H, W, T, theta, t_out, order=order)
+    torch.cuda.synchronize()
+    ref, rf, rl, rn = oracle.reconstruct(s, H, W, T, theta, t_out, order=order, windows=True)
+    np.testing.assert_array_equal(wf.cpu().numpy(), rf)
+    np.testing.assert_array_equal(wl.cpu().numpy(), rl)
+    np.testing.assert_array_equal(wn.cpu().numpy(), rn)
+    o = out.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(o, ref, rtol=REL_TOL, atol=0)
+    np.testing.assert_array_equal(out.cpu().numpy(), ref.astype(np.float32))
+    np.testing.assert_array_equal(out2.cpu().numpy(), out.cpu().numpy())
+    return out
+
+
+def check_segments(spk, s, H, W, T, order, cap):
+    print("segments H=%d W=%d T=%d order=%d" % (H, W, T, order), flush=True)
+    sf, sl, sn, cnt = spk.segments(dev(s), H, W, T, order=order, cap=cap)
+    torch.cuda.synchronize()
+    rf, rl, rn, rc = oracle.segments(s, H, W, T, order=order, cap=cap)
+    np.testing.assert_array_equal(cnt.cpu().numpy(), rc)
+    np.testing.assert_array_equal(sf.cpu().numpy(), rf)
+    np.testing.assert_array_equal(sl.cpu().numpy(), rl)
+    np.testing.assert_array_equal(sn.cpu().numpy(), rn)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_worked_example(spk, order):
+    s, H, W, T = worked_example_stream()
+    rows = [r for r in _read_golden() if r[0] == ("FSR" if order == 1 else "SSR")]
+    t_out = [r[2] for r in rows]
+    out = check_recon(spk, s, H, W, T, t_out, order).cpu().numpy()
+    for k, (_, p, t, a, b, n, frac) in enumerate(rows):
+        assert out[k, 0, p] == np.float32(float(frac))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_every_stream_of_12_frames(spk, order):
+    T = 12
+    n = 1 << T
+    p = np.arange(n)
+    bits = ((p[None, :] >> np.arange(T)[:, None]) & 1).astype(np.uint8)
+    s = spkgen.pack(bits)
+    check_segments(spk, s, 32, 128, T, order, cap=T)
+    check_recon(spk, s, 32, 128, T, list(range(T)), order)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_blocks_250x400(spk, order):
+    """Static 16x16 blocks, 250x400, 1024 frames, 8 outputs (+ first/last frame)."""
+    H, W, T = 250, 400, 1024
+    s = spkgen.blocks(H, W, T, seed=1)
+    t_out = [64 + 128 * k for k in range(8)] + [0, T - 1]
+    check_recon(spk, s, H, W, T, t_out, order)
+    check_segments(spk, s, H, W, T, order, cap=4)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_gratings_ragged(spk, order):
+    """Moving gratings + disk with Poisson noise; H*W and T not multiples of
+    64; output times unsorted with duplicates."""
+    H, W, T = 37, 91, 3001
+    s = spkgen.gratings(H, W, T, seed=7)
+    rng = np.random.default_rng(0)
+    t_out = rng.integers(0, T, 300).tolist() + [0, 0, T - 1, 5, 5]
+    check_recon(spk, s, H, W, T, t_out, order)
+    check_segments(spk, s, H, W, T, order, cap=400)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_moving_blocks(spk, order):
+    H, W, T = 64, 80, 2048
+    s = spkgen.blocks(H, W, T, seed=5, vx=0.7, vy=-0.4)
+    check_recon(spk, s, H, W, T, list(range(0, T, 3)), order)
+    check_segments(spk, s, H, W, T, order, cap=2048)
+
+
+def test_edge_cases(spk):
+    # one pixel, one frame
+    s = spkgen.pack(np.ones((1, 1), dtype=np.uint8))
+    check_recon(spk, s, 1, 1, 1, [0], 1)
+    # pixels with 0, 1, 2 spikes; a pixel firing every frame; T = 65
+    T = 65
+    bits = np.zeros((T, 6), dtype=np.uint8)
+    bits[40, 1] = 1
+    bits[[3, 64], 2] = 1
+    bits[:, 3] = 1
+    bits[[0, 63, 64], 4] = 1
+    bits[[63, 64], 5] = 1
+    s = spkgen.pack(bits)
+    for order in (1, 2):
+        check_recon(spk, s, 1, 6, T, list(range(T)), order)
+        check_segments(spk, s, 1, 6, T, order, cap=T)
+
+
+def test_reconstruct_rejects_bad_t_out(spk):
+    s = dev(np.zeros((4, 16), dtype=np.uint8))
+    with pytest.raises(spk.SpkError):
+        spk.reconstruct(s, 4, 4, 4, 1.0, [4])
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_gratings_full_size_sampled(spk, order):
+    """250x400, 20000 frames, every 10th frame out (the benchmark launch):
+    the GPU computes all 2000 planes; 40 evenly spaced planes are checked
+    against the oracle, element by element."""
+    H, W, T = 250, 400, 20000
+    s = _full_gratings()
+    t_out = list(range(0, T, 10))
+    print("full-size gratings order=%d" % order, flush=True)
+    ds = dev(s)
+    out = spk.reconstruct(ds, H, W, T, 1.0, t_out, order=order)
+    torch.cuda.synchronize()
+    pick = list(range(0, len(t_out), 50))
+    ref = oracle.reconstruct(s, H, W, T, 1.0, [t_out[k] for k in pick], order=order)
+    got = out[pick].cpu().numpy()
+    np.testing.assert_array_equal(got, ref.astype(np.float32))
+
+
+_CACHE = {}
+
+
+def _full_gratings():
+    if "g" not in _CACHE:
+        _CACHE["g"] = spkgen.gratings(250, 400, 20000, seed=2)
+    return _CACHE["g"]
