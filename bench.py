@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Throughput of plain FSR/SSR spike-stream reconstruction on one MI355X.
+
+Workload: 250x400 pixels, 20000 frames (1 s at 20 kHz) of moving gratings
+plus a rotating sectored disk with Poisson photon noise (seed 2), intensity
+reconstructed at every 10th frame (2000 output planes).  One step = one
+spk_reconstruct call over the whole stream (ingest, transpose, spike
+intervals, FSR + SSR segmentation, Eq. 6 intensity, output writes), with the
+packed stream already resident in HBM.
+
+Prints one JSON line.  Also:
+  --parse-rocprof DIR   summarise rocprofv3 output (kernel stats or PMC
+                        counters) found under DIR as text, for profiles/.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "recon Mpixel-frames/s + %HBM peak; surrogate vs plain at ≥40 dB PSNR"
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAME = "recon_kernel"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_recon_gratings_250x400_T20000.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_11639_amd", "csrc", f)
+                  for f in ("recon.hip", "spk_internal.h")]
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(H, W, T, n_out) -> int:
+    """One bit in per pixel-frame, one float32 out per pixel per output."""
+    return T * H * W // 8 + n_out * H * W * 4
+
+
+def load_traffic(order_name):
+    """HBM traffic per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    v = t.get("per_order", {}).get(order_name, {}).get("hbm_bytes_per_launch")
+    return None if v is None else round(v)
+
+
+def run_cpu_baseline(s, H, W, T, t_out, order, rows):
+    """The oracle, as it stands, on the first ``rows`` rows of the workload
+    (all frames, all outputs), on all host cores (at most 16)."""
+    import numpy as np
+
+    import oracle
+    import spkgen
+    sub = spkgen.pack(spkgen.unpack(s, H, W)[:, :rows, :])
+    n = min(16, os.cpu_count() or 1)
+    oracle.reconstruct(sub[:256], rows, W, 256, 1.0, [0], order=order, nthreads=n)  # warm
+    t0 = time.perf_counter()
+    ref = oracle.reconstruct(sub, rows, W, T, 1.0, t_out, order=order, nthreads=n)
+    dt = time.perf_counter() - t0
+    return ref, dt, n, np
+
+
+COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB each way
+
+
+def traffic_from_counters(d: str):
+    """HBM bytes per launch of each reconstruction kernel from the FETCH_SIZE
+    and WRITE_SIZE passes under d, each scaled by what the same counter reads
+    for the 1 GiB calibration copy in the same run."""
+    import sqlite3
+    vals = {}
+    for f in glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True):
+        con = sqlite3.connect(f)
+        try:
+            rows = con.execute("select kernel_name, counter_name, avg(value) "
+                               "from counters_collection group by kernel_name, counter_name")
+            for name, cname, mean in rows:
+                vals[(name, cname)] = mean
+        except sqlite3.Error:
+            pass
+        con.close()
+    out = {}
+    for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+        copy = [v for (n, c), v in vals.items() if c == cname and "copyBuffer" in n]
+        if not copy:
+            continue
+        factor = COPY_BYTES / (copy[0] * 1024.0)
+        for (n, c), v in vals.items():
+            if c == cname and KERNEL_NAME in n:
+                key = "SSR" if "recon_kernel<2" in n else "FSR"
+                out.setdefault(key, {})[cname] = {"kib": v, "factor": factor,
+                                                  "bytes": v * 1024.0 * factor}
+    for key, d2 in out.items():
+        if "FETCH_SIZE" in d2 and "WRITE_SIZE" in d2:
+            d2["hbm_bytes_per_launch"] = d2["FETCH_SIZE"]["bytes"] + d2["WRITE_SIZE"]["bytes"]
+    return out
+
+
+def parse_rocprof(d: str) -> str:
+    """Summarise rocprofv3 output (rocpd SQLite databases or CSV) under d."""
+    import sqlite3
+    lines = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True)):
+        con = sqlite3.connect(f)
+        lines.append("# rocpd: %s" % os.path.relpath(f, d))
+        try:
+            for name, calls, total, avg in con.execute(
+                    "select name, total_calls, total_duration, average from top_kernels"):
+                lines.append("kernel %-70s calls=%-5d avg_ns=%-12.1f total_ns=%.1f"
+                             % (name[:70], calls, avg, total))
+        except sqlite3.Error:
+            pass
+        try:
+            for name, cname, n, mean in con.execute(
+                    "select kernel_name, counter_name, count(*), avg(value) "
+                    "from counters_collection group by kernel_name, counter_name"):
+                lines.append("counter %-70s %-12s dispatches=%-4d mean=%.1f"
+                             % (name[:70], cname, n, mean))
+        except sqlite3.Error:
+            pass
+        con.close()
+    stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    for f in stats:
+        lines.append("# kernel stats: %s" % os.path.relpath(f, d))
+        with open(f) as fh:
+            rows = list(csv.DictReader(fh))
+        for r in rows:
+            lines.append("%-60s calls=%-6s avg_ns=%-12s total_ns=%-14s pct=%s" % (
+                r.get("Name", "")[:60], r.get("Calls"), r.get("AverageNs"),
+                r.get("TotalDurationNs"), r.get("Percentage")))
+    pmc = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    for f in pmc:
+        lines.append("# counters: %s" % os.path.relpath(f, d))
+        agg = {}
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                key = (r.get("Kernel_Name", "")[:60], r.get("Counter_Name"))
+                agg.setdefault(key, []).append(float(r.get("Counter_Value", 0)))
+        for (k, c), v in sorted(agg.items()):
+            lines.append("%-60s %-12s dispatches=%-5d mean=%.1f" % (k, c, len(v), sum(v) / len(v)))
+    return "\n".join(lines)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--order", choices=["fsr", "ssr"], default="ssr")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--parse-rocprof", default=None)
+    ap.add_argument("--traffic-out", default=None,
+                    help="with --parse-rocprof: write the per-launch HBM traffic JSON")
+    args = ap.parse_args()
+
+    if args.parse_rocprof:
+        print(parse_rocprof(args.parse_rocprof))
+        if args.traffic_out:
+            t = {"kernel_sha": kernel_sha(), "per_order": traffic_from_counters(args.parse_rocprof),
+                 "note": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the same "
+                         "counter's reading for a 1 GiB device copy"}
+            with open(args.traffic_out, "w") as f:
+                json.dump(t, f, indent=1)
+        return 0
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2412_11639_amd as spk
+    import spkgen
+
+    wl = spkgen.GRATINGS_250x400
+    H, W, T = wl.H, wl.W, wl.T
+    t_out = wl.times()
+    n_out = len(t_out)
+    order = spk.SSR if args.order == "ssr" else spk.FSR
+    print("generating %s" % wl.name, file=sys.stderr, flush=True)
+    s = wl.generate()
+    ds = torch.from_numpy(s).cuda()
+    out = torch.empty((n_out, H, W), dtype=torch.float32, device="cuda")
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step(o=order):
+        spk.reconstruct(ds, H, W, T, 1.0, t_out, order=o, out=out)
+
+    def timed(o):
+        for _ in range(args.warmup):
+            step(o)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            step(o)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        return e0.elapsed_time(e1) / args.steps, wall
+
+    print("timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    other = spk.FSR if order == spk.SSR else spk.SSR
+    ms_other, _ = timed(other)
+    ms, wall = timed(order)
+    gpu_out = out.cpu().numpy()
+
+    px_frames = H * W * T
+    value = px_frames / (ms * 1e-3) / 1e6
+    alg = algorithmic_bytes(H, W, T, n_out)
+    achieved = alg / (ms * 1e-3) / 1e9
+    traffic = load_traffic(args.order.upper())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rows = min(args.cpu_rows, H)
+        print("cpu baseline: oracle on %d rows" % rows, file=sys.stderr, flush=True)
+        ref, dt, cores, _ = run_cpu_baseline(s, H, W, T, t_out, order, rows)
+        # the benchmark's own output checked against the oracle on the sample
+        ok = np.array_equal(gpu_out[:, :rows, :], ref.astype(np.float32))
+        if not ok:
+            print("PARITY FAILURE against the oracle on the sample", file=sys.stderr)
+            return 1
+        cpu = {"value": rows * W * T / dt / 1e6, "unit": "Mpixel-frames/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "first %d of %d rows, all %d frames and %d outputs (%s); "
+                         "bit-exact vs the GPU output on the same rows" % (
+                             rows, H, T, n_out, args.order.upper())}
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpixel-frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "H": H, "W": W, "T": T, "n_out": n_out,
+                   "order": args.order.upper(), "theta": 1.0,
+                   "scene": "1-3 moving sinusoidal gratings + rotating sectored disk, "
+                            "Poisson photons (1000 per threshold), seed 2"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "other_order": {"order": "FSR" if order == spk.SSR else "SSR",
+                        "ms_per_step": round(ms_other, 4),
+                        "value": round(px_frames / (ms_other * 1e-3) / 1e6, 1)},
+        "wall_s_timed": round(wall, 3),
+    }
+    print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
