@@ -66,6 +66,21 @@ const char *spk_strerror(int code);
 int spk_version(void);
 
 /*
+ * Process-wide tuning options (not part of any result: every setting gives
+ * bit-identical output).
+ *   SPK_OPT_TIME_CHUNKS  number of time chunks a long stream is split into
+ *                        so that more waves run at once; 0 = automatic
+ *                        (the default; the SPK_CHUNKS environment variable
+ *                        overrides it at first use).  Values above the
+ *                        number of 64-frame tiles are clamped.
+ * spk_set_option returns SPK_OK or SPK_EINVAL (unknown option, value < 0);
+ * spk_get_option returns the value or SPK_EINVAL.
+ */
+enum { SPK_OPT_TIME_CHUNKS = 1 };
+int spk_set_option(int option, int value);
+int spk_get_option(int option);
+
+/*
  * Reconstruct intensity at the requested frames (Sec. III-B segmentation,
  * Eq. 6 intensity).  theta: finite and > 0 (255 reproduces Eq. 6's 8-bit
  * scale).  The intensity is computed as (double)theta * N / D and rounded

@@ -20,7 +20,7 @@ FSR = 1
 SSR = 2
 
 __all__ = ["FSR", "SSR", "SpkError", "frame_bytes", "reconstruct", "reconstruct_windows",
-           "segments", "version"]
+           "segments", "version", "set_time_chunks", "get_time_chunks"]
 
 
 def frame_bytes(H: int, W: int) -> int:
@@ -28,8 +28,21 @@ def frame_bytes(H: int, W: int) -> int:
     return int(_lib.load().spk_frame_bytes(H, W))
 
 
+OPT_TIME_CHUNKS = 1
+
+
 def version() -> int:
     return int(_lib.load().spk_version())
+
+
+def set_time_chunks(n: int) -> None:
+    """Number of time chunks for long streams (0 = automatic).  Results are
+    identical for every setting; only the degree of parallelism changes."""
+    _lib.check("spk_set_option", _lib.load().spk_set_option(OPT_TIME_CHUNKS, int(n)))
+
+
+def get_time_chunks() -> int:
+    return int(_lib.load().spk_get_option(OPT_TIME_CHUNKS))
 
 
 def _stream_handle(stream):

@@ -32,6 +32,10 @@ def _declare(lib):
     lib.spk_strerror.argtypes = [ctypes.c_int]
     lib.spk_version.restype = ctypes.c_int
     lib.spk_version.argtypes = []
+    lib.spk_set_option.restype = ctypes.c_int
+    lib.spk_set_option.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.spk_get_option.restype = ctypes.c_int
+    lib.spk_get_option.argtypes = [ctypes.c_int]
     lib.spk_reconstruct.restype = ctypes.c_int
     lib.spk_reconstruct.argtypes = [P_u8, c_i32, c_i32, c_i32, ctypes.c_float, P_i32, c_i32,
                                     P_f32, c_i32, ctypes.c_void_p]

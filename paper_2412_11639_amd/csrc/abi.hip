@@ -3,6 +3,7 @@
 // times, and kernel launches on the caller's stream.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -125,6 +126,66 @@ int get_tables(int dev, int32_t T, const int32_t *t_out, int32_t n_out, hipStrea
     return SPK_OK;
 }
 
+// Device scratch for the per-chunk records, one buffer per (device, stream)
+// so that calls on different streams never share it.  Grows on demand;
+// growing waits for the device so a buffer still in use is never freed.
+struct Scratch {
+    int dev = -1;
+    hipStream_t stream = nullptr;
+    int32_t *buf = nullptr;
+    size_t ints = 0;
+};
+std::vector<Scratch> g_scratch;
+
+int get_scratch(int dev, hipStream_t stream, size_t ints, int32_t **out)
+{
+    *out = nullptr;
+    if (ints == 0) return SPK_OK;
+    Scratch *s = nullptr;
+    for (auto &e : g_scratch)
+        if (e.dev == dev && e.stream == stream) s = &e;
+    if (!s) {
+        g_scratch.push_back(Scratch{dev, stream, nullptr, 0});
+        s = &g_scratch.back();
+    }
+    if (s->ints < ints) {
+        if (s->buf) {
+            if (hipDeviceSynchronize() != hipSuccess) return SPK_EHIP;
+            hipFree(s->buf);
+            s->buf = nullptr;
+            s->ints = 0;
+        }
+        if (hipMalloc((void **)&s->buf, ints * sizeof(int32_t)) != hipSuccess) return SPK_ENOMEM;
+        s->ints = ints;
+    }
+    *out = s->buf;
+    return SPK_OK;
+}
+
+// Chunk count for long streams: 0 = automatic (SPK_CHUNKS in the
+// environment, else sized to fill the chip); set by spk_set_option.
+int g_chunks = -1;
+
+int requested_chunks()
+{
+    if (g_chunks < 0) {
+        const char *e = std::getenv("SPK_CHUNKS");
+        g_chunks = e ? std::max(0, std::atoi(e)) : 0;
+    }
+    return g_chunks;
+}
+
+// Warm-up tiles before each speculative chunk (tuning; SPK_WARM, default
+// automatic).
+int requested_warm()
+{
+    static const int v = [] {
+        const char *e = std::getenv("SPK_WARM");
+        return e ? std::max(0, std::atoi(e)) : -1;
+    }();
+    return v;
+}
+
 int check_common(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order)
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0) return SPK_EINVAL;
@@ -169,7 +230,10 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
     p.win_first = wf;
     p.win_last = wl;
     p.win_n = wn;
-    return spk::launch_recon(p, order, spk::MODE_RECON, st) == hipSuccess ? SPK_OK : SPK_EHIP;
+    spk::ChunkPlan cp = spk::plan_chunks(p.HW, T, requested_chunks(), requested_warm());
+    rc = get_scratch(dev, st, spk::chunk_record_ints(cp, p.HW), &cp.rec);
+    if (rc) return rc;
+    return spk::launch_recon(p, order, spk::MODE_RECON, cp, st) == hipSuccess ? SPK_OK : SPK_EHIP;
 }
 
 }  // namespace
@@ -195,6 +259,28 @@ const char *spk_strerror(int code)
 }
 
 int spk_version(void) { return 100; }
+
+int spk_set_option(int option, int value)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    switch (option) {
+    case SPK_OPT_TIME_CHUNKS:
+        if (value < 0) return SPK_EINVAL;
+        g_chunks = value;
+        return SPK_OK;
+    default:
+        return SPK_EINVAL;
+    }
+}
+
+int spk_get_option(int option)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    switch (option) {
+    case SPK_OPT_TIME_CHUNKS: return requested_chunks();
+    default: return SPK_EINVAL;
+    }
+}
 
 int spk_reconstruct(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
                     const int32_t *t_out, int32_t n_out, float *out, int32_t order,
@@ -237,8 +323,8 @@ int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t
     p.seg_last = seg_last;
     p.seg_n = seg_n;
     p.count = count;
-    return spk::launch_recon(p, order, spk::MODE_SEGMENTS, (hipStream_t)hip_stream) ==
-                   hipSuccess
+    return spk::launch_recon(p, order, spk::MODE_SEGMENTS, spk::ChunkPlan{},
+                             (hipStream_t)hip_stream) == hipSuccess
                ? SPK_OK
                : SPK_EHIP;
 }

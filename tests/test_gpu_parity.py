@@ -158,3 +158,62 @@ def _full_gratings():
     if "g" not in _CACHE:
         _CACHE["g"] = spkgen.gratings(250, 400, 20000, seed=2)
     return _CACHE["g"]
+
+
+@pytest.fixture
+def chunks(spk):
+    yield spk.set_time_chunks
+    spk.set_time_chunks(0)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("n_chunks", [2, 3, 7, 100])
+def test_time_chunks_gratings(spk, chunks, order, n_chunks):
+    """Time-chunked runs (speculative chunks + exact fixup) give the same
+    result as the oracle for any chunk count, down to one tile per chunk."""
+    chunks(n_chunks)
+    H, W, T = 37, 91, 3001
+    s = spkgen.gratings(H, W, T, seed=8)
+    t_out = list(range(0, T, 7)) + [T - 1]
+    check_recon(spk, s, H, W, T, t_out, order)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("n_chunks", [4, 16])
+def test_time_chunks_static_and_moving_blocks(spk, chunks, order, n_chunks):
+    """Static blocks keep one segment across every chunk boundary (the fixup
+    converges without a common cut); moving blocks cut often."""
+    chunks(n_chunks)
+    H, W, T = 48, 80, 2048
+    check_recon(spk, spkgen.blocks(H, W, T, seed=21), H, W, T, list(range(0, T, 5)), order)
+    check_recon(spk, spkgen.blocks(H, W, T, seed=22, vx=0.3, vy=0.2), H, W, T,
+                list(range(3, T, 11)), order)
+
+
+@pytest.mark.parametrize("n_chunks", [5, 64])
+def test_time_chunks_sparse_and_edge_pixels(spk, chunks, n_chunks):
+    """Pixels whose first spike, or only spikes, fall in late chunks; chunks
+    without any spike; unsorted output times with duplicates."""
+    chunks(n_chunks)
+    T = 64 * 64
+    rng = np.random.default_rng(9)
+    bits = np.zeros((T, 200), dtype=np.uint8)
+    for p in range(200):
+        kind = p % 5
+        if kind == 0:
+            continue                                   # no spike
+        if kind == 1:
+            bits[rng.integers(0, T), p] = 1            # one spike
+        elif kind == 2:
+            a, b = sorted(rng.integers(0, T, 2))
+            bits[[a, b], p] = 1                        # two spikes far apart
+        elif kind == 3:
+            start = int(rng.integers(T // 2, T))       # spikes only late
+            bits[start::int(rng.integers(1, 9)), p] = 1
+        else:
+            m = rng.random(T) < rng.uniform(0.01, 0.9)
+            bits[m, p] = 1
+    s = spkgen.pack(bits)
+    t_out = rng.integers(0, T, 400).tolist() + [0, T - 1, T - 1]
+    for order in (1, 2):
+        check_recon(spk, s, 1, 200, T, t_out, order)
