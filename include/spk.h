@@ -113,6 +113,52 @@ int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t
                  int32_t cap, int32_t *seg_first, int32_t *seg_last, int32_t *seg_n,
                  int32_t *count, void *hip_stream);
 
+/*
+ * Batched plans: many streams of uneven size reconstructed by one
+ * persistent kernel (one wave per 64-pixel strip of a stream at a time,
+ * strips taken from per-XCD work counters), captured once in a HIP graph.
+ *
+ * spk_job describes one stream: stream and out are device pointers laid
+ * out as for spk_reconstruct; t_out is a host pointer read (and copied)
+ * during spk_plan_create only; n_out > 0.
+ *
+ * spk_plan_create validates every job on the host (SPK_EINVAL on any bad
+ * field, nothing allocated), uploads the job table and the sorted output
+ * times, chooses the launch shape (with SPK_PLAN_AUTOTUNE: by timing a few
+ * shapes on the real jobs, which writes their outputs; the choice is
+ * cached per job-size signature in the process and, if the environment
+ * variable SPK_TUNE_CACHE names a file, in that JSON file), captures the
+ * graph (unless SPK_PLAN_NO_GRAPH) and synchronises before returning.
+ * The streams must stay valid and unchanged in place for the plan's life;
+ * their contents may change between executions.
+ *
+ * spk_plan_execute enqueues one execution on hip_stream (NULL = default
+ * stream) and returns; executions of one plan must not overlap (they share
+ * the plan's work counters).  spk_plan_destroy waits for the plan's device
+ * to drain and frees everything the plan owns.  Results are identical to
+ * spk_reconstruct of each job, for every launch shape.
+ */
+typedef struct spk_job {
+    const uint8_t *stream;
+    int32_t H, W, T;
+    float theta;
+    const int32_t *t_out;
+    int32_t n_out;
+    float *out;
+} spk_job;
+
+typedef struct spk_plan_s *spk_plan_t;
+
+enum { SPK_PLAN_AUTOTUNE = 1, SPK_PLAN_NO_GRAPH = 2 };
+
+int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32_t order,
+                    int32_t flags);
+int spk_plan_execute(spk_plan_t plan, void *hip_stream);
+/* Launch shape and size: workgroups (one wave each), strips taken per
+ * counter grab, total strips.  Any pointer may be NULL. */
+int spk_plan_info(spk_plan_t plan, int32_t *grid, int32_t *grab, int32_t *items);
+int spk_plan_destroy(spk_plan_t plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,11 @@ FSR = 1
 SSR = 2
 
 __all__ = ["FSR", "SSR", "SpkError", "frame_bytes", "reconstruct", "reconstruct_windows",
-           "segments", "version", "set_time_chunks", "get_time_chunks"]
+           "segments", "version", "set_time_chunks", "get_time_chunks", "Plan",
+           "PLAN_AUTOTUNE", "PLAN_NO_GRAPH"]
+
+PLAN_AUTOTUNE = 1
+PLAN_NO_GRAPH = 2
 
 
 def frame_bytes(H: int, W: int) -> int:
@@ -115,3 +119,63 @@ def segments(stream_t, H, W, T, order=FSR, cap=64, stream=None):
                                   _stream_handle(stream))
     _lib.check("spk_segments", rc)
     return sf, sl, sn, cnt
+
+
+class Plan:
+    """A batched reconstruction of several streams (``spk_plan_*``).
+
+    ``jobs`` is a sequence of dicts with keys ``stream`` (device uint8
+    tensor), ``H``, ``W``, ``T``, ``t_out`` (host sequence), ``theta``
+    (default 1.0) and optionally ``out`` (device float32 tensor
+    [n_out, H, W]; allocated if absent).  The tensors must stay alive and in
+    place for the plan's life; ``execute`` re-runs the captured graph."""
+
+    def __init__(self, jobs, order: int = FSR, autotune: bool = True, graph: bool = True):
+        import ctypes
+        lib = _lib.load()
+        self.jobs = []
+        arr = (_lib.SpkJob * len(jobs))()
+        self._keep = []
+        for i, j in enumerate(jobs):
+            H, W, T = int(j["H"]), int(j["W"]), int(j["T"])
+            _check_stream_tensor(j["stream"], H, W, T)
+            t, tp = _host_times(j["t_out"])
+            out = j.get("out")
+            if out is None:
+                out = torch.empty((len(t), H, W), dtype=torch.float32, device=j["stream"].device)
+            assert out.dtype == torch.float32 and out.is_contiguous()
+            assert out.numel() >= len(t) * H * W
+            self._keep.append((j["stream"], t, out))
+            self.jobs.append(dict(j, out=out))
+            arr[i] = _lib.SpkJob(j["stream"].data_ptr(), H, W, T, float(j.get("theta", 1.0)), tp,
+                                 len(t), out.data_ptr())
+        flags = (PLAN_AUTOTUNE if autotune else 0) | (0 if graph else PLAN_NO_GRAPH)
+        handle = ctypes.c_void_p()
+        rc = lib.spk_plan_create(ctypes.byref(handle), arr, len(jobs), order, flags)
+        _lib.check("spk_plan_create", rc)
+        self._h = handle
+
+    def execute(self, stream=None):
+        _lib.check("spk_plan_execute", _lib.load().spk_plan_execute(self._h,
+                                                                    _stream_handle(stream)))
+
+    def info(self):
+        import ctypes
+        g, b, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check("spk_plan_info", _lib.load().spk_plan_info(self._h, ctypes.byref(g),
+                                                              ctypes.byref(b), ctypes.byref(n)))
+        return {"grid": g.value, "grab": b.value, "items": n.value}
+
+    def outputs(self):
+        return [j["out"] for j in self.jobs]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check("spk_plan_destroy", _lib.load().spk_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -53,8 +53,21 @@ def _declare(lib):
     return lib
 
 
-# entry points added by later modules register their signatures here
-EXTRA_DECLS: dict = {}
+class SpkJob(ctypes.Structure):
+    """Mirror of ``spk_job`` in include/spk.h."""
+    _fields_ = [("stream", ctypes.c_void_p), ("H", c_i32), ("W", c_i32), ("T", c_i32),
+                ("theta", ctypes.c_float), ("t_out", ctypes.c_void_p), ("n_out", c_i32),
+                ("out", ctypes.c_void_p)]
+
+
+EXTRA_DECLS: dict = {
+    "spk_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SpkJob), c_i32, c_i32,
+                        c_i32],
+    "spk_plan_execute": [ctypes.c_void_p, ctypes.c_void_p],
+    "spk_plan_info": [ctypes.c_void_p, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                      ctypes.POINTER(c_i32)],
+    "spk_plan_destroy": [ctypes.c_void_p],
+}
 
 
 def load():

@@ -1,0 +1,499 @@
+// Device building blocks shared by the reconstruction kernels (plain,
+// chunked and batched): the wave-wide 64x64 bit transpose, the per-pixel
+// FSR/SSR state machine, the segment writer and the per-word walk.
+#pragma once
+
+#include "spk_internal.h"
+
+namespace spk {
+namespace {
+
+constexpr int kBig = 1 << 29;
+constexpr int kGroup = 8;          // tiles per prefetch group
+constexpr int kMaxLdsPlanes = 8192;  // plane map staged in LDS up to this size
+constexpr int kTargetWaves = 12288;  // chunk a stream until this many waves run
+constexpr int kMinChunkTiles = 16;   // shortest chunk worth a separate wave
+constexpr int kWarmTiles = 4;        // speculative warm-up before a chunk
+constexpr int kCaptureTiles = 4;     // tiles after a chunk's start that record the
+                                     // first segment's window for the fixup pass
+
+// ---- cross-lane moves ----------------------------------------------------
+
+template <int S>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane)
+{
+    if constexpr (S == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (S == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (S == 4 || S == 8) {
+        // within a row of 16 lanes: lanes with bit S clear read lane + S
+        // (row_shl), the others lane - S (row_shr)
+        const int up = __builtin_amdgcn_update_dpp(0, (int)v, 0x100 + S, 0xF, 0xF, false);
+        const int dn = __builtin_amdgcn_update_dpp(0, (int)v, 0x110 + S, 0xF, 0xF, false);
+        return (uint32_t)((lane & S) ? dn : up);
+    } else {
+        static_assert(S == 16, "lane_xor");
+        // swap rows 1<->0 and 3<->2 of 16 lanes
+        auto r = __builtin_amdgcn_permlane16_swap((int)v, (int)v, false, false);
+        return (uint32_t)((lane & 16) ? r[0] : r[1]);
+    }
+}
+
+// Per-lane constants of the transpose stages s = 16, 8, 4, 2, 1 acting on
+// each 32-bit half: the bits a lane keeps and the rotation that brings the
+// partner's bits into place.
+struct Xpose {
+    uint32_t keep[5];
+    uint32_t rot[5];
+    __device__ __forceinline__ explicit Xpose(int lane)
+    {
+        constexpr uint32_t m[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u,
+                                   0x55555555u};
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            const int s = 16 >> i;
+            const bool up = (lane & s) != 0;
+            keep[i] = up ? ~m[i] : m[i];
+            rot[i] = up ? (uint32_t)s : (uint32_t)(32 - s);
+        }
+    }
+};
+
+template <int I>
+__device__ __forceinline__ uint32_t xstage(uint32_t v, const Xpose &X, int lane)
+{
+    constexpr int s = 16 >> I;
+    const uint32_t y = lane_xor<s>(v, lane);
+    // rotate the partner's word so its swapped block lands in place; bits
+    // wrapped around by the rotation fall outside the taken mask
+    const uint32_t t = __builtin_amdgcn_alignbit(y, y, X.rot[I]);
+    return (v & X.keep[I]) | (t & ~X.keep[I]);
+}
+
+// 64x64 bit-matrix transpose across a wave: on entry lane j holds row j as
+// (lo, hi), on exit lane i holds column i (bit j of lane i = bit i of row j).
+// Stage s swaps the off-diagonal s x s blocks between lanes j and j ^ s.
+__device__ __forceinline__ uint64_t transpose64(uint32_t lo, uint32_t hi, const Xpose &X,
+                                                int lane)
+{
+    // s = 32: lanes 32..63 take the partner's high word as their low word,
+    // lanes 0..31 the partner's low word as their high word
+    auto r = __builtin_amdgcn_permlane32_swap((int)lo, (int)hi, false, false);
+    lo = (uint32_t)r[0];
+    hi = (uint32_t)r[1];
+    lo = xstage<0>(lo, X, lane);
+    hi = xstage<0>(hi, X, lane);
+    lo = xstage<1>(lo, X, lane);
+    hi = xstage<1>(hi, X, lane);
+    lo = xstage<2>(lo, X, lane);
+    hi = xstage<2>(hi, X, lane);
+    lo = xstage<3>(lo, X, lane);
+    hi = xstage<3>(hi, X, lane);
+    lo = xstage<4>(lo, X, lane);
+    hi = xstage<4>(hi, X, lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
+__device__ __forceinline__ int hibit64(uint64_t v) { return 63 - __builtin_clzll(v); }
+__device__ __forceinline__ int popc64(uint64_t v) { return __builtin_popcountll(v); }
+
+// Single-wave workgroups are dispatched round-robin over the 8 XCDs; give
+// each XCD a contiguous range of pixel strips.
+__device__ __forceinline__ int xcd_strip(int b, int nblocks)
+{
+    const int q = nblocks / 8, r = nblocks % 8;
+    const int xcd = b % 8, j = b / 8;
+    return xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
+}
+
+// Segmentation state of one pixel (registers).
+struct SegState {
+    int32_t flo, fhi;  // extremes of the open FSR segment's S1 values
+    // SSR: inside the open piece, per interval value (keyed by parity: an
+    // FSR segment holds at most two adjacent values) the piece-local index
+    // of its latest occurrence (-1: none) and the extremes of its S2 gaps
+    int32_t np;        // intervals in the open piece
+    int32_t l0, l1, g0l, g0h, g1l, g1h;
+
+    __device__ __forceinline__ void reset()
+    {
+        flo = kBig;
+        fhi = -kBig;
+        np = 0;
+        l0 = l1 = -1;
+        g0l = g1l = kBig;
+        g0h = g1h = -kBig;
+    }
+
+    // Add interval x; returns true if x opens a new segment (the previous
+    // spike then ends the closed one).
+    template <int ORDER>
+    __device__ __forceinline__ bool step(int32_t x)
+    {
+        const int32_t nlo = min(flo, x), nhi = max(fhi, x);
+        const bool fcut = nhi - nlo > 1;  // S1 leaves zero-order stability
+        flo = fcut ? x : nlo;
+        fhi = fcut ? x : nhi;
+        if constexpr (ORDER == 1) {
+            return fcut;
+        } else {
+            const bool odd = x & 1;
+            const int32_t l = odd ? l1 : l0;
+            const int32_t gl = odd ? g1l : g0l, gh = odd ? g1h : g0h;
+            const int32_t d = np - l;  // next element of S2 for value x
+            const int32_t ngl = min(gl, d), ngh = max(gh, d);
+            const bool cut = fcut || (l >= 0 && ngh - ngl > 1);
+            const bool fresh = cut || l < 0;
+            const int32_t ugl = fresh ? kBig : ngl, ugh = fresh ? -kBig : ngh;
+            const int32_t idx = cut ? 0 : np;
+            if (odd) {
+                l1 = idx; g1l = ugl; g1h = ugh;
+                l0 = cut ? -1 : l0; g0l = cut ? kBig : g0l; g0h = cut ? -kBig : g0h;
+            } else {
+                l0 = idx; g0l = ugl; g0h = ugh;
+                l1 = cut ? -1 : l1; g1l = cut ? kBig : g1l; g1h = cut ? -kBig : g1h;
+            }
+            np = idx + 1;
+            return cut;
+        }
+    }
+};
+
+// How output k (in time order) maps to its plane: identity, through an LDS
+// copy of the map, or through the map in global memory (very large maps).
+enum PlaneMap { PMAP_IDENT = 0, PMAP_LDS = 1, PMAP_GLOBAL = 2 };
+
+// Writes of one pixel's closed segments.
+template <int MODE, bool WIN, int PMAP>
+struct Emitter {
+    const ReconParams &P;
+    const int32_t *plane_s;  // LDS copy of the plane map (PMAP_LDS)
+    int64_t p;
+    bool valid;
+    int32_t segc;
+    int32_t kmin;            // outputs below this belong to an earlier chunk
+
+    __device__ __forceinline__ int32_t plane(int32_t k) const
+    {
+        if constexpr (PMAP == PMAP_IDENT) return k;
+        else if constexpr (PMAP == PMAP_LDS) return plane_s[k];
+        else return P.plane[k];
+    }
+
+    // A closed segment spanning spike frames [first, last] with n intervals
+    // covers sorted outputs [k0, kend).
+    __device__ __forceinline__ void close(int32_t first, int32_t last, int32_t n, int32_t k0,
+                                          int32_t kend)
+    {
+        if (!valid) return;
+        if constexpr (MODE == MODE_SEGMENTS) {
+            if (segc < P.cap) {
+                const int64_t o = (int64_t)segc * P.HW + p;
+                P.seg_first[o] = first;
+                P.seg_last[o] = last;
+                P.seg_n[o] = n;
+            }
+            segc++;
+        } else {
+            k0 = max(k0, kmin);
+            if (k0 >= kend) return;
+            // Eq. 6: theta / ((1/N) sum T0(i)); the N intervals sum to last - first
+            const float I = (float)(P.theta * (double)n / (double)(last - first));
+            for (int32_t k = k0; k < kend; k++) {
+                const int64_t o = (int64_t)plane(k) * P.HW + p;
+                if constexpr (WIN) {
+                    if (P.out) P.out[o] = I;
+                    if (P.win_first) P.win_first[o] = first;
+                    if (P.win_last) P.win_last[o] = last;
+                    if (P.win_n) P.win_n[o] = n;
+                } else {
+                    P.out[o] = I;
+                }
+            }
+        }
+    }
+
+    // Fewer than two spikes: no interval, output 0 and window (-1, -1, 0).
+    __device__ __forceinline__ void empty()
+    {
+        if (!valid || MODE == MODE_SEGMENTS) return;
+        for (int32_t k = 0; k < P.n_out; k++) {
+            const int64_t o = (int64_t)plane(k) * P.HW + p;
+            if constexpr (WIN) {
+                if (P.out) P.out[o] = 0.0f;
+                if (P.win_first) P.win_first[o] = -1;
+                if (P.win_last) P.win_last[o] = -1;
+                if (P.win_n) P.win_n[o] = 0;
+            } else {
+                P.out[o] = 0.0f;
+            }
+        }
+    }
+};
+
+// Running state of one pixel.
+struct Run {
+    int32_t lastspk;    // frame of the latest spike (-1: none yet)
+    int32_t cnt_last;   // number of sorted outputs at or before lastspk
+    int32_t cum;        // spikes so far
+    int32_t first;      // first spike frame of the open segment
+    int32_t first_idx;  // its index among the pixel's spikes
+    int32_t k0;         // first sorted output owned by the open segment
+    int32_t lastb;      // last spike of the latest closed segment (-1: none)
+    int32_t cs;         // first frame of the chunk (0 outside chunked runs)
+    int32_t fb1, fn1;   // first segment closed at or after cs: last spike, N,
+    int32_t fi1;        //   index of that last spike,
+    int32_t fwlo, fwhi; //   and its FSR window
+    SegState st;
+
+    __device__ __forceinline__ void reset(int32_t k0_, int32_t cs_ = 0)
+    {
+        lastspk = -1;
+        cnt_last = 0;
+        cum = 0;
+        first = -1;
+        first_idx = 0;
+        k0 = k0_;
+        lastb = -1;
+        cs = cs_;
+        fb1 = -1;
+        fn1 = 0;
+        fi1 = 0;
+        fwlo = kBig;  // kBig: not captured yet
+        fwhi = -kBig;
+        st.reset();
+    }
+
+    // One interval; while CAPTURE, the FSR window of the first segment that
+    // closes at or after the chunk's start is kept for the fixup pass.
+    template <int ORDER, bool CAPTURE>
+    __device__ __forceinline__ bool step_capture(int32_t x, int32_t tau)
+    {
+        if constexpr (ORDER == 1 && CAPTURE) {
+            const int32_t lo = st.flo, hi = st.fhi;
+            const bool cut = st.template step<ORDER>(x);
+            if (cut && fwlo == kBig && tau - x >= cs) {
+                fwlo = lo;
+                fwhi = hi;
+            }
+            return cut;
+        } else {
+            return st.template step<ORDER>(x);
+        }
+    }
+
+    // Process the 64-frame word w starting at frame t0; cnt_row[j] is the
+    // number of sorted outputs at or before frame t0 + j.
+    template <int ORDER, bool CAPTURE, class EM>
+    __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em)
+    {
+        const uint64_t wfull = w;
+        const int32_t cum0 = cum, lastspk0 = lastspk, cnt_last0 = cnt_last;
+        int32_t lp;  // position of the previous spike relative to t0
+        if (lastspk < 0) {
+            // the pixel's first spike opens its first segment
+            const int pos = ctz64(w);
+            w &= w - 1;
+            first = t0 + pos;
+            first_idx = 0;
+            lp = pos;
+        } else {
+            lp = lastspk - t0;
+        }
+        // walk the spikes of each 32-bit half; B marks spikes whose interval
+        // opens a new segment
+        uint32_t Blo = 0, Bhi = 0;
+        uint32_t h = (uint32_t)w;
+        while (h) {
+            const uint32_t nh = h & (h - 1);
+            const int pos = __builtin_ctz(h);
+            const int32_t x = pos - lp;  // interval T0 ending at this spike
+            lp = pos;
+            Blo |= step_capture<ORDER, CAPTURE>(x, t0 + pos) ? (h ^ nh) : 0u;
+            h = nh;
+        }
+        h = (uint32_t)(w >> 32);
+        while (h) {
+            const uint32_t nh = h & (h - 1);
+            const int pos = __builtin_ctz(h) + 32;
+            const int32_t x = pos - lp;
+            lp = pos;
+            Bhi |= step_capture<ORDER, CAPTURE>(x, t0 + pos) ? (h ^ nh) : 0u;
+            h = nh;
+        }
+        // close the segments that ended in this word
+        uint64_t B = ((uint64_t)Bhi << 32) | Blo;
+        while (B) {
+            const int cpos = ctz64(B);
+            B &= B - 1;
+            const uint64_t below = wfull & ((1ull << cpos) - 1);
+            int32_t last, kend;
+            if (below) {
+                const int bp = hibit64(below);
+                last = t0 + bp;
+                kend = cnt_row[bp];
+            } else {
+                last = lastspk0;
+                kend = cnt_last0;
+            }
+            const int32_t last_idx = cum0 + popc64(below) - 1;
+            em.close(first, last, last_idx - first_idx, k0, kend);
+            if (fb1 < 0 && last >= cs) {
+                fb1 = last;
+                fn1 = last_idx - first_idx;
+                fi1 = last_idx;
+            }
+            first = last;
+            first_idx = last_idx;
+            k0 = kend;
+            lastb = last;
+        }
+        cum = cum0 + popc64(wfull);
+        const int hp = hibit64(wfull);
+        lastspk = t0 + hp;
+        cnt_last = cnt_row[hp];
+    }
+};
+
+// Per-chunk record of the running state at the chunk's end, [field][chunk][pixel].
+enum RecField {
+    R_LASTSPK, R_CNTLAST, R_CUM, R_FIRST, R_FIRSTIDX, R_K0, R_LASTB, R_FB1, R_FN1,
+    R_FI1, R_FWLO, R_FWHI,
+    R_FLO, R_FHI, R_NP, R_L0, R_L1, R_G0L, R_G0H, R_G1L, R_G1H, R_NFIELDS
+};
+static_assert(R_NFIELDS == kRecFields, "record layout");
+
+// Records of chunk c: the state at the chunk's end (all chunks) and the
+// warmed-up speculative state at its start (chunks > 0), each [field][chunk][HW].
+__device__ __forceinline__ int32_t *rec_end(const ChunkPlan &cp, int c, int64_t p, int32_t HW)
+{
+    return cp.rec + (int64_t)c * HW + p;
+}
+__device__ __forceinline__ int32_t *rec_start(const ChunkPlan &cp, int c, int64_t p, int32_t HW)
+{
+    return cp.rec + (int64_t)R_NFIELDS * cp.nchunks * HW + (int64_t)c * HW + p;
+}
+
+__device__ __forceinline__ void save_run(int32_t *rec, int64_t stride, const Run &r)
+{
+    const int32_t v[R_NFIELDS] = {r.lastspk, r.cnt_last, r.cum, r.first, r.first_idx, r.k0,
+                                  r.lastb, r.fb1, r.fn1, r.fi1, r.fwlo, r.fwhi,
+                                  r.st.flo, r.st.fhi, r.st.np,
+                                  r.st.l0, r.st.l1,
+                                  r.st.g0l, r.st.g0h, r.st.g1l, r.st.g1h};
+#pragma unroll
+    for (int f = 0; f < R_NFIELDS; f++) rec[f * stride] = v[f];
+}
+
+__device__ __forceinline__ void load_run(const int32_t *rec, int64_t stride, Run &r)
+{
+    int32_t v[R_NFIELDS];
+#pragma unroll
+    for (int f = 0; f < R_NFIELDS; f++) v[f] = rec[f * stride];
+    r.lastspk = v[R_LASTSPK];
+    r.cnt_last = v[R_CNTLAST];
+    r.cum = v[R_CUM];
+    r.first = v[R_FIRST];
+    r.first_idx = v[R_FIRSTIDX];
+    r.k0 = v[R_K0];
+    r.lastb = v[R_LASTB];
+    r.fb1 = v[R_FB1];
+    r.fn1 = v[R_FN1];
+    r.fi1 = v[R_FI1];
+    r.fwlo = v[R_FWLO];
+    r.fwhi = v[R_FWHI];
+    r.cs = 0;
+    r.st.flo = v[R_FLO];
+    r.st.fhi = v[R_FHI];
+    r.st.np = v[R_NP];
+    r.st.l0 = v[R_L0];
+    r.st.l1 = v[R_L1];
+    r.st.g0l = v[R_G0L];
+    r.st.g0h = v[R_G0H];
+    r.st.g1l = v[R_G1L];
+    r.st.g1h = v[R_G1H];
+}
+
+// Two states make the same cut decisions for every continuation when their
+// FSR extremes agree and, for SSR, each value's S2 gap extremes and the
+// distance back to its latest occurrence agree (piece-local indices differ
+// by a constant shift, which no decision sees).
+template <int ORDER>
+__device__ __forceinline__ bool same_decisions(const SegState &a, const SegState &b)
+{
+    if (a.flo != b.flo || a.fhi != b.fhi) return false;
+    if constexpr (ORDER == 1) {
+        return true;
+    } else {
+        const int32_t a0 = a.l0 < 0 ? -1 : a.np - a.l0, b0 = b.l0 < 0 ? -1 : b.np - b.l0;
+        const int32_t a1 = a.l1 < 0 ? -1 : a.np - a.l1, b1 = b.l1 < 0 ? -1 : b.np - b.l1;
+        return a0 == b0 && a1 == b1 && a.g0l == b.g0l && a.g0h == b.g0h && a.g1l == b.g1l &&
+               a.g1h == b.g1h;
+    }
+}
+
+
+// One wave walks tiles [tilew, tile1) of its 64-pixel strip starting at
+// p0, prefetching a group of tiles ahead.  In a chunked run (CHUNKED) the
+// tiles before tile0 only warm the state up, the state at tile0 is saved to
+// rec_start, and the first tiles after tile0 keep what the fixup pass needs.
+template <int ORDER, bool CHUNKED, class EM>
+__device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
+                                     const uint8_t *base, const Xpose &X, int lane,
+                                     int32_t tilew, int32_t tile0, int32_t tile1,
+                                     uint64_t (*word_s)[64], int32_t (*cnt_s)[64],
+                                     int32_t *rec_start, int64_t fstride, int32_t &cum_base)
+{
+    uint32_t rlo[kGroup], rhi[kGroup];
+    int32_t rc[kGroup];
+    auto fetch = [&](int32_t tg) {
+#pragma unroll
+        for (int i = 0; i < kGroup; i++) {
+            const int32_t tr = (tg + i) * 64 + lane;
+            rlo[i] = rhi[i] = 0;
+            rc[i] = 0;
+            if (tg + i < tile1 && tr < P.T) {
+                const uint2 v = *(const uint2 *)(base + (int64_t)tr * P.fb);
+                rlo[i] = v.x;
+                rhi[i] = v.y;
+                if (P.cnt_le) rc[i] = P.cnt_le[tr];
+            }
+        }
+    };
+    fetch(tilew);
+    for (int32_t tg = tilew; tg < tile1; tg += kGroup) {
+        // the group's rows are in registers: transpose into LDS, then start
+        // fetching the next group
+#pragma unroll
+        for (int i = 0; i < kGroup; i++) {
+            word_s[i][lane] = transpose64(rlo[i], rhi[i], X, lane);
+            cnt_s[i][lane] = rc[i];
+        }
+        fetch(tg + kGroup);
+        __syncthreads();
+        const int32_t ni = min(kGroup, tile1 - tg);
+        for (int i = 0; i < ni; i++) {
+            const int32_t t = tg + i;
+            const uint64_t w = word_s[i][lane];
+            if constexpr (CHUNKED) {
+                if (t == tile0 && rec_start) {
+                    // the speculative state the fixup pass starts from
+                    if (em.valid) save_run(rec_start, fstride, run);
+                    cum_base = run.cum;
+                }
+                // the first tiles of a later chunk keep what the fixup needs
+                if (ORDER == 1 && rec_start && t >= tile0 && t < tile0 + kCaptureTiles) {
+                    if (w) run.template word<ORDER, true>(t * 64, w, cnt_s[i], em);
+                    continue;
+                }
+            }
+            if (w) run.template word<ORDER, false>(t * 64, w, cnt_s[i], em);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+}  // namespace spk

@@ -204,3 +204,15 @@ BLOCKS_250x400 = Workload("blocks_250x400_T1024", 250, 400, 1024, 1, "blocks",
 # 250x400 moving gratings + disk with Poisson noise, 20000 frames, every 10th out
 GRATINGS_250x400 = Workload("gratings_250x400_T20000_every10", 250, 400, 20000, 2,
                             "gratings", out_every=10)
+
+
+# 16 streams of 4096 frames, sizes drawn uniformly from four resolutions
+# (seed 3), static blocks per stream (seed 3000 + i), 64 outputs at 32 + 64 k
+BATCH_SIZES = ((250, 400), (500, 800), (720, 1280), (1000, 1000))
+
+
+def batch_workload(n_streams: int = 16, T: int = 4096, seed: int = 3):
+    """Shapes, seeds and output times of the batched workload."""
+    rng_sizes = [BATCH_SIZES[rng_u64(seed, 6, i) % len(BATCH_SIZES)] for i in range(n_streams)]
+    t_out = [32 + 64 * k for k in range(64) if 32 + 64 * k < T]
+    return [dict(H=H, W=W, T=T, seed=3000 + i, t_out=t_out) for i, (H, W) in enumerate(rng_sizes)]

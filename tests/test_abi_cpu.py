@@ -90,3 +90,46 @@ def test_segments_rejects_bad_arguments(lib):
 def test_zero_outputs_is_noop(lib):
     # n_out == 0 returns before any device work
     assert lib.spk_reconstruct(FAKE, 4, 4, 10, 1.0, None, 0, None, 1, None) == 0
+
+
+def _job(lib, **kw):
+    from paper_2412_11639_amd._lib import SpkJob
+    t = (ctypes.c_int32 * 4)(*kw.pop("t_out", [0, 1, 2, 3]))
+    a = dict(stream=FAKE, H=4, W=4, T=10, theta=1.0, n_out=4, out=FAKE)
+    a.update(kw)
+    j = SpkJob(a["stream"], a["H"], a["W"], a["T"], a["theta"], ctypes.addressof(t), a["n_out"],
+               a["out"])
+    return j, t
+
+
+@pytest.mark.parametrize("bad", [
+    dict(stream=0), dict(out=0), dict(H=0), dict(T=-1), dict(theta=0.0),
+    dict(theta=float("nan")), dict(n_out=0), dict(t_out=[0, 1, 2, 10]),
+    dict(H=65536, W=65536)])
+def test_plan_create_rejects_bad_jobs(lib, bad):
+    from paper_2412_11639_amd._lib import SpkJob
+    good, tg = _job(lib)
+    badj, tb = _job(lib, **bad)
+    arr = (SpkJob * 2)(good, badj)
+    h = ctypes.c_void_p()
+    assert lib.spk_plan_create(ctypes.byref(h), arr, 2, 1, 0) == -1
+    assert not h.value
+
+
+def test_plan_create_rejects_bad_arguments(lib):
+    from paper_2412_11639_amd._lib import SpkJob
+    good, tg = _job(lib)
+    arr = (SpkJob * 1)(good)
+    h = ctypes.c_void_p()
+    assert lib.spk_plan_create(None, arr, 1, 1, 0) == -1
+    assert lib.spk_plan_create(ctypes.byref(h), arr, 0, 1, 0) == -1
+    assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 3, 0) == -1
+    assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 1, 8) == -1
+    assert lib.spk_plan_execute(None, None) == -1
+    assert lib.spk_plan_destroy(None) == 0
+
+
+def test_options(lib):
+    assert lib.spk_set_option(99, 1) == -1
+    assert lib.spk_set_option(1, -1) == -1
+    assert lib.spk_get_option(99) == -1

@@ -1,0 +1,95 @@
+"""Batched plans (persistent kernel in a HIP graph) against the oracle and
+against single-stream calls."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import spkgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spk():
+    import paper_2412_11639_amd as m
+    assert torch.cuda.is_available(), "no GPU"
+    return m
+
+
+def make_jobs(order_seed=0, unsorted=False):
+    rng = np.random.default_rng(order_seed)
+    shapes = [(37, 91, 1500), (64, 64, 777), (20, 250, 2049), (1, 7, 300), (50, 80, 1024)]
+    jobs = []
+    for i, (H, W, T) in enumerate(shapes):
+        if i % 2:
+            s = spkgen.gratings(H, W, T, seed=100 + i)
+        else:
+            s = spkgen.blocks(H, W, T, seed=100 + i, vx=0.2 * i, vy=-0.1 * i)
+        t_out = sorted(set(rng.integers(0, T, 40).tolist()))
+        if unsorted and i == 2:
+            t_out = rng.integers(0, T, 60).tolist() + [0, 0, T - 1]
+        jobs.append(dict(np_stream=s, stream=torch.from_numpy(s).cuda(), H=H, W=W, T=T,
+                         t_out=t_out, theta=1.0 + 0.5 * i))
+    return jobs
+
+
+def check_against_oracle(jobs, outs, order):
+    for j, out in zip(jobs, outs):
+        print("job H=%d W=%d T=%d" % (j["H"], j["W"], j["T"]), flush=True)
+        ref = oracle.reconstruct(j["np_stream"], j["H"], j["W"], j["T"], j["theta"], j["t_out"],
+                                 order=order)
+        np.testing.assert_array_equal(out.cpu().numpy(), ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("unsorted", [False, True])
+def test_plan_matches_oracle(spk, order, unsorted):
+    jobs = make_jobs(1, unsorted)
+    plan = spk.Plan(jobs, order=order, autotune=True)
+    plan.execute()
+    torch.cuda.synchronize()
+    info = plan.info()
+    assert info["items"] == sum((j["H"] * j["W"] + 63) // 64 for j in jobs)
+    assert info["grid"] > 0 and info["grab"] > 0
+    check_against_oracle(jobs, plan.outputs(), order)
+    plan.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_graph_replays_match_eager(spk, order):
+    """Replay the captured graph several times with unrelated eager work and
+    synchronisations in between; every replay equals the single-stream
+    result."""
+    jobs = make_jobs(2)
+    eager = [spk.reconstruct(j["stream"], j["H"], j["W"], j["T"], j["theta"], j["t_out"],
+                             order=order) for j in jobs]
+    plan = spk.Plan(jobs, order=order, autotune=False)
+    for rep in range(4):
+        for o in plan.outputs():
+            o.fill_(-1.0)
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        plan.execute()
+        torch.cuda.synchronize()
+        for o, e in zip(plan.outputs(), eager):
+            assert torch.equal(o, e), "replay %d differs" % rep
+        del junk
+    plan.close()
+
+
+def test_plan_without_graph_and_shapes_agree(spk):
+    jobs = make_jobs(3)
+    a = spk.Plan(jobs, order=1, autotune=False, graph=False)
+    a.execute()
+    torch.cuda.synchronize()
+    first = [o.clone() for o in a.outputs()]
+    a.close()
+    b = spk.Plan(jobs, order=1, autotune=True)
+    for o in b.outputs():
+        o.zero_()
+    b.execute()
+    torch.cuda.synchronize()
+    for x, y in zip(first, b.outputs()):
+        assert torch.equal(x, y)
+    b.close()
