@@ -108,6 +108,33 @@ __device__ __forceinline__ int xcd_strip(int b, int nblocks)
     return xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
 }
 
+// OR of (w >> d) for d = 1..k, 0 <= k <= 15: bit j is set when some spike
+// lies within k frames after frame j.
+__device__ __forceinline__ uint64_t smear_down(uint64_t w, int k)
+{
+    const uint64_t r1 = w >> 1, r2 = r1 | (r1 >> 1), r4 = r2 | (r2 >> 2), r8 = r4 | (r4 >> 4);
+    uint64_t s = (k & 8) ? r8 : 0;
+    int sh = k & 8;
+    s |= ((k & 4) ? r4 : 0) >> sh;
+    sh += k & 4;
+    s |= ((k & 2) ? r2 : 0) >> sh;
+    sh += k & 2;
+    s |= ((k & 1) ? r1 : 0) >> sh;
+    return s;
+}
+
+// True when every gap between consecutive spikes of the nonzero word w is a
+// (or a + 1 when plus1), 1 <= a <= 15.
+__device__ __forceinline__ bool gaps_within(uint64_t w, int a, bool plus1)
+{
+    const uint64_t near = smear_down(w, a - 1);  // another spike closer than a
+    const uint64_t within = near | (w >> a) | (plus1 ? (w >> (a + 1)) : 0ull);
+    const uint64_t top = 1ull << (63 - __builtin_clzll(w));
+    return !(w & near) && (w & ~within) == top;
+}
+
+constexpr int kFastMaxGap = 15;  // word-level shortcut for intervals up to this
+
 // Segmentation state of one pixel (registers).
 struct SegState {
     int32_t flo, fhi;  // extremes of the open FSR segment's S1 values
@@ -125,6 +152,52 @@ struct SegState {
         l0 = l1 = -1;
         g0l = g1l = kBig;
         g0h = g1h = -kBig;
+    }
+
+    // Whole-word shortcut: if none of the word's intervals -- x0 (from the
+    // previous word's last spike to the word's first spike) and the gaps
+    // inside the nonzero word w, c spikes in all -- opens a new segment,
+    // apply them all and return true; otherwise change nothing and return
+    // false.  FSR: all intervals in [flo, flo + 1] keep the segment stable.
+    // SSR: only words whose intervals all equal one value v, with the S2
+    // gaps of v staying stable (the gaps inside the word are all 1).
+    template <int ORDER>
+    __device__ __forceinline__ bool fast_word(uint64_t w, int32_t x0, int32_t c)
+    {
+        if constexpr (ORDER == 1) {
+            const int32_t a = flo;
+            if (a < 1 || a > kFastMaxGap || x0 < a || x0 > a + 1) return false;
+            if (!gaps_within(w, a, true)) return false;
+            // a gap of a + 1 somewhere (the others are exactly a)
+            const bool wide = x0 == a + 1 || popc64(w & (w >> a)) < c - 1;
+            fhi = max(fhi, wide ? a + 1 : a);
+            return true;
+        } else {
+            const int32_t v = x0;
+            if (v < 1 || v > kFastMaxGap || max(fhi, v) - min(flo, v) > 1) return false;
+            if (c > 1 && !gaps_within(w, v, false)) return false;
+            const bool odd = v & 1;
+            const int32_t l = odd ? l1 : l0;
+            int32_t gl = odd ? g1l : g0l, gh = odd ? g1h : g0h;
+            if (l >= 0) {
+                gl = min(gl, np - l);
+                gh = max(gh, np - l);
+            }
+            if (c > 1) {
+                gl = min(gl, 1);
+                gh = max(gh, 1);
+            }
+            if (gh - gl > 1) return false;
+            flo = min(flo, v);
+            fhi = max(fhi, v);
+            if (odd) {
+                l1 = np + c - 1; g1l = gl; g1h = gh;
+            } else {
+                l0 = np + c - 1; g0l = gl; g0h = gh;
+            }
+            np += c;
+            return true;
+        }
     }
 
     // Add interval x; returns true if x opens a new segment (the previous
@@ -289,6 +362,17 @@ struct Run {
     template <int ORDER, bool CAPTURE, class EM>
     __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em)
     {
+        if (lastspk >= 0) {
+            const int32_t c = popc64(w);
+            if (st.template fast_word<ORDER>(w, t0 + ctz64(w) - lastspk, c)) {
+                // no segment ends in this word
+                cum += c;
+                const int hp = hibit64(w);
+                lastspk = t0 + hp;
+                cnt_last = cnt_row[hp];
+                return;
+            }
+        }
         const uint64_t wfull = w;
         const int32_t cum0 = cum, lastspk0 = lastspk, cnt_last0 = cnt_last;
         int32_t lp;  // position of the previous spike relative to t0
