@@ -46,6 +46,10 @@ def _bind(lib):
     lib.spk_oracle_reconstruct.argtypes = [
         P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P_i32,
         ctypes.c_int32, ctypes.c_int32, P_f64, P_i32, P_i32, P_i32, ctypes.c_int32]
+    lib.spk_oracle_window.restype = ctypes.c_int32
+    lib.spk_oracle_window.argtypes = [P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_double, ctypes.c_int32, P_f64,
+                                      ctypes.POINTER(ctypes.c_uint8)]
     lib.spk_oracle_segments.restype = ctypes.c_int32
     lib.spk_oracle_segments.argtypes = [
         P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -125,3 +129,17 @@ def segments(stream, H, W, T, order=FSR, cap=64, nthreads=None, lib=None):
     if rc != 0:
         raise ValueError("spk_oracle_segments: bad arguments")
     return sf, sl, sn, cnt
+
+
+def window_estimate(stream, H, W, T, theta, t, lib=None):
+    """Short-window estimate and stability flag at output time t (>= 31):
+    (est float64 [H, W], stable bool [H, W])."""
+    lib = lib or load()
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    est = np.zeros((H, W), dtype=np.float64)
+    st = np.zeros((H, W), dtype=np.uint8)
+    rc = lib.spk_oracle_window(_ptr(stream, P_u8), H, W, T, float(theta), int(t),
+                               _ptr(est, P_f64), st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if rc != 0:
+        raise ValueError("spk_oracle_window: bad arguments")
+    return est, st.astype(bool)

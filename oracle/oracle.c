@@ -354,3 +354,39 @@ int32_t spk_oracle_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t
     run_all(&tk, nthreads);
     return 0;
 }
+
+/* ---- short-window estimate for the learned surrogate -------------------
+ * For output time t (t >= 31) the window is the 32 frames t-31 .. t of the
+ * pixel, taken as a stream of its own.  Its estimate is what O-1 .. O-7
+ * give on that stream at its last frame: the FSR segment holding the last
+ * interval (the interval in progress at t), intensity theta*N/D.  With
+ * fewer than two spikes in the window the estimate is the fixed-window rate
+ * theta*K/32 (TFP with a 32-frame window, Sec. II).  The window is "stable"
+ * when FSR keeps it as one segment (at least two spikes, no cut). */
+int32_t spk_oracle_window(const uint8_t *stream, int32_t H, int32_t W, int32_t T, double theta,
+                          int32_t t, double *est, uint8_t *stable)
+{
+    if (!stream || !est || !stable || H <= 0 || W <= 0 || t < 31 || t >= T) return -1;
+    size_t fb = frame_bytes(H, W);
+    int64_t hw = (int64_t)H * W;
+    int32_t tau[32], x[32], start[32], work[32];
+    for (int64_t p = 0; p < hw; p++) {
+        int32_t K = 0;
+        for (int32_t j = 0; j < 32; j++) {
+            int32_t f = t - 31 + j;
+            if ((stream[(size_t)f * fb + (size_t)(p >> 3)] >> (p & 7)) & 1) tau[K++] = j;
+        }
+        if (K < 2) {
+            est[p] = theta * (double)K / 32.0;
+            stable[p] = 0;
+            continue;
+        }
+        for (int32_t i = 0; i + 1 < K; i++) x[i] = tau[i + 1] - tau[i];
+        int32_t nseg = segment_intervals(x, K - 1, ORACLE_FSR, start, work);
+        int32_t a = start[nseg - 1];
+        int32_t cnt = (K - 1) - a;
+        est[p] = theta * (double)cnt / (double)(tau[K - 1] - tau[a]);
+        stable[p] = nseg == 1;
+    }
+    return 0;
+}
