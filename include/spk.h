@@ -159,6 +159,75 @@ int spk_plan_execute(spk_plan_t plan, void *hip_stream);
 int spk_plan_info(spk_plan_t plan, int32_t *grid, int32_t *grab, int32_t *items);
 int spk_plan_destroy(spk_plan_t plan);
 
+/*
+ * Learned surrogate (not part of the paper's method: a small CNN that maps
+ * a 32-frame spike window plus the plain short-window estimate to the
+ * long-window reconstruction; the plain method stays the fallback).
+ *
+ * Network: four 3x3 convolutions with zero padding, 33 -> 32 -> 32 -> 32 -> 1
+ * channels, ReLU after the first three, output added to the estimate
+ * (y = est + CNN).  Input channel j < 32 is frame t-31+j of the pixel
+ * (0/1), channel 32 the short-window estimate.
+ * Parameters: one device float32 vector of SPK_SUR_NPARAMS values,
+ * W1 [32][9][33], b1 [32], W2 [32][9][32], b2 [32], W3 [32][9][32], b3 [32],
+ * W4 [1][9][32], b4 [1]; tap k = 3*dy + dx reads offset (dy - 1, dx - 1).
+ * The kernels compute in bfloat16 on the matrix cores with float32
+ * accumulation; weights, inputs, activations and backpropagated gradients
+ * are rounded to bfloat16, everything else stays float32.
+ *
+ * A batch is B images of Hc x Wc pixels, arrays [B][Hc][Wc] (device).
+ * workspace: device scratch of spk_sur_workspace_bytes(B, Hc, Wc) bytes,
+ * owned by the caller; spk_sur_backward reads the activations that the
+ * spk_sur_forward call before it left there (same params, inputs, shape).
+ */
+#define SPK_SUR_NPARAMS 28321
+#define SPK_SUR_MAX_SAMPLES 64
+
+typedef struct spk_sur_sample {
+    const uint8_t *stream; /* device: T packed frames of an H x W stream   */
+    int32_t H, W, T;
+    int32_t oy, ox;        /* crop origin; the crop lies inside the frame */
+    int32_t t;             /* output time, 31 <= t < T                    */
+    const float *target;   /* device H x W training targets, or NULL      */
+} spk_sur_sample;
+
+size_t spk_sur_workspace_bytes(int32_t B, int32_t Hc, int32_t Wc);
+
+/* Window, short-window estimate and stability flag for B <= 64 crops
+ * (samples is a host array).  win[b][y][x] bit j = frame t-31+j; est = the
+ * plain method (FSR, Eq. 6) on the window as a stream of its own at its last
+ * frame, theta*K/32 below two spikes; stable = FSR keeps the window as one
+ * segment.  target (may be NULL) receives the crops of the samples' target
+ * frames, which must then all be given. */
+int spk_sur_input(const spk_sur_sample *samples, int32_t B, int32_t Hc, int32_t Wc, float theta,
+                  uint32_t *win, float *est, uint8_t *stable, float *target, void *hip_stream);
+
+/* Streaming update for a whole H x W frame: win = (win >> 1) | frame << 31,
+ * then est and stable of the new window (frame: one packed frame). */
+int spk_sur_stream_step(const uint8_t *frame, int32_t H, int32_t W, float theta, uint32_t *win,
+                        float *est, uint8_t *stable, void *hip_stream);
+
+/* y = network(win, est), float32 [B][Hc][Wc]. */
+int spk_sur_forward(const float *params, const uint32_t *win, const float *est, int32_t B,
+                    int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream);
+
+/* Gradient of the mean squared error between y and target over all B*Hc*Wc
+ * pixels with respect to the parameters (grad: float32 [SPK_SUR_NPARAMS],
+ * overwritten).  loss_partial (may be NULL): ceil(B*Hc*Wc / 256) partial
+ * sums of squared errors, in block order. */
+int spk_sur_backward(const float *params, const uint32_t *win, const float *est, int32_t B,
+                     int32_t Hc, int32_t Wc, const float *y, const float *target, float *grad,
+                     float *loss_partial, void *workspace, void *hip_stream);
+
+/* One Adam step (with bias correction, step >= 1) on params in place;
+ * m and v are the caller's float32 moment buffers. */
+int spk_sur_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void *hip_stream);
+
+/* Fallback: out = stable ? y : est, over n values. */
+int spk_sur_mux(const float *y, const float *est, const uint8_t *stable, int64_t n, float *out,
+                void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,7 +1,8 @@
 """CPU reference of the learned surrogate -- TEST INFRASTRUCTURE ONLY.
 
 The surrogate is a small CNN: four 3x3 convolutions with zero padding,
-33 -> 32 -> 32 -> 32 -> 1 channels, ReLU after the first three.  Its input at
+33 -> 32 -> 32 -> 32 -> 1 channels, ReLU after the first three, whose output
+is added to the plain short-window estimate (y = est + CNN).  Its input at
 output time t is, per pixel, the 32 binary frames t-31 .. t (channels 0..31,
 channel j = frame t-31+j) and the plain short-window estimate (channel 32).
 
@@ -106,8 +107,9 @@ def make_input(win_bits, est, bf=True):
     return np.stack(chans, axis=-1)
 
 
-def forward(params, x0, bf=True):
-    """Returns (y [B,H,W], activations (a0, a1, a2, a3))."""
+def forward(params, x0, bf=True, est=None):
+    """Returns (y [B,H,W], activations (a0, a1, a2, a3)).  ``est`` (the
+    unrounded estimate) is added to the output when given."""
     r = bf16 if bf else _id
     p = unflatten(params)
     a0 = x0
@@ -115,14 +117,16 @@ def forward(params, x0, bf=True):
     a2 = r(np.maximum(conv3x3(a1, r(p["W2"]), p["b2"]), 0.0))
     a3 = r(np.maximum(conv3x3(a2, r(p["W3"]), p["b3"]), 0.0))
     y = conv3x3(a3, r(p["W4"]), p["b4"])[..., 0]
+    if est is not None:
+        y = y + np.asarray(est, dtype=np.float64)
     return y, (a0, a1, a2, a3)
 
 
-def loss_and_grad(params, x0, target, bf=True):
+def loss_and_grad(params, x0, target, bf=True, est=None):
     """Mean squared error over all pixels and its gradient (flat, float64)."""
     r = bf16 if bf else _id
     p = unflatten(params)
-    y, (a0, a1, a2, a3) = forward(params, x0, bf)
+    y, (a0, a1, a2, a3) = forward(params, x0, bf, est)
     n = y.size
     loss = float(np.mean((y - target) ** 2))
     g4 = r(2.0 * (y - target) / n)[..., None]                    # dL/dy

@@ -1,0 +1,773 @@
+// Learned surrogate for gfx950: a 4-layer 3x3 CNN (33 -> 32 -> 32 -> 32 -> 1,
+// ReLU between) that maps a 32-frame spike window plus the plain
+// short-window estimate to the long-window reconstruction.  The output is
+// residual on the estimate: y = est + CNN(window, est).
+//
+//   sur_input     per pixel: the 32-frame window as a bit word (a wave
+//                 loads 32 frame rows of 64 pixels and transposes them),
+//                 the plain estimate on that window (FSR on the window as a
+//                 stream of its own, Eq. 6; fixed-window rate below two
+//                 spikes) and whether FSR keeps the window as one segment.
+//   conv (MFMA)   implicit GEMM per 16-pixel row tile: M = 16 pixels,
+//                 N = 16 output channels per v_mfma_f32_16x16x32_bf16,
+//                 K = 32 input channels of one tap per step, 9 taps (plus a
+//                 step for the estimate channel in layer 1).  The weights of
+//                 a layer are packed once into the B-operand lane layout and
+//                 kept in registers by every wave; activations are bfloat16
+//                 NHWC, accumulation float32; the epilogue adds the bias,
+//                 applies ReLU (forward) or the ReLU mask (backward) and
+//                 writes 16-byte rows through LDS.  The input gradient of a
+//                 layer is the same GEMM with the taps mirrored and the
+//                 channel roles swapped.
+//   wgrad         per 16x16 pixel block, each thread accumulates its share
+//                 of dW in float32 from LDS tiles; blocks write partial sums
+//                 that a second kernel adds in a fixed order (deterministic).
+//   loss, adam, mux  elementwise.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "spk.h"
+#include "spk_internal.h"
+
+namespace spk {
+namespace sur {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int C = 32;
+constexpr int kBig = 1 << 29;
+
+// Parameter blob offsets (floats): W1 [32][9][33], b1, W2 [32][9][32], b2,
+// W3 [32][9][32], b3, W4 [1][9][32], b4.
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + 32 * 9 * 33;
+constexpr int OFF_W2 = OFF_B1 + 32;
+constexpr int OFF_B2 = OFF_W2 + 32 * 9 * 32;
+constexpr int OFF_W3 = OFF_B2 + 32;
+constexpr int OFF_B3 = OFF_W3 + 32 * 9 * 32;
+constexpr int OFF_W4 = OFF_B3 + 32;
+constexpr int OFF_B4 = OFF_W4 + 9 * 32;
+constexpr int NPARAMS = OFF_B4 + 1;
+static_assert(NPARAMS == SPK_SUR_NPARAMS, "parameter layout");
+
+// Packed B operands: [step][nblock][lane][8] bf16.
+enum PackKind { PK_FIRST = 0, PK_MID2, PK_MID3, PK_LAST, PK_DG3, PK_DG2, PK_DG4, PK_COUNT };
+__host__ __device__ constexpr int pack_steps(int k) { return k == PK_FIRST ? 10 : (k == PK_DG4 ? 1 : 9); }
+__host__ __device__ constexpr int pack_nb(int k) { return k == PK_LAST ? 1 : 2; }
+__host__ __device__ constexpr int pack_elems(int k) { return pack_steps(k) * pack_nb(k) * 64 * 8; }
+__host__ __device__ constexpr int pack_offset(int k)
+{
+    int o = 0;
+    for (int i = 0; i < k; i++) o += pack_elems(i);
+    return o;
+}
+constexpr int PACK_TOTAL = pack_offset(PK_COUNT);
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// Value of the packed B operand: step s, block nb, column j (output channel
+// within the block), row k (input channel within the step).
+__device__ float pack_value(const float *P, int kind, int s, int nb, int j, int k)
+{
+    const int co = nb * 16 + j;
+    switch (kind) {
+    case PK_FIRST:  // steps 0..8: tap s, bit channel k; step 9: estimate, tap k
+        if (s < 9) return P[OFF_W1 + (co * 9 + s) * 33 + k];
+        return k < 9 ? P[OFF_W1 + (co * 9 + k) * 33 + 32] : 0.0f;
+    case PK_MID2: return P[OFF_W2 + (co * 9 + s) * 32 + k];
+    case PK_MID3: return P[OFF_W3 + (co * 9 + s) * 32 + k];
+    case PK_LAST: return j == 0 ? P[OFF_W4 + s * 32 + k] : 0.0f;
+    // input gradients: tap mirrored (8 - s), row = output channel of the
+    // forward layer, column = its input channel
+    case PK_DG3: return P[OFF_W3 + (k * 9 + (8 - s)) * 32 + co];
+    case PK_DG2: return P[OFF_W2 + (k * 9 + (8 - s)) * 32 + co];
+    case PK_DG4: return k < 9 ? P[OFF_W4 + (8 - k) * 32 + co] : 0.0f;
+    }
+    return 0.0f;
+}
+
+__global__ void pack_kernel(const float *params, __bf16 *packed)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= PACK_TOTAL) return;
+    int kind = 0;
+    while (kind + 1 < PK_COUNT && idx >= pack_offset(kind + 1)) kind++;
+    int r = idx - pack_offset(kind);
+    const int e = r % 8;
+    r /= 8;
+    const int lane = r % 64;
+    r /= 64;
+    const int nb = r % pack_nb(kind);
+    const int s = r / pack_nb(kind);
+    const int j = lane % 16, k = (lane / 16) * 8 + e;
+    packed[idx] = to_bf16(pack_value(params, kind, s, nb, j, k));
+}
+
+// ---------------------------------------------------------------------------
+// input: window bits, short-window estimate, stability flag (+ target crop)
+
+struct SampleTab {
+    spk_sur_sample s[SPK_SUR_MAX_SAMPLES];
+};
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m)
+{
+    const int lo = __shfl_xor((int)(uint32_t)v, m, 64);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+// 64x64 bit transpose across the wave (lane j row j -> lane i column i).
+__device__ __forceinline__ uint64_t transpose64(uint64_t a, int lane)
+{
+    constexpr uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
+                                   0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
+                                   0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        const int s = 32 >> i;
+        const uint64_t y = shfl_xor64(a, s);
+        const bool up = (lane & s) != 0;
+        const uint64_t sh = up ? (y >> s) : (y << s);
+        const uint64_t keep = up ? ~masks[i] : masks[i];
+        a = (a & keep) | (sh & ~keep);
+    }
+    return a;
+}
+
+// FSR on a 32-frame window (bit j = frame t-31+j) valued at its last frame:
+// the last segment's theta*N/D; fewer than two spikes: theta*K/32.
+__device__ __forceinline__ void window_estimate(uint32_t win, double theta, float &est,
+                                                uint8_t &stable)
+{
+    const int K = __builtin_popcount(win);
+    if (K < 2) {
+        est = (float)(theta * (double)K / 32.0);
+        stable = 0;
+        return;
+    }
+    uint32_t h = win;
+    int last = __builtin_ctz(h);
+    h &= h - 1;
+    int first = last, n = 0, lo = kBig, hi = -kBig, nseg = 1;
+    while (h) {
+        const int pos = __builtin_ctz(h);
+        h &= h - 1;
+        const int x = pos - last;
+        const int nlo = min(lo, x), nhi = max(hi, x);
+        if (nhi - nlo > 1) {  // the interval opens a new segment at `last`
+            first = last;
+            n = 0;
+            lo = hi = x;
+            nseg++;
+        } else {
+            lo = nlo;
+            hi = nhi;
+        }
+        n++;
+        last = pos;
+    }
+    est = (float)(theta * (double)n / (double)(last - first));
+    stable = nseg == 1;
+}
+
+__global__ __launch_bounds__(64) void input_kernel(SampleTab tab, int Hc, int Wc, int xtiles,
+                                                   double theta, uint32_t *win, float *est,
+                                                   uint8_t *stable, float *target)
+{
+    const int lane = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int b = tile / (Hc * xtiles);
+    const int y = (tile / xtiles) % Hc;
+    const int x0 = (tile % xtiles) * 64;
+    const spk_sur_sample &S = tab.s[b];
+    const int64_t fb = (int64_t)(((int64_t)S.H * S.W + 127) / 128) * 16;
+    // frame row of 64 consecutive stream pixels starting at q0 (not aligned)
+    const int64_t q0 = (int64_t)(S.oy + y) * S.W + S.ox + x0;
+    uint64_t row = 0;
+    if (lane < 32) {
+        const uint8_t *frame = S.stream + (int64_t)(S.t - 31 + lane) * fb;
+        const int64_t wi = q0 >> 6;
+        const int sh = (int)(q0 & 63);
+        const uint64_t w0 = *(const uint64_t *)(frame + wi * 8);
+        uint64_t w1 = 0;
+        if (sh && (wi + 1) * 8 < fb) w1 = *(const uint64_t *)(frame + (wi + 1) * 8);
+        row = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;
+    }
+    const uint32_t w = (uint32_t)transpose64(row, lane);
+    const int x = x0 + lane;
+    if (x >= Wc) return;
+    const int64_t o = ((int64_t)b * Hc + y) * Wc + x;
+    float e;
+    uint8_t st;
+    window_estimate(w, theta, e, st);
+    win[o] = w;
+    est[o] = e;
+    stable[o] = st;
+    if (target && S.target) target[o] = S.target[(int64_t)(S.oy + y) * S.W + S.ox + x];
+}
+
+// Streaming window update for a full frame: win = (win >> 1) | bit(t) << 31,
+// then the estimate and flag of the new window.
+__global__ __launch_bounds__(256) void stream_kernel(const uint8_t *frame, int64_t HW,
+                                                     double theta, uint32_t *win, float *est,
+                                                     uint8_t *stable)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= HW) return;
+    const uint32_t bit = (frame[p >> 3] >> (p & 7)) & 1u;
+    const uint32_t w = (win[p] >> 1) | (bit << 31);
+    float e;
+    uint8_t st;
+    window_estimate(w, theta, e, st);
+    win[p] = w;
+    est[p] = e;
+    stable[p] = st;
+}
+
+// ---------------------------------------------------------------------------
+// convolution as implicit GEMM on MFMA
+
+enum ConvKind {
+    CK_FIRST = 0,   // bits + estimate -> 32, ReLU
+    CK_MID,         // 32 -> 32, ReLU
+    CK_LAST,        // 32 -> 1, linear, float32 out
+    CK_DGRAD_MID,   // gradient 32 -> 32 through mirrored taps, ReLU mask
+    CK_DGRAD_LAST,  // gradient 1 -> 32 through mirrored taps, ReLU mask
+};
+
+struct ConvArgs {
+    int B, Hc, Wc;
+    int xtiles, ntiles;
+    const uint32_t *win;    // CK_FIRST
+    const float *scalar;    // CK_FIRST: estimate; CK_DGRAD_LAST: dL/dy
+    const __bf16 *act;      // source activations / gradients (NHWC, 32 ch)
+    const __bf16 *packed;   // this layer's packed B operand
+    const float *bias;      // forward layers
+    const __bf16 *mask;     // dgrad: activations whose ReLU mask applies
+    __bf16 *out;            // NHWC 32 ch
+    float *out_f32;         // CK_LAST
+};
+
+template <int KIND>
+struct ConvShape {
+    static constexpr int steps = KIND == CK_FIRST ? 10 : (KIND == CK_DGRAD_LAST ? 1 : 9);
+    static constexpr int nb = KIND == CK_LAST ? 1 : 2;
+};
+
+// 8 bfloat16 ones/zeros from 8 bits
+__device__ __forceinline__ bf16x8 bits_to_bf16(uint32_t bits)
+{
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; e++) v[e] = ((bits >> e) & 1u) ? (__bf16)1.0f : (__bf16)0.0f;
+    return v;
+}
+
+template <int KIND>
+__device__ __forceinline__ bf16x8 a_operand(const ConvArgs &A, int b, int y, int x, int s, int g)
+{
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
+    if constexpr (KIND == CK_FIRST || KIND == CK_DGRAD_LAST) {
+        const bool scalar_step = KIND == CK_DGRAD_LAST || s == 9;
+        if (scalar_step) {
+            // row k = tap k of the scalar channel (estimate or dL/dy)
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int k = g * 8 + e;
+                if (k < 9) {
+                    const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
+                    if (yy >= 0 && yy < A.Hc && xx >= 0 && xx < A.Wc)
+                        v[e] = (__bf16)A.scalar[((int64_t)b * A.Hc + yy) * A.Wc + xx];
+                }
+            }
+            return v;
+        }
+    }
+    const int yy = y + s / 3 - 1, xx = x + s % 3 - 1;
+    if (yy < 0 || yy >= A.Hc || xx < 0 || xx >= A.Wc) return v;
+    const int64_t pix = ((int64_t)b * A.Hc + yy) * A.Wc + xx;
+    if constexpr (KIND == CK_FIRST) {
+        return bits_to_bf16((A.win[pix] >> (8 * g)) & 0xFFu);
+    } else {
+        return *(const bf16x8 *)(A.act + pix * C + 8 * g);
+    }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
+{
+    using S = ConvShape<KIND>;
+    __shared__ __bf16 stage[4][16 * C];  // one 16-pixel x 32-channel tile per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    // this layer's weights, resident in registers
+    bf16x8 Bop[S::steps][S::nb];
+#pragma unroll
+    for (int s = 0; s < S::steps; s++)
+#pragma unroll
+        for (int n = 0; n < S::nb; n++)
+            Bop[s][n] = *(const bf16x8 *)(A.packed + ((s * S::nb + n) * 64 + lane) * 8);
+    float bias[S::nb];
+#pragma unroll
+    for (int n = 0; n < S::nb; n++) {
+        bias[n] = 0.0f;
+        if constexpr (KIND == CK_FIRST || KIND == CK_MID) bias[n] = A.bias[n * 16 + i];
+        if constexpr (KIND == CK_LAST) bias[n] = A.bias[0];
+    }
+    const int nwaves = gridDim.x * 4;
+    for (int t = blockIdx.x * 4 + wave; t < A.ntiles; t += nwaves) {
+        const int b = t / (A.Hc * A.xtiles);
+        const int y = (t / A.xtiles) % A.Hc;
+        const int x0 = (t % A.xtiles) * 16;
+        f32x4 acc[S::nb];
+#pragma unroll
+        for (int n = 0; n < S::nb; n++) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < S::steps; s++) {
+            const bf16x8 a = a_operand<KIND>(A, b, y, x0 + i, s, g);
+#pragma unroll
+            for (int n = 0; n < S::nb; n++)
+                acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[s][n], acc[n], 0, 0, 0);
+        }
+        // lane holds D[pixel 4g + r][channel 16n + i]
+        if constexpr (KIND == CK_LAST) {
+            // residual on the plain short-window estimate
+            if (i == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int x = x0 + 4 * g + r;
+                    if (x < A.Wc) {
+                        const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+                        A.out_f32[pix] = A.scalar[pix] + (acc[0][r] + bias[0]);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int n = 0; n < S::nb; n++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    float v = acc[n][r] + bias[n];
+                    if constexpr (KIND == CK_FIRST || KIND == CK_MID) v = fmaxf(v, 0.0f);
+                    stage[wave][(4 * g + r) * C + 16 * n + i] = to_bf16(v);
+                }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // each lane writes 8 channels of one pixel: pixel lane/4, part lane%4
+            const int px = lane >> 2, part = lane & 3;
+            const int x = x0 + px;
+            bf16x8 v = *(const bf16x8 *)(&stage[wave][px * C + part * 8]);
+            if (x < A.Wc) {
+                const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+                if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
+                    const bf16x8 m = *(const bf16x8 *)(A.mask + pix * C + part * 8);
+#pragma unroll
+                    for (int e = 0; e < 8; e++)
+                        if (!((float)m[e] > 0.0f)) v[e] = (__bf16)0.0f;
+                }
+                *(bf16x8 *)(A.out + pix * C + part * 8) = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// loss: dL/dy = 2 (y - target) / N, rounded to bfloat16 like every gradient
+// the GEMMs consume; per-block partial sums of the squared error
+
+__global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *tgt, int64_t n,
+                                                   float *dy, float *partial)
+{
+    __shared__ float red[256];
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float sq = 0.0f;
+    if (idx < n) {
+        const float d = y[idx] - tgt[idx];
+        sq = d * d;
+        dy[idx] = (float)to_bf16(2.0f * d / (float)n);
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: dW[co][tap][ci] = sum_p g[p][co] * a[p + off(tap)][ci],
+// db[co] = sum_p g[p][co].  One block per 16x16 pixel tile of one image.
+
+enum WgKind { WG_FIRST = 0, WG_MID, WG_LAST };
+
+template <int K>
+struct WgShape {
+    static constexpr int cout = K == WG_LAST ? 1 : 32;
+    static constexpr int cin = K == WG_FIRST ? 33 : 32;
+    static constexpr int nw = cout * 9 * cin;       // weights
+    static constexpr int np = nw + cout;            // + biases
+};
+
+struct WgArgs {
+    int B, Hc, Wc, tx, ty;       // tiles per row / column
+    const __bf16 *g;             // NHWC 32 ch gradients (WG_FIRST, WG_MID)
+    const float *gy;             // dL/dy (WG_LAST)
+    const __bf16 *a;             // NHWC 32 ch activations (WG_MID, WG_LAST)
+    const uint32_t *win;         // WG_FIRST
+    const float *est;            // WG_FIRST
+    float *partial;              // [nblocks][np]
+};
+
+template <int K>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
+{
+    using S = WgShape<K>;
+    // bfloat16 tiles (the values are bfloat16 already): gradients of the
+    // 256 pixels, activations of the 18 x 18 pixels around them
+    __shared__ __bf16 gs[256][S::cout == 1 ? 1 : 34];
+    __shared__ __bf16 as[18 * 18][S::cin + 1];
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int b = blk / (A.tx * A.ty);
+    const int ty0 = ((blk / A.tx) % A.ty) * 16, tx0 = (blk % A.tx) * 16;
+    // gradient tile
+    for (int idx = tid; idx < 256 * S::cout; idx += 256) {
+        const int px = idx / S::cout, c = idx % S::cout;
+        const int y = ty0 + px / 16, x = tx0 + px % 16;
+        float v = 0.0f;
+        if (y < A.Hc && x < A.Wc) {
+            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+            if constexpr (K == WG_LAST) v = A.gy[pix];
+            else v = (float)A.g[pix * C + c];
+        }
+        gs[px][c] = to_bf16(v);
+    }
+    // activation tile, rows ty0-1 .. ty0+16, columns tx0-1 .. tx0+16
+    for (int idx = tid; idx < 18 * 18 * S::cin; idx += 256) {
+        const int q = idx / S::cin, c = idx % S::cin;
+        const int y = ty0 - 1 + q / 18, x = tx0 - 1 + q % 18;
+        float v = 0.0f;
+        if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc) {
+            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+            if constexpr (K == WG_FIRST) {
+                v = c < 32 ? (float)((A.win[pix] >> c) & 1u) : (float)to_bf16(A.est[pix]);
+            } else {
+                v = (float)A.a[pix * C + c];
+            }
+        }
+        as[q][c] = to_bf16(v);
+    }
+    __syncthreads();
+    float *out = A.partial + (int64_t)blk * S::np;
+    // each thread owns weights w = tid, tid + 256, ... (fixed summation order)
+    for (int w = tid; w < S::np; w += 256) {
+        float acc = 0.0f;
+        if (w < S::nw) {
+            const int co = w / (9 * S::cin), tap = (w / S::cin) % 9, ci = w % S::cin;
+            const int dy = tap / 3, dx = tap % 3;
+            for (int px = 0; px < 256; px++) {
+                const int q = (px / 16 + dy) * 18 + (px % 16 + dx);
+                acc += (float)gs[px][co] * (float)as[q][ci];
+            }
+        } else {
+            const int co = w - S::nw;
+            for (int px = 0; px < 256; px++) acc += (float)gs[px][co];
+        }
+        out[w] = acc;
+    }
+}
+
+// dst[j] = sum over blocks of partial[blk][j], blocks in order
+__global__ void reduce_kernel(const float *partial, int nblocks, int np, float *dst)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    float acc = 0.0f;
+    for (int k = 0; k < nblocks; k++) acc += partial[(int64_t)k * np + j];
+    dst[j] = acc;
+}
+
+// The weight-gradient kernels produce dW[co][tap][ci] and db[co] per layer,
+// already in the parameter blob's order: W block followed by its bias.
+
+// ---------------------------------------------------------------------------
+
+__global__ void adam_kernel(float *p, float *m, float *v, const float *g, int n, float lr,
+                            float b1, float b2, float eps, float c1, float c2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.0f - b1) * gj;
+    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    p[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
+
+__global__ void mux_kernel(const float *y, const float *est, const uint8_t *stable, int64_t n,
+                           float *out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) out[j] = stable[j] ? y[j] : est[j];
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+
+struct Workspace {
+    __bf16 *packed;
+    __bf16 *a1, *a2, *a3;   // activations after ReLU
+    __bf16 *g1, *g2;        // gradient ping-pong (NHWC 32 ch)
+    float *dy;
+    float *partial;
+    float *loss_partial;
+};
+
+__host__ __device__ inline int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+inline int wg_blocks(int B, int Hc, int Wc) { return B * ((Hc + 15) / 16) * ((Wc + 15) / 16); }
+
+inline int64_t workspace_bytes(int B, int Hc, int Wc)
+{
+    const int64_t P = (int64_t)B * Hc * Wc;
+    int64_t s = align256((int64_t)PACK_TOTAL * 2);
+    s += 5 * align256(P * C * 2);
+    s += align256(P * 4);
+    s += align256((int64_t)wg_blocks(B, Hc, Wc) * WgShape<WG_FIRST>::np * 4);
+    s += align256(((P + 255) / 256) * 4);
+    return s;
+}
+
+inline Workspace carve(void *ws, int B, int Hc, int Wc)
+{
+    const int64_t P = (int64_t)B * Hc * Wc;
+    char *c = (char *)ws;
+    Workspace w;
+    w.packed = (__bf16 *)c;
+    c += align256((int64_t)PACK_TOTAL * 2);
+    __bf16 **acts[5] = {&w.a1, &w.a2, &w.a3, &w.g1, &w.g2};
+    for (auto a : acts) {
+        *a = (__bf16 *)c;
+        c += align256(P * C * 2);
+    }
+    w.dy = (float *)c;
+    c += align256(P * 4);
+    w.partial = (float *)c;
+    c += align256((int64_t)wg_blocks(B, Hc, Wc) * WgShape<WG_FIRST>::np * 4);
+    w.loss_partial = (float *)c;
+    return w;
+}
+
+ConvArgs conv_args(int B, int Hc, int Wc)
+{
+    ConvArgs a{};
+    a.B = B;
+    a.Hc = Hc;
+    a.Wc = Wc;
+    a.xtiles = (Wc + 15) / 16;
+    a.ntiles = B * Hc * a.xtiles;
+    return a;
+}
+
+template <int KIND>
+void launch_conv(const ConvArgs &a, hipStream_t st)
+{
+    const int blocks = (a.ntiles + 3) / 4 < 2048 ? (a.ntiles + 3) / 4 : 2048;
+    hipLaunchKernelGGL(conv_kernel<KIND>, dim3(blocks), dim3(256), 0, st, a);
+}
+
+template <int K>
+void launch_wgrad(WgArgs a, float *dst, hipStream_t st)
+{
+    const int nblk = a.B * a.tx * a.ty;
+    hipLaunchKernelGGL(wgrad_kernel<K>, dim3(nblk), dim3(256), 0, st, a);
+    const int np = WgShape<K>::np;
+    hipLaunchKernelGGL(reduce_kernel, dim3((np + 255) / 256), dim3(256), 0, st, a.partial, nblk,
+                       np, dst);
+}
+
+void forward_all(const float *params, const uint32_t *win, const float *est, int B, int Hc,
+                 int Wc, float *y, const Workspace &w, hipStream_t st)
+{
+    hipLaunchKernelGGL(pack_kernel, dim3((PACK_TOTAL + 255) / 256), dim3(256), 0, st, params,
+                       w.packed);
+    ConvArgs a = conv_args(B, Hc, Wc);
+    a.win = win;
+    a.scalar = est;
+    a.packed = w.packed + pack_offset(PK_FIRST);
+    a.bias = params + OFF_B1;
+    a.out = w.a1;
+    launch_conv<CK_FIRST>(a, st);
+    a.act = w.a1;
+    a.packed = w.packed + pack_offset(PK_MID2);
+    a.bias = params + OFF_B2;
+    a.out = w.a2;
+    launch_conv<CK_MID>(a, st);
+    a.act = w.a2;
+    a.packed = w.packed + pack_offset(PK_MID3);
+    a.bias = params + OFF_B3;
+    a.out = w.a3;
+    launch_conv<CK_MID>(a, st);
+    a.act = w.a3;
+    a.scalar = est;
+    a.packed = w.packed + pack_offset(PK_LAST);
+    a.bias = params + OFF_B4;
+    a.out = nullptr;
+    a.out_f32 = y;
+    launch_conv<CK_LAST>(a, st);
+}
+
+}  // namespace
+}  // namespace sur
+}  // namespace spk
+
+using namespace spk::sur;
+
+extern "C" {
+
+size_t spk_sur_workspace_bytes(int32_t B, int32_t Hc, int32_t Wc)
+{
+    if (B <= 0 || Hc <= 0 || Wc <= 0) return 0;
+    return (size_t)workspace_bytes(B, Hc, Wc);
+}
+
+static int check_batch(int32_t B, int32_t Hc, int32_t Wc)
+{
+    if (B <= 0 || Hc <= 0 || Wc <= 0) return SPK_EINVAL;
+    if ((int64_t)B * Hc * Wc > ((int64_t)1 << 31) / C) return SPK_EINVAL;
+    return SPK_OK;
+}
+
+int spk_sur_input(const spk_sur_sample *samples, int32_t B, int32_t Hc, int32_t Wc, float theta,
+                  uint32_t *win, float *est, uint8_t *stable, float *target, void *hip_stream)
+{
+    if (!samples || !win || !est || !stable || B > SPK_SUR_MAX_SAMPLES) return SPK_EINVAL;
+    if (check_batch(B, Hc, Wc) || !std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
+    SampleTab tab{};
+    for (int b = 0; b < B; b++) {
+        const spk_sur_sample &S = samples[b];
+        if (!S.stream || S.H <= 0 || S.W <= 0 || S.T < 32 || S.t < 31 || S.t >= S.T ||
+            S.oy < 0 || S.ox < 0 || S.oy + Hc > S.H || S.ox + Wc > S.W)
+            return SPK_EINVAL;
+        if ((int64_t)S.H * S.W > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
+        if (target && !S.target) return SPK_EINVAL;
+        tab.s[b] = S;
+    }
+    const int xtiles = (Wc + 63) / 64;
+    hipLaunchKernelGGL(input_kernel, dim3(B * Hc * xtiles), dim3(64), 0, (hipStream_t)hip_stream,
+                       tab, Hc, Wc, xtiles, (double)theta, win, est, stable, target);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_stream_step(const uint8_t *frame, int32_t H, int32_t W, float theta, uint32_t *win,
+                        float *est, uint8_t *stable, void *hip_stream)
+{
+    if (!frame || !win || !est || !stable || H <= 0 || W <= 0) return SPK_EINVAL;
+    if (!std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
+    const int64_t HW = (int64_t)H * W;
+    if (HW > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
+    hipLaunchKernelGGL(stream_kernel, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)hip_stream, frame, HW, (double)theta, win, est, stable);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_forward(const float *params, const uint32_t *win, const float *est, int32_t B,
+                    int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream)
+{
+    if (!params || !win || !est || !y || !workspace || check_batch(B, Hc, Wc)) return SPK_EINVAL;
+    const Workspace w = carve(workspace, B, Hc, Wc);
+    forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_backward(const float *params, const uint32_t *win, const float *est, int32_t B,
+                     int32_t Hc, int32_t Wc, const float *y, const float *target, float *grad,
+                     float *loss_partial_out, void *workspace, void *hip_stream)
+{
+    if (!params || !win || !est || !y || !target || !grad || !workspace ||
+        check_batch(B, Hc, Wc))
+        return SPK_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Workspace w = carve(workspace, B, Hc, Wc);
+    const int64_t P = (int64_t)B * Hc * Wc;
+    const int lblocks = (int)((P + 255) / 256);
+    hipLaunchKernelGGL(loss_kernel, dim3(lblocks), dim3(256), 0, st, y, target, P, w.dy,
+                       loss_partial_out ? loss_partial_out : w.loss_partial);
+    ConvArgs a = conv_args(B, Hc, Wc);
+    // layer 4: weights from dL/dy and a3; gradient into a3's pre-activation
+    WgArgs g{};
+    g.B = B;
+    g.Hc = Hc;
+    g.Wc = Wc;
+    g.tx = (Wc + 15) / 16;
+    g.ty = (Hc + 15) / 16;
+    g.partial = w.partial;
+    g.gy = w.dy;
+    g.a = w.a3;
+    launch_wgrad<WG_LAST>(g, grad + OFF_W4, st);
+    a.scalar = w.dy;
+    a.packed = w.packed + pack_offset(PK_DG4);
+    a.mask = w.a3;
+    a.out = w.g1;
+    launch_conv<CK_DGRAD_LAST>(a, st);
+    // layer 3
+    g.g = w.g1;
+    g.a = w.a2;
+    launch_wgrad<WG_MID>(g, grad + OFF_W3, st);
+    a.act = w.g1;
+    a.packed = w.packed + pack_offset(PK_DG3);
+    a.mask = w.a2;
+    a.out = w.g2;
+    launch_conv<CK_DGRAD_MID>(a, st);
+    // layer 2
+    g.g = w.g2;
+    g.a = w.a1;
+    launch_wgrad<WG_MID>(g, grad + OFF_W2, st);
+    a.act = w.g2;
+    a.packed = w.packed + pack_offset(PK_DG2);
+    a.mask = w.a1;
+    a.out = w.g1;
+    launch_conv<CK_DGRAD_MID>(a, st);
+    // layer 1
+    g.g = w.g1;
+    g.win = win;
+    g.est = est;
+    launch_wgrad<WG_FIRST>(g, grad + OFF_W1, st);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void *hip_stream)
+{
+    if (!params || !m || !v || !grad || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f) ||
+        !(beta1 < 1.0f) || !(beta2 >= 0.0f) || !(beta2 < 1.0f) || !(eps > 0.0f))
+        return SPK_EINVAL;
+    const float c1 = 1.0f - std::pow(beta1, (float)step), c2 = 1.0f - std::pow(beta2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((NPARAMS + 255) / 256), dim3(256), 0,
+                       (hipStream_t)hip_stream, params, m, v, grad, NPARAMS, lr, beta1, beta2, eps,
+                       c1, c2);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_mux(const float *y, const float *est, const uint8_t *stable, int64_t n, float *out,
+                void *hip_stream)
+{
+    if (!y || !est || !stable || !out || n < 0) return SPK_EINVAL;
+    if (n == 0) return SPK_OK;
+    hipLaunchKernelGGL(mux_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)hip_stream, y, est, stable, n, out);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+"""Learned surrogate: binding of the spk_sur_* entry points and its trainer.
+
+A small CNN (four 3x3 convolutions, 33 -> 32 -> 32 -> 32 -> 1, ReLU between,
+output added to the estimate) maps a 32-frame spike window plus the plain
+short-window estimate to the intensity the plain method only reaches over a
+long stable window.  Every
+step (window extraction, the estimate, convolutions, gradients, loss, Adam,
+fallback) runs in the library's kernels; this module marshals arguments,
+owns the parameter and workspace tensors and drives the training loop.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from . import _stream_handle, _check_stream_tensor, reconstruct, FSR
+
+NPARAMS = 28321
+MAX_SAMPLES = 64
+SHAPES = [("W1", (32, 9, 33)), ("b1", (32,)), ("W2", (32, 9, 32)), ("b2", (32,)),
+          ("W3", (32, 9, 32)), ("b3", (32,)), ("W4", (1, 9, 32)), ("b4", (1,))]
+
+
+class SurSample(ctypes.Structure):
+    """Mirror of ``spk_sur_sample`` in include/spk.h."""
+    _fields_ = [("stream", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("T", ctypes.c_int32), ("oy", ctypes.c_int32), ("ox", ctypes.c_int32),
+                ("t", ctypes.c_int32), ("target", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_lib.EXTRA_DECLS.update({
+    "spk_sur_input": [ctypes.POINTER(SurSample), _i32, _i32, _i32, ctypes.c_float, _P, _P, _P,
+                      _P, _P],
+    "spk_sur_stream_step": [_P, _i32, _i32, ctypes.c_float, _P, _P, _P, _P],
+    "spk_sur_forward": [_P, _P, _P, _i32, _i32, _i32, _P, _P, _P],
+    "spk_sur_backward": [_P, _P, _P, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P],
+    "spk_sur_adam": [_P, _P, _P, _P, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                     ctypes.c_float, _P],
+    "spk_sur_mux": [_P, _P, _P, ctypes.c_int64, _P, _P],
+})
+
+
+def _lib_sur():
+    lib = _lib.load()
+    if not getattr(lib, "_sur_declared", False):
+        lib.spk_sur_workspace_bytes.restype = ctypes.c_size_t
+        lib.spk_sur_workspace_bytes.argtypes = [_i32, _i32, _i32]
+        for name, argtypes in _lib.EXTRA_DECLS.items():
+            if name.startswith("spk_sur_"):
+                f = getattr(lib, name)
+                f.restype = ctypes.c_int
+                f.argtypes = argtypes
+        lib._sur_declared = True
+    return lib
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal hidden weights, zero biases, zero output layer: the network
+    starts as the identity on the plain estimate (y = est)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in SHAPES:
+        if name.startswith("W") and name != "W4":
+            fan_in = shape[1] * shape[2]
+            parts.append(rng.normal(0.0, math.sqrt(2.0 / fan_in), size=shape).reshape(-1))
+        else:
+            parts.append(np.zeros(int(np.prod(shape))))
+    p = np.concatenate(parts)
+    assert p.shape == (NPARAMS,)
+    return p
+
+
+class Surrogate:
+    """Parameters (float32, device), Adam moments and per-shape workspaces."""
+
+    def __init__(self, params=None, device="cuda", seed: int = 0):
+        if params is None:
+            params = init_params(seed)
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32)).to(device).contiguous()
+        assert self.params.numel() == NPARAMS
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step_count = 0
+        self.device = device
+        self._ws = {}
+
+    def workspace(self, B, Hc, Wc):
+        key = (B, Hc, Wc)
+        if key not in self._ws:
+            n = int(_lib_sur().spk_sur_workspace_bytes(B, Hc, Wc))
+            self._ws[key] = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    # -- inputs ---------------------------------------------------------------
+    @staticmethod
+    def input(samples, Hc, Wc, theta=1.0, with_target=False, stream=None):
+        """samples: list of dicts (stream tensor, H, W, T, oy, ox, t[, target
+        tensor]).  Returns (win uint32 as int32, est float32, stable uint8
+        [, target float32]), each [B, Hc, Wc]."""
+        B = len(samples)
+        assert 0 < B <= MAX_SAMPLES
+        dev = samples[0]["stream"].device
+        arr = (SurSample * B)()
+        for i, s in enumerate(samples):
+            _check_stream_tensor(s["stream"], s["H"], s["W"], s["T"])
+            tgt = s.get("target")
+            arr[i] = SurSample(s["stream"].data_ptr(), s["H"], s["W"], s["T"], s["oy"], s["ox"],
+                               s["t"], tgt.data_ptr() if tgt is not None else None)
+        win = torch.empty((B, Hc, Wc), dtype=torch.int32, device=dev)
+        est = torch.empty((B, Hc, Wc), dtype=torch.float32, device=dev)
+        st = torch.empty((B, Hc, Wc), dtype=torch.uint8, device=dev)
+        tg = torch.empty((B, Hc, Wc), dtype=torch.float32, device=dev) if with_target else None
+        rc = _lib_sur().spk_sur_input(arr, B, Hc, Wc, float(theta), win.data_ptr(),
+                                      est.data_ptr(), st.data_ptr(),
+                                      tg.data_ptr() if tg is not None else None,
+                                      _stream_handle(stream))
+        _lib.check("spk_sur_input", rc)
+        return (win, est, st, tg) if with_target else (win, est, st)
+
+    @staticmethod
+    def stream_step(frame, H, W, theta, win, est, stable, stream=None):
+        """Advance full-frame windows by one packed frame (device uint8)."""
+        rc = _lib_sur().spk_sur_stream_step(frame.data_ptr(), H, W, float(theta), win.data_ptr(),
+                                            est.data_ptr(), stable.data_ptr(),
+                                            _stream_handle(stream))
+        _lib.check("spk_sur_stream_step", rc)
+
+    # -- network --------------------------------------------------------------
+    def forward(self, win, est, out=None, stream=None):
+        B, Hc, Wc = win.shape
+        y = out if out is not None else torch.empty((B, Hc, Wc), dtype=torch.float32,
+                                                    device=win.device)
+        rc = _lib_sur().spk_sur_forward(self.params.data_ptr(), win.data_ptr(), est.data_ptr(),
+                                        B, Hc, Wc, y.data_ptr(),
+                                        self.workspace(B, Hc, Wc).data_ptr(),
+                                        _stream_handle(stream))
+        _lib.check("spk_sur_forward", rc)
+        return y
+
+    def backward(self, win, est, y, target, stream=None):
+        """Gradient of the MSE into self.grad; returns the loss partial sums
+        tensor (sum / N is the loss)."""
+        B, Hc, Wc = win.shape
+        nblk = (B * Hc * Wc + 255) // 256
+        lp = torch.empty(nblk, dtype=torch.float32, device=win.device)
+        rc = _lib_sur().spk_sur_backward(self.params.data_ptr(), win.data_ptr(), est.data_ptr(),
+                                         B, Hc, Wc, y.data_ptr(), target.data_ptr(),
+                                         self.grad.data_ptr(), lp.data_ptr(),
+                                         self.workspace(B, Hc, Wc).data_ptr(),
+                                         _stream_handle(stream))
+        _lib.check("spk_sur_backward", rc)
+        return lp
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step_count += 1
+        rc = _lib_sur().spk_sur_adam(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                     self.grad.data_ptr(), self.step_count, lr, beta1, beta2, eps,
+                                     _stream_handle(stream))
+        _lib.check("spk_sur_adam", rc)
+
+    @staticmethod
+    def mux(y, est, stable, out=None, stream=None):
+        out = out if out is not None else torch.empty_like(y)
+        rc = _lib_sur().spk_sur_mux(y.data_ptr(), est.data_ptr(), stable.data_ptr(), y.numel(),
+                                    out.data_ptr(), _stream_handle(stream))
+        _lib.check("spk_sur_mux", rc)
+        return out
+
+    def train_step(self, win, est, target, lr=1e-3):
+        y = self.forward(win, est)
+        lp = self.backward(win, est, y, target)
+        self.adam(lr=lr)
+        return lp
+
+    def state(self):
+        return {"params": self.params.cpu().numpy().copy(), "m": self.m.cpu().numpy().copy(),
+                "v": self.v.cpu().numpy().copy(), "step": self.step_count}
+
+
+# ---------------------------------------------------------------------------
+# training data: seeded static block scenes, targets from the plain method
+
+class SceneSet:
+    """Block scenes resident on the device with long-window plain targets
+    (FSR over the whole stream) at a few times per scene."""
+
+    def __init__(self, seeds, H=250, W=400, T=4096, target_times=(31, 1055, 2079, 3103, 4095),
+                 theta=1.0, device="cuda", nthreads=None):
+        import spkgen
+        self.H, self.W, self.T, self.theta = H, W, T, theta
+        self.seeds = list(seeds)
+        self.target_times = list(target_times)
+        self.streams, self.targets, self.host = [], [], []
+        for sd in self.seeds:
+            s = spkgen.blocks(H, W, T, sd, nthreads=nthreads)
+            ds = torch.from_numpy(s).to(device)
+            self.streams.append(ds)
+            self.targets.append(reconstruct(ds, H, W, T, theta, self.target_times, order=FSR))
+            self.host.append(s)
+
+    def samples(self, rng, B, Hc, Wc):
+        out = []
+        for _ in range(B):
+            i = int(rng.integers(len(self.seeds)))
+            k = int(rng.integers(len(self.target_times)))
+            out.append(dict(stream=self.streams[i], H=self.H, W=self.W, T=self.T,
+                            oy=int(rng.integers(0, self.H - Hc + 1)),
+                            ox=int(rng.integers(0, self.W - Wc + 1)),
+                            t=self.target_times[k], target=self.targets[i][k]))
+        return out
+
+
+def train(model: Surrogate, scenes: SceneSet, steps: int, B: int = 16, Hc: int = 64,
+          Wc: int = 64, lr: float = 2e-3, seed: int = 0, log_every: int = 0):
+    """Adam on random crops; returns the per-step losses (host floats)."""
+    rng = np.random.default_rng(seed)
+    losses = []
+    n = B * Hc * Wc
+    parts = []
+    for step in range(steps):
+        # cosine decay of the learning rate
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(1, steps)))
+        win, est, st, tgt = Surrogate.input(scenes.samples(rng, B, Hc, Wc), Hc, Wc,
+                                            scenes.theta, with_target=True)
+        parts.append(model.train_step(win, est, tgt, lr=lr_t))
+        if log_every and (step + 1) % log_every == 0:
+            l = float(torch.stack([p.sum() for p in parts]).cpu().sum()) / (n * len(parts))
+            print("step %d loss %.6g" % (step + 1, l), flush=True)
+            losses.append(l)
+            parts = []
+    if parts:
+        losses.append(float(torch.stack([p.sum() for p in parts]).cpu().sum())
+                      / (n * len(parts)))
+    return losses

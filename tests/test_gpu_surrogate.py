@@ -1,0 +1,172 @@
+"""Surrogate kernels against the CPU reference (oracle/conv.py, oracle window
+estimate).
+
+Window bits, the short-window estimate (float32 rounding of the oracle's
+double) and the stability flag must match exactly.  Network outputs and
+gradients: both sides use the same bfloat16-rounded weights, inputs,
+activations and gradients; they differ by float32 versus float64
+accumulation and, rarely, by one bfloat16 step where a float32 sum lands on
+the other side of a rounding boundary than its float64 value.  The bounds
+below allow a few such steps (bfloat16 has 8 significant bits, 2^-8 = 0.4%).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.conv as oc
+import spkgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sur():
+    import paper_2412_11639_amd.surrogate as m
+    assert torch.cuda.is_available(), "no GPU"
+    return m
+
+
+def _samples(streams, rng, B, Hc, Wc, T):
+    out = []
+    for b in range(B):
+        s, H, W = streams[b % len(streams)]
+        out.append(dict(stream=s, H=H, W=W, T=T, oy=int(rng.integers(0, H - Hc + 1)),
+                        ox=int(rng.integers(0, W - Wc + 1)), t=int(rng.integers(31, T))))
+    return out
+
+
+def test_input_matches_oracle(sur):
+    rng = np.random.default_rng(0)
+    T = 300
+    g = spkgen.gratings(40, 100, T, seed=51)
+    k = spkgen.blocks(33, 70, T, seed=52, vx=0.4)
+    streams = [(torch.from_numpy(g).cuda(), 40, 100), (torch.from_numpy(k).cuda(), 33, 70)]
+    hosts = [g, k]
+    Hc, Wc = 13, 29          # not multiples of anything, unaligned crops
+    samples = _samples(streams, rng, 8, Hc, Wc, T)
+    win, est, st = sur.Surrogate.input(samples, Hc, Wc, theta=2.0)
+    win, est, st = win.cpu().numpy().view(np.uint32), est.cpu().numpy(), st.cpu().numpy()
+    for b, s in enumerate(samples):
+        host = hosts[b % 2]
+        H, W = s["H"], s["W"]
+        bits = spkgen.unpack(host[s["t"] - 31:s["t"] + 1], H, W).astype(np.uint64)
+        ref_win = sum(bits[j] << np.uint64(j) for j in range(32)).astype(np.uint32)
+        crop = (slice(s["oy"], s["oy"] + Hc), slice(s["ox"], s["ox"] + Wc))
+        np.testing.assert_array_equal(win[b], ref_win[crop])
+        e, stab = oracle.window_estimate(host, H, W, T, 2.0, s["t"])
+        np.testing.assert_array_equal(est[b], e[crop].astype(np.float32))
+        np.testing.assert_array_equal(st[b].astype(bool), stab[crop])
+
+
+def test_stream_step_matches_input(sur):
+    H, W, T = 24, 50, 120
+    s = spkgen.gratings(H, W, T, seed=53)
+    ds = torch.from_numpy(s).cuda()
+    fb = spkgen.frame_bytes(H, W)
+    win = torch.zeros((H, W), dtype=torch.int32, device="cuda")
+    est = torch.zeros((H, W), dtype=torch.float32, device="cuda")
+    st = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    for t in range(T):
+        sur.Surrogate.stream_step(ds[t], H, W, 1.0, win, est, st)
+        if t >= 31 and t % 17 == 0:
+            w2, e2, s2 = sur.Surrogate.input([dict(stream=ds, H=H, W=W, T=T, oy=0, ox=0, t=t)],
+                                             H, W, 1.0)
+            assert torch.equal(win, w2[0]) and torch.equal(est, e2[0]) and torch.equal(st, s2[0])
+
+
+def _rand_batch(rng, B, Hc, Wc):
+    win = rng.integers(0, 1 << 32, size=(B, Hc, Wc), dtype=np.uint64).astype(np.uint32)
+    # sparser windows, like real ones
+    win &= rng.integers(0, 1 << 32, size=(B, Hc, Wc), dtype=np.uint64).astype(np.uint32)
+    est = rng.uniform(0, 1, size=(B, Hc, Wc)).astype(np.float32)
+    return win, est
+
+
+def _to_dev(win, est):
+    return (torch.from_numpy(win.view(np.int32).copy()).cuda(), torch.from_numpy(est).cuda())
+
+
+@pytest.mark.parametrize("shape", [(2, 16, 16), (3, 19, 37), (1, 64, 80)])
+def test_forward_matches_reference(sur, shape):
+    rng = np.random.default_rng(1)
+    B, Hc, Wc = shape
+    params = sur.init_params(2) + rng.normal(0, 0.05, sur.NPARAMS)
+    model = sur.Surrogate(params)
+    win, est = _rand_batch(rng, B, Hc, Wc)
+    y = model.forward(*_to_dev(win, est)).cpu().numpy().astype(np.float64)
+    ref, _ = oc.forward(model.params.cpu().numpy().astype(np.float64),
+                        oc.make_input(win, est.astype(np.float64), bf=True), bf=True,
+                        est=est.astype(np.float64))
+    scale = np.abs(ref).max()
+    err = np.abs(y - ref)
+    assert err.max() <= 2e-2 * scale, err.max()
+    assert err.mean() <= 1e-3 * scale, err.mean()
+
+
+@pytest.mark.parametrize("shape", [(2, 16, 16), (2, 21, 35)])
+def test_backward_matches_reference(sur, shape):
+    rng = np.random.default_rng(3)
+    B, Hc, Wc = shape
+    params = sur.init_params(4) + rng.normal(0, 0.05, sur.NPARAMS)
+    model = sur.Surrogate(params)
+    win, est = _rand_batch(rng, B, Hc, Wc)
+    target = rng.uniform(0, 1, size=(B, Hc, Wc)).astype(np.float32)
+    dwin, dest = _to_dev(win, est)
+    y = model.forward(dwin, dest)
+    lp = model.backward(dwin, dest, y, torch.from_numpy(target).cuda())
+    g = model.grad.cpu().numpy().astype(np.float64)
+    loss_ref, g_ref, _ = oc.loss_and_grad(model.params.cpu().numpy().astype(np.float64),
+                                          oc.make_input(win, est.astype(np.float64), bf=True),
+                                          target.astype(np.float64), bf=True,
+                                          est=est.astype(np.float64))
+    loss = float(lp.sum().cpu()) / target.size
+    assert abs(loss - loss_ref) <= 1e-3 * loss_ref
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in oc.SHAPES])
+    for (name, _), a, b in zip(oc.SHAPES, offs[:-1], offs[1:]):
+        d = np.linalg.norm(g[a:b] - g_ref[a:b]) / max(np.linalg.norm(g_ref[a:b]), 1e-30)
+        assert d <= 2e-2, (name, d)
+
+
+def test_adam_matches_reference(sur):
+    rng = np.random.default_rng(5)
+    p0 = rng.normal(0, 0.1, sur.NPARAMS)
+    model = sur.Surrogate(p0)
+    p, m, v = model.params.cpu().numpy().astype(np.float64), np.zeros(sur.NPARAMS), np.zeros(sur.NPARAMS)
+    for step in range(1, 4):
+        gr = rng.normal(0, 1e-2, sur.NPARAMS).astype(np.float32)
+        model.grad.copy_(torch.from_numpy(gr))
+        model.adam(lr=1e-3)
+        p, m, v = oc.adam(p, m, v, gr.astype(np.float64), step, 1e-3)
+    np.testing.assert_allclose(model.params.cpu().numpy(), p, rtol=0, atol=1e-6)
+
+
+def test_mux(sur):
+    y = torch.rand(1000, device="cuda")
+    e = torch.rand(1000, device="cuda")
+    s = (torch.rand(1000, device="cuda") > 0.5).to(torch.uint8)
+    out = sur.Surrogate.mux(y, e, s)
+    assert torch.equal(out, torch.where(s.bool(), y, e))
+
+
+def test_training_reduces_loss_and_beats_short_window(sur):
+    """A short training run on block scenes lowers the loss, and on held-out
+    scenes the network's output is closer to the long-window plain result
+    than the plain short-window estimate is."""
+    scenes = sur.SceneSet([10000 + i for i in range(6)], H=96, W=128, T=1024,
+                          target_times=(31, 500, 1023))
+    held = sur.SceneSet([20000, 20001], H=96, W=128, T=1024, target_times=(31, 500, 1023))
+    model = sur.Surrogate(seed=0)
+    losses = sur.train(model, scenes, steps=300, B=16, Hc=48, Wc=48, lr=2e-3, seed=1,
+                       log_every=50)
+    assert losses[-1] < losses[0], losses
+    rng = np.random.default_rng(7)
+    err_net, err_est = [], []
+    for _ in range(4):
+        smp = held.samples(rng, 8, 64, 64)
+        win, est, st, tgt = sur.Surrogate.input(smp, 64, 64, 1.0, with_target=True)
+        y = model.forward(win, est)
+        err_net.append(((y - tgt) ** 2).mean().item())
+        err_est.append(((est - tgt) ** 2).mean().item())
+    print("held-out MSE net %.3g est %.3g" % (np.mean(err_net), np.mean(err_est)))
+    assert np.mean(err_net) < np.mean(err_est)
