@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAME = "recon_kernel"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_recon_gratings_250x400_T20000.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_11639_amd", "csrc", f)
-                  for f in ("recon.hip", "spk_internal.h")]
+                  for f in ("recon.hip", "recon_core.h", "spk_internal.h")]
 
 
 def kernel_sha() -> str:
@@ -60,22 +60,6 @@ def load_traffic(order_name):
         return None
     v = t.get("per_order", {}).get(order_name, {}).get("hbm_bytes_per_launch")
     return None if v is None else round(v)
-
-
-def run_cpu_baseline(s, H, W, T, t_out, order, rows):
-    """The oracle, as it stands, on the first ``rows`` rows of the workload
-    (all frames, all outputs), on all host cores (at most 16)."""
-    import numpy as np
-
-    import oracle
-    import spkgen
-    sub = spkgen.pack(spkgen.unpack(s, H, W)[:, :rows, :])
-    n = min(16, os.cpu_count() or 1)
-    oracle.reconstruct(sub[:256], rows, W, 256, 1.0, [0], order=order, nthreads=n)  # warm
-    t0 = time.perf_counter()
-    ref = oracle.reconstruct(sub, rows, W, T, 1.0, t_out, order=order, nthreads=n)
-    dt = time.perf_counter() - t0
-    return ref, dt, n, np
 
 
 COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB each way
@@ -116,8 +100,8 @@ def traffic_from_counters(d: str):
 
 def run_batched(args, spk, spkgen, torch, np):
     """16 streams of uneven size, 4096 frames each, 64 outputs each, in one
-    autotuned plan (persistent kernel in a HIP graph); the smallest stream is
-    checked against the oracle."""
+    autotuned plan (persistent kernel in a HIP graph).  Returns the result
+    and the smallest stream with its GPU output, for the CPU leg."""
     jobs = spkgen.batch_workload()
     order = spk.SSR if args.order == "ssr" else spk.FSR
     print("batched: generating %d streams" % len(jobs), file=sys.stderr, flush=True)
@@ -142,24 +126,263 @@ def run_batched(args, spk, spkgen, torch, np):
     ms = e0.elapsed_time(e1) / args.steps
     px_frames = sum(j["H"] * j["W"] * j["T"] for j in jobs)
     alg = sum(algorithmic_bytes(j["H"], j["W"], j["T"], len(j["t_out"])) for j in jobs)
-    parity = None
-    if not args.no_cpu_baseline:
-        import oracle
-        s, j, idx = host0
-        ref = oracle.reconstruct(s, j["H"], j["W"], j["T"], 1.0, j["t_out"], order=order,
-                                 nthreads=min(16, os.cpu_count() or 1))
-        parity = bool(np.array_equal(plan.outputs()[idx].cpu().numpy(), ref.astype(np.float32)))
-        if not parity:
-            print("PARITY FAILURE in the batched plan", file=sys.stderr)
+    s0, j0, idx = host0
+    check = dict(stream=s0, job=j0, order=order, got=plan.outputs()[idx].cpu().numpy())
     info = plan.info()
     plan.close()
+    del dev_jobs
+    torch.cuda.empty_cache()
     return {"workload": "batch16_mixed_T4096_64out", "order": args.order.upper(),
             "streams": len(jobs), "pixels": sum(j["H"] * j["W"] for j in jobs),
             "ms_per_step": round(ms, 4), "value": round(px_frames / (ms * 1e-3) / 1e6, 1),
             "unit": "Mpixel-frames/s", "achieved_GBs": round(alg / (ms * 1e-3) / 1e9, 1),
             "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "launch": info, "graph": True, "autotuned": True,
-            "smallest_stream_bit_exact_vs_oracle": parity}
+            "launch": info, "graph": True, "autotuned": True}, check
+
+
+SUR_FLOP_PER_PX = 2 * 28224       # forward multiply-adds of the 4 conv layers
+# training: forward + input gradients of layers 2-4 + weight gradients of all 4
+SUR_TRAIN_FLOP_PER_PX = 3 * SUR_FLOP_PER_PX - 2 * 9 * 33 * 32
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def _psnr(x, ref, np):
+    """10 log10(theta^2 / MSE) with theta = 1."""
+    mse = float(np.mean((np.asarray(x, np.float64) - np.asarray(ref, np.float64)) ** 2))
+    return 10.0 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+
+
+def run_surrogate(args, spk, spkgen, torch, np):
+    """Surrogate training on seeded static block scenes (250x400x4096;
+    targets = the plain method over the whole stream, computed by the
+    library), held-out outputs, and the 1000x1000 streaming run."""
+    import paper_2412_11639_amd.surrogate as sur
+    out, checks = {}, {}
+    H, W, T = 250, 400, 4096
+    t0 = time.perf_counter()
+    print("surrogate: %d training scenes" % args.sur_scenes, file=sys.stderr, flush=True)
+    scenes = sur.SceneSet([10000 + i for i in range(args.sur_scenes)], H=H, W=W, T=T)
+    held = sur.SceneSet([20000 + i for i in range(32)], H=H, W=W, T=T)
+    gen_s = time.perf_counter() - t0
+    B, Hc, Wc, lr = 32, 64, 64, 3e-4
+    sur.train(sur.Surrogate(seed=0), scenes, steps=20, B=B, Hc=Hc, Wc=Wc, lr=lr, seed=99)
+    model = sur.Surrogate(seed=0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    print("surrogate: training %d steps" % args.sur_steps, file=sys.stderr, flush=True)
+    e0.record()
+    losses = sur.train(model, scenes, steps=args.sur_steps, B=B, Hc=Hc, Wc=Wc, lr=lr, seed=1,
+                       log_every=max(1, args.sur_steps // 6))
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.sur_steps
+    # held-out outputs at two times per scene, whole frames
+    eval_times = [held.target_times[1], held.target_times[3]]
+    ys, ests, muxs, plain_long = [], [], [], []
+    for i in range(len(held.seeds)):
+        for k, t in enumerate(eval_times):
+            smp = [dict(stream=held.streams[i], H=H, W=W, T=T, oy=0, ox=0, t=t)]
+            win, est, st = sur.Surrogate.input(smp, H, W, 1.0)
+            y = model.forward(win, est)
+            ys.append(y[0].cpu().numpy())
+            ests.append(est[0].cpu().numpy())
+            muxs.append(sur.Surrogate.mux(y, est, st)[0].cpu().numpy())
+            plain_long.append(held.targets[i][held.target_times.index(t)].cpu().numpy())
+    train_tflops = SUR_TRAIN_FLOP_PER_PX * B * Hc * Wc / (ms_step * 1e-3) / 1e12
+    out["surrogate"] = {
+        "workload": "blocks_250x400_T4096: %d training scenes (seeds 10000+), 32 held out "
+                    "(seeds 20000-20031), outputs at t=%s" % (args.sur_scenes, eval_times),
+        "train_steps": args.sur_steps, "batch": "%d crops of %dx%d" % (B, Hc, Wc), "lr": lr,
+        "train_ms_per_step": round(ms_step, 3), "train_tflops": round(train_tflops, 2),
+        "train_mfma_frac": round(train_tflops / MFMA_BF16_PEAK_TFLOPS, 5),
+        "loss_curve": [float("%.4g" % l) for l in losses], "data_gen_s": round(gen_s, 1)}
+    checks["surrogate"] = dict(host=held.host, H=H, W=W, T=T, times=eval_times,
+                               y=np.stack(ys), est=np.stack(ests), mux=np.stack(muxs),
+                               plain_long=np.stack(plain_long))
+    del scenes, held
+    torch.cuda.empty_cache()
+    out["streaming"], checks["streaming"] = run_streaming(args, spk, spkgen, torch, np, model, sur)
+    return out, checks
+
+
+def run_streaming(args, spk, spkgen, torch, np, model, sur):
+    """1000x1000 blocks translating at one velocity, |v| in (0, 2] px/frame
+    (seed 5).  Per frame: advance the 32-frame window, run the surrogate and
+    the fallback mux; latency from HIP events around each frame.  Beside it
+    the plain method two ways: one pass over the whole stream with an output
+    every frame, and the latency-bound form that re-scans the last 4096
+    frames for each output frame."""
+    H = W = 1000
+    T = args.stream_frames
+    speed = 2.0 * (1.0 - spkgen.rng_u64(5, 7, 0) / 2.0 ** 64)    # (0, 2]
+    ang = 2.0 * np.pi * (spkgen.rng_u64(5, 7, 1) / 2.0 ** 64)
+    vx, vy = speed * np.cos(ang), speed * np.sin(ang)
+    print("streaming: generating 1000x1000x%d" % T, file=sys.stderr, flush=True)
+    s = spkgen.blocks(H, W, T, 5, vx=vx, vy=vy)
+    ds = torch.from_numpy(s).cuda()
+    win = torch.zeros((1, H, W), dtype=torch.int32, device="cuda")
+    est = torch.zeros((1, H, W), dtype=torch.float32, device="cuda")
+    st = torch.zeros((1, H, W), dtype=torch.uint8, device="cuda")
+    y = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    mx = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    n_check = min(400, T - 31)
+    check_t = sorted(set(np.linspace(31, T - 1, n_check).astype(int).tolist()))
+    kept = {k: torch.empty((len(check_t), H, W), dtype=torch.float32, device="cuda")
+            for k in ("surrogate", "surrogate_with_fallback", "plain_short_window")}
+    slot = {t: i for i, t in enumerate(check_t)}
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(T)]
+    print("streaming: %d frames" % T, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for t in range(T):
+        a, b = evs[t]
+        a.record()
+        sur.Surrogate.stream_step(ds[t], H, W, 1.0, win, est, st)
+        if t >= 31:
+            model.forward(win, est, out=y)
+            sur.Surrogate.mux(y, est, st, out=mx)
+        b.record()
+        if t in slot:
+            kept["surrogate"][slot[t]].copy_(y[0])
+            kept["surrogate_with_fallback"][slot[t]].copy_(mx[0])
+            kept["plain_short_window"][slot[t]].copy_(est[0])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    lat = np.array([evs[t][0].elapsed_time(evs[t][1]) for t in range(31, T)])
+    sur_rate = H * W * len(lat) / (lat.sum() * 1e-3) / 1e6
+    fwd = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fwd[0].record()
+    for _ in range(20):
+        model.forward(win, est, out=y)
+    fwd[1].record()
+    torch.cuda.synchronize()
+    fwd_ms = fwd[0].elapsed_time(fwd[1]) / 20
+    # plain, one pass, an output every frame from 31 on
+    frames = list(range(31, T))
+    plain_out = torch.empty((len(frames), H, W), dtype=torch.float32, device="cuda")
+    spk.reconstruct(ds, H, W, T, 1.0, frames, order=spk.FSR, out=plain_out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    spk.reconstruct(ds, H, W, T, 1.0, frames, order=spk.FSR, out=plain_out)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    plain_kept = plain_out[[t - 31 for t in check_t]].cpu().numpy()
+    del plain_out
+    # plain, latency-bound: re-scan the last Wn frames for one output frame
+    Wn = min(4096, T)
+    one = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    rs_ms = []
+    for t in np.linspace(Wn - 1, T - 1, 8).astype(int):
+        sub = ds[t - Wn + 1:t + 1]
+        spk.reconstruct(sub, H, W, Wn, 1.0, [Wn - 1], order=spk.FSR, out=one)
+        e0.record()
+        spk.reconstruct(sub, H, W, Wn, 1.0, [Wn - 1], order=spk.FSR, out=one)
+        e1.record()
+        torch.cuda.synchronize()
+        rs_ms.append(e0.elapsed_time(e1))
+    rs_ms = float(np.median(rs_ms))
+    res = {"workload": "blocks_1000x1000 translating |v|=%.3f px/frame (seed 5), %d frames "
+                       "(the full run has 40000)" % (speed, T),
+           "frames": T,
+           "surrogate_mpx_frames_per_s": round(sur_rate, 1),
+           "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+           "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+           "surrogate_forward_ms": round(fwd_ms, 4),
+           "surrogate_mfma_frac": round(SUR_FLOP_PER_PX * H * W / (fwd_ms * 1e-3) / 1e12
+                                        / MFMA_BF16_PEAK_TFLOPS, 4),
+           "plain_single_pass": {"mpx_frames_per_s": round(H * W * T / (plain_ms * 1e-3) / 1e6, 1),
+                                 "ms": round(plain_ms, 3),
+                                 "outputs": "every frame 31..%d" % (T - 1)},
+           "plain_rescan_%d" % Wn: {"mpx_frames_per_s": round(H * W / (rs_ms * 1e-3) / 1e6, 1),
+                                    "latency_ms": round(rs_ms, 4)},
+           "wall_s": round(wall, 2)}
+    check = dict(stream=s, H=H, W=W, T=T, times=check_t, plain=plain_kept,
+                 **{k: v.cpu().numpy() for k, v in kept.items()})
+    del ds, kept
+    torch.cuda.empty_cache()
+    return res, check
+
+
+def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
+    """Every use of the oracle in this benchmark.  Times the oracle on a
+    sample of the plain workload (the cpu_baseline figure) and checks the
+    GPU outputs of every leg against it: bit-exact for the plain method,
+    PSNR and maximum absolute error for the surrogate."""
+    import oracle
+    import spkgen
+    n = min(16, os.cpu_count() or 1)
+    s, H, W, T, t_out, order, gpu_out = plain
+    rows = min(args.cpu_rows, H)
+    print("cpu baseline: oracle on %d rows" % rows, file=sys.stderr, flush=True)
+    sub = s if rows == H else spkgen.pack(spkgen.unpack(s, H, W)[:, :rows, :])
+    oracle.reconstruct(sub[:256], rows, W, 256, 1.0, [0], order=order, nthreads=n)  # warm
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ref = oracle.reconstruct(sub, rows, W, T, 1.0, t_out, order=order, nthreads=n)
+        runs.append(time.perf_counter() - t0)
+    dt = float(np.median(runs))
+    ok = bool(np.array_equal(gpu_out[:, :rows, :], ref.astype(np.float32)))
+    del ref
+    r1 = min(4, rows)
+    sub1 = spkgen.pack(spkgen.unpack(s, H, W)[:, :r1, :])
+    t0 = time.perf_counter()
+    oracle.reconstruct(sub1, r1, W, T, 1.0, t_out, order=order, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    res["cpu_baseline"] = {
+        "value": round(rows * W * T / dt / 1e6, 1), "unit": "Mpixel-frames/s", "cores": n,
+        "kind": "oracle",
+        "sample": "%d of %d rows, all %d frames and %d outputs (%s); median of 3 runs "
+                  "(%.2f s each) after a warm-up; GPU output on the same rows bit-exact: %s"
+                  % (rows, H, T, len(t_out), "SSR" if order == 2 else "FSR", dt, ok),
+        "single_thread_value": round(r1 * W * T / dt1 / 1e6, 2)}
+    failures = [] if ok else ["plain"]
+    if batched is not None:
+        j = batched["job"]
+        r = oracle.reconstruct(batched["stream"], j["H"], j["W"], j["T"], 1.0, j["t_out"],
+                               order=batched["order"], nthreads=n)
+        eq = bool(np.array_equal(batched["got"], r.astype(np.float32)))
+        res["batched"]["smallest_stream_bit_exact_vs_oracle"] = eq
+        failures += [] if eq else ["batched"]
+    if sur_checks:
+        c = sur_checks["surrogate"]
+        refs = np.concatenate([oracle.reconstruct(h, c["H"], c["W"], c["T"], 1.0, c["times"],
+                                                  order=1, nthreads=n) for h in c["host"]])
+        eq = bool(np.array_equal(c["plain_long"], refs.astype(np.float32)))
+        res["surrogate"]["vs_oracle"] = {
+            "psnr_db": {"surrogate": round(_psnr(c["y"], refs, np), 2),
+                        "surrogate_with_fallback": round(_psnr(c["mux"], refs, np), 2),
+                        "plain_short_window": round(_psnr(c["est"], refs, np), 2)},
+            "max_abs": {"surrogate": float("%.4g" % np.abs(c["y"] - refs).max()),
+                        "surrogate_with_fallback": float("%.4g" % np.abs(c["mux"] - refs).max()),
+                        "plain_short_window": float("%.4g" % np.abs(c["est"] - refs).max())},
+            "training_targets_bit_exact": eq}
+        failures += [] if eq else ["surrogate targets"]
+        c = sur_checks["streaming"]
+        print("cpu leg: streaming references at %d frames" % len(c["times"]),
+              file=sys.stderr, flush=True)
+        refs = oracle.reconstruct(c["stream"], c["H"], c["W"], c["T"], 1.0, c["times"],
+                                  order=1, nthreads=n)
+        eq = bool(np.array_equal(c["plain"], refs.astype(np.float32)))
+        q = {"frames": len(c["times"]), "plain_bit_exact": eq}
+        for name, r in (("whole_stream", refs), ("causal", None)):
+            if r is None:
+                del refs
+                r = oracle.reconstruct(c["stream"], c["H"], c["W"], c["T"], 1.0, c["times"],
+                                       order=1, nthreads=n, causal=True)
+            q[name] = {"psnr_db": {k: round(_psnr(c[k], r, np), 2)
+                                   for k in ("surrogate", "surrogate_with_fallback",
+                                             "plain_short_window")},
+                       "max_abs": {k: float("%.4g" % np.abs(c[k] - r).max())
+                                   for k in ("surrogate", "surrogate_with_fallback",
+                                             "plain_short_window")}}
+            del r
+        res["streaming"]["vs_oracle"] = q
+        failures += [] if eq else ["streaming plain"]
+    return failures
 
 
 def parse_rocprof(d: str) -> str:
@@ -214,12 +437,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--order", choices=["fsr", "ssr"], default="ssr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=64)
+    ap.add_argument("--cpu-rows", type=int, default=250,
+                    help="rows of the plain workload the oracle runs on (all by default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched 16-stream measurement")
     ap.add_argument("--only-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip surrogate training/evaluation and the streaming run")
+    ap.add_argument("--only-surrogate", action="store_true")
+    ap.add_argument("--sur-steps", type=int, default=3000)
+    ap.add_argument("--sur-scenes", type=int, default=256)
+    ap.add_argument("--stream-frames", type=int, default=4000,
+                    help="frames of the 1000x1000 streaming run (the full config has 40000)")
     ap.add_argument("--parse-rocprof", default=None)
     ap.add_argument("--traffic-out", default=None,
                     help="with --parse-rocprof: write the per-launch HBM traffic JSON")
@@ -245,8 +476,14 @@ def main():
     import paper_2412_11639_amd as spk
     import spkgen
 
-    if args.only_batched:
-        print(json.dumps({"batched": run_batched(args, spk, spkgen, torch, np)}))
+    if args.only_batched or args.only_surrogate:
+        args.no_cpu_baseline = True
+        out = {}
+        if args.only_batched:
+            out["batched"] = run_batched(args, spk, spkgen, torch, np)[0]
+        if args.only_surrogate:
+            out.update(run_surrogate(args, spk, spkgen, torch, np)[0])
+        print(json.dumps(out))
         return 0
 
     wl = spkgen.GRATINGS_250x400
@@ -296,22 +533,6 @@ def main():
     achieved = alg / (ms * 1e-3) / 1e9
     traffic = load_traffic(args.order.upper())
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        rows = min(args.cpu_rows, H)
-        print("cpu baseline: oracle on %d rows" % rows, file=sys.stderr, flush=True)
-        ref, dt, cores, _ = run_cpu_baseline(s, H, W, T, t_out, order, rows)
-        # the benchmark's own output checked against the oracle on the sample
-        ok = np.array_equal(gpu_out[:, :rows, :], ref.astype(np.float32))
-        if not ok:
-            print("PARITY FAILURE against the oracle on the sample", file=sys.stderr)
-            return 1
-        cpu = {"value": rows * W * T / dt / 1e6, "unit": "Mpixel-frames/s", "cores": cores,
-               "kind": "oracle",
-               "sample": "first %d of %d rows, all %d frames and %d outputs (%s); "
-                         "bit-exact vs the GPU output on the same rows" % (
-                             rows, H, T, n_out, args.order.upper())}
-
     res = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -332,7 +553,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
-        "cpu_baseline": cpu,
+        "cpu_baseline": None,
         "other_order": {"order": "FSR" if order == spk.SSR else "SSR",
                         "ms_per_step": round(ms_other, 4),
                         "value": round(px_frames / (ms_other * 1e-3) / 1e6, 1)},
@@ -340,8 +561,19 @@ def main():
     }
     del ds, out
     torch.cuda.empty_cache()
+    bcheck, schecks = None, None
     if not args.no_batched:
-        res["batched"] = run_batched(args, spk, spkgen, torch, np)
+        res["batched"], bcheck = run_batched(args, spk, spkgen, torch, np)
+    if not args.no_surrogate:
+        sres, schecks = run_surrogate(args, spk, spkgen, torch, np)
+        res.update(sres)
+    if not args.no_cpu_baseline:
+        failures = cpu_baseline_leg(args, (s, H, W, T, t_out, order, gpu_out), bcheck, schecks,
+                                    res, np)
+        if failures:
+            print("PARITY FAILURE against the oracle: %s" % ", ".join(failures), file=sys.stderr)
+            print(json.dumps(res))
+            return 1
     print(json.dumps(res))
     return 0
 

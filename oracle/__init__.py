@@ -46,6 +46,8 @@ def _bind(lib):
     lib.spk_oracle_reconstruct.argtypes = [
         P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P_i32,
         ctypes.c_int32, ctypes.c_int32, P_f64, P_i32, P_i32, P_i32, ctypes.c_int32]
+    lib.spk_oracle_reconstruct_causal.restype = ctypes.c_int32
+    lib.spk_oracle_reconstruct_causal.argtypes = lib.spk_oracle_reconstruct.argtypes
     lib.spk_oracle_window.restype = ctypes.c_int32
     lib.spk_oracle_window.argtypes = [P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, P_f64,
@@ -91,9 +93,11 @@ def segment_intervals(x, order: int = FSR, lib=None) -> list:
 
 
 def reconstruct(stream, H, W, T, theta, t_out, order=FSR, windows=False, nthreads=None,
-                lib=None):
+                lib=None, causal=False):
     """Intensity per output time and pixel, [n_out, H, W] float64.  With
-    ``windows`` also returns (first, last, n) int32 arrays of the same shape."""
+    ``windows`` also returns (first, last, n) int32 arrays of the same shape.
+    With ``causal`` the output at t is the method's result on frames 0..t
+    alone (streaming reading)."""
     lib = lib or load()
     stream = np.ascontiguousarray(stream, dtype=np.uint8)
     t_out = np.ascontiguousarray(t_out, dtype=np.int32)
@@ -104,10 +108,10 @@ def reconstruct(stream, H, W, T, theta, t_out, order=FSR, windows=False, nthread
         wf = np.zeros((n_out, H, W), dtype=np.int32)
         wl = np.zeros((n_out, H, W), dtype=np.int32)
         wn = np.zeros((n_out, H, W), dtype=np.int32)
-    rc = lib.spk_oracle_reconstruct(_ptr(stream, P_u8), H, W, T, float(theta),
-                                    _ptr(t_out, P_i32), n_out, order, _ptr(out, P_f64),
-                                    _ptr(wf, P_i32), _ptr(wl, P_i32), _ptr(wn, P_i32),
-                                    _nthreads(nthreads))
+    fn = lib.spk_oracle_reconstruct_causal if causal else lib.spk_oracle_reconstruct
+    rc = fn(_ptr(stream, P_u8), H, W, T, float(theta), _ptr(t_out, P_i32), n_out, order,
+            _ptr(out, P_f64), _ptr(wf, P_i32), _ptr(wl, P_i32), _ptr(wn, P_i32),
+            _nthreads(nthreads))
     if rc != 0:
         raise ValueError("spk_oracle_reconstruct: bad arguments")
     return (out, wf, wl, wn) if windows else out

@@ -185,6 +185,8 @@ typedef struct {
     /* segments mode */
     int32_t cap;
     int32_t *seg_first, *seg_last, *seg_n, *count;
+    /* causal mode: output at t from frames 0 .. t only */
+    int32_t causal;
     int64_t p0, p1;
 } task_t;
 
@@ -227,7 +229,25 @@ static void pixel_task(const task_t *tk, scratch_t *sc, int64_t p)
     for (int32_t k = 0; k < tk->n_out; k++) {
         double I = 0.0;
         int32_t first = -1, last = -1, cnt = 0;
-        if (K >= 2) {
+        if (tk->causal) {
+            /* The method run on frames 0 .. t alone, valued at its last frame.
+             * That stream holds the Kt = #{spikes at frames <= t} first spikes,
+             * so its S1 is the first Kt-1 intervals of the whole stream's S1.
+             * FSR and SSR decide every cut from the intervals up to the cut,
+             * so its segments are the whole stream's segments cut off after
+             * interval Kt-1; O-6 on it picks that last interval (t lies at or
+             * after its last spike).  Result: the segment holding interval
+             * Kt-1, truncated there. */
+            int32_t Kt = spikes_before(sc->tau, K, tk->t_out[k] + 1);
+            if (Kt >= 2) {
+                int32_t i = Kt - 2;               /* 0-based index of interval Kt-1 */
+                int32_t a = sc->start[sc->seg_of[i]];
+                first = sc->tau[a];
+                last = sc->tau[i + 1];
+                cnt = i - a + 1;
+                I = tk->theta * (double)cnt / (double)(last - first);
+            }
+        } else if (K >= 2) {
             /* O-6: interval in progress at t (1-based m, clamped to [1, K-1]) */
             int32_t m = spikes_before(sc->tau, K, tk->t_out[k]);
             if (m < 1) m = 1;
@@ -322,6 +342,39 @@ int32_t spk_oracle_reconstruct(const uint8_t *stream, int32_t H, int32_t W, int3
     tk.win_first = win_first;
     tk.win_last = win_last;
     tk.win_n = win_n;
+    run_all(&tk, nthreads);
+    return 0;
+}
+
+/* Streaming (causal) reading: for each output time t, what the method gives
+ * on the stream cut after frame t, at that frame.  Same layout and
+ * arguments as spk_oracle_reconstruct. */
+int32_t spk_oracle_reconstruct_causal(const uint8_t *stream, int32_t H, int32_t W, int32_t T,
+                                      double theta, const int32_t *t_out, int32_t n_out,
+                                      int32_t order, double *out, int32_t *win_first,
+                                      int32_t *win_last, int32_t *win_n, int32_t nthreads)
+{
+    if (!stream || H <= 0 || W <= 0 || T <= 0 || n_out < 0 || (n_out > 0 && !t_out) ||
+        (order != ORACLE_FSR && order != ORACLE_SSR))
+        return -1;
+    for (int32_t k = 0; k < n_out; k++)
+        if (t_out[k] < 0 || t_out[k] >= T) return -1;
+    task_t tk;
+    memset(&tk, 0, sizeof(tk));
+    tk.stream = stream;
+    tk.H = H;
+    tk.W = W;
+    tk.T = T;
+    tk.fb = frame_bytes(H, W);
+    tk.theta = theta;
+    tk.t_out = t_out;
+    tk.n_out = n_out;
+    tk.order = order;
+    tk.out = out;
+    tk.win_first = win_first;
+    tk.win_last = win_last;
+    tk.win_n = win_n;
+    tk.causal = 1;
     run_all(&tk, nthreads);
     return 0;
 }

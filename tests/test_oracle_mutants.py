@@ -32,6 +32,10 @@ MUTANTS = {
     "ssr_gap_not_recorded": ("            tr[j].has_gap = 1;\n", ""),
     "interval_sign": ("sc->x[i] = sc->tau[i + 1] - sc->tau[i];",
                       "sc->x[i] = sc->tau[i] - sc->tau[i + 1] + 2 * (sc->tau[i + 1] - sc->tau[i]) - (i == 0);"),
+    "causal_excludes_spike_at_t": ("spikes_before(sc->tau, K, tk->t_out[k] + 1)",
+                                   "spikes_before(sc->tau, K, tk->t_out[k])"),
+    "causal_untruncated": ("                last = sc->tau[i + 1];",
+                           "                last = sc->tau[i + 1 < K - 1 ? i + 2 : i + 1];"),
     "first_segment_start": ("    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0];",
                             "    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0] + 1;"),
 }
@@ -86,6 +90,15 @@ def _battery(lib):
     out = oracle.reconstruct(s, 1, 8, 300, 1.0, [0, 150, 299], lib=lib)
     if not np.all(out[:, 0, :] == (Q / th)[None, :]):
         failed.append("exact_intensity")
+    # causal reading == the method on each prefix
+    H, W, T = 4, 9, 60
+    s = spkgen.blocks(H, W, T, seed=62, block=3, vx=0.7)
+    got = oracle.reconstruct(s, H, W, T, 1.0, list(range(T)), causal=True, lib=lib)
+    for t in range(T):
+        ref = oracle.reconstruct(s[:t + 1], H, W, t + 1, 1.0, [t], lib=lib)
+        if not np.array_equal(got[t], ref[0]):
+            failed.append("causal_prefix")
+            break
     return failed
 
 

@@ -336,3 +336,44 @@ def test_argument_errors():
         oracle.reconstruct(s, 1, 8, 4, 1.0, [4])          # t out of range
     with pytest.raises(ValueError):
         oracle.reconstruct(s, 1, 8, 4, 1.0, [0], order=3)  # unknown order
+
+
+@pytest.mark.parametrize("order", [oracle.FSR, oracle.SSR])
+def test_causal_reading_is_the_method_on_the_prefix(order):
+    """Streaming reading: the causal output at t is, by definition, the
+    method run on frames 0..t alone and valued at frame t.  Checked against
+    exactly that (the oracle on each truncated stream), on moving noisy and
+    moving block scenes, at every frame of a short stream."""
+    H, W, T = 6, 21, 160
+    for s in (spkgen.gratings(H, W, T, seed=61), spkgen.blocks(H, W, T, seed=62, block=4, vx=0.7)):
+        t_out = list(range(T))
+        got, gf, gl, gn = oracle.reconstruct(s, H, W, T, 1.0, t_out, order=order, windows=True,
+                                             causal=True)
+        for t in t_out:
+            ref, rf, rl, rn = oracle.reconstruct(s[:t + 1], H, W, t + 1, 1.0, [t], order=order,
+                                                 windows=True)
+            np.testing.assert_array_equal(got[t], ref[0])
+            np.testing.assert_array_equal(gf[t], rf[0])
+            np.testing.assert_array_equal(gl[t], rl[0])
+            np.testing.assert_array_equal(gn[t], rn[0])
+
+
+def test_causal_reading_bruteforce():
+    """On every stream of 12 frames and at every t: the causal output is
+    theta*n/D of the last piece of the declarative FSR partition of the
+    intervals that have ended by t (0 with fewer than two spikes)."""
+    T = 12
+    s, bits, H, W = _all_streams(T)
+    got = oracle.reconstruct(s, H, W, T, 1.0, list(range(T)), order=oracle.FSR, causal=True)
+    got = got.reshape(T, -1)
+    for p in range(H * W):
+        tau = _spike_frames(bits[:, p])
+        for t in range(T):
+            tt = [f for f in tau if f <= t]
+            if len(tt) < 2:
+                assert got[t, p] == 0.0
+                continue
+            x = brute.intervals_of(tt)
+            parts = brute.enumerate_partitions(x, lambda st: brute.is_fsr_partition(x, st))
+            a = parts[0][-1]
+            assert got[t, p] == len(x[a:]) / (tt[-1] - tt[a]), (p, t, tt)
