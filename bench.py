@@ -65,22 +65,34 @@ def load_traffic(order_name):
 COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB each way
 
 
-def traffic_from_counters(d: str):
-    """HBM bytes per launch of each reconstruction kernel from the FETCH_SIZE
-    and WRITE_SIZE passes under d, each scaled by what the same counter reads
-    for the 1 GiB calibration copy in the same run."""
+def _counter_means(d: str):
+    """(kernel name, counter) -> mean value per dispatch, from rocprofv3
+    output under d (rocpd SQLite databases or counter_collection CSVs)."""
     import sqlite3
-    vals = {}
+    acc = {}
     for f in glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True):
         con = sqlite3.connect(f)
         try:
-            rows = con.execute("select kernel_name, counter_name, avg(value) "
-                               "from counters_collection group by kernel_name, counter_name")
-            for name, cname, mean in rows:
-                vals[(name, cname)] = mean
+            for name, cname, v in con.execute(
+                    "select kernel_name, counter_name, value from counters_collection"):
+                acc.setdefault((name, cname), []).append(v)
         except sqlite3.Error:
             pass
         con.close()
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                acc.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(
+                    float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic_from_counters(d: str):
+    """HBM bytes per reconstruction step (recon_kernel + fixup_kernel) of each
+    order from the FETCH_SIZE and WRITE_SIZE passes under d, each scaled by
+    what the same counter reads for the 1 GiB calibration copy in the same
+    run."""
+    vals = _counter_means(d)
     out = {}
     for cname in ("FETCH_SIZE", "WRITE_SIZE"):
         copy = [v for (n, c), v in vals.items() if c == cname and "copyBuffer" in n]
@@ -88,10 +100,14 @@ def traffic_from_counters(d: str):
             continue
         factor = COPY_BYTES / (copy[0] * 1024.0)
         for (n, c), v in vals.items():
-            if c == cname and KERNEL_NAME in n:
-                key = "SSR" if "recon_kernel<2" in n else "FSR"
-                out.setdefault(key, {})[cname] = {"kib": v, "factor": factor,
-                                                  "bytes": v * 1024.0 * factor}
+            if c != cname:
+                continue
+            for kern in ("recon_kernel", "fixup_kernel"):
+                for o, key in (("1", "FSR"), ("2", "SSR")):
+                    if kern + "<" + o in n:
+                        e = out.setdefault(key, {}).setdefault(cname, {"factor": factor})
+                        e[kern + "_kib"] = v
+                        e["bytes"] = e.get("bytes", 0.0) + v * 1024.0 * factor
     for key, d2 in out.items():
         if "FETCH_SIZE" in d2 and "WRITE_SIZE" in d2:
             d2["hbm_bytes_per_launch"] = d2["FETCH_SIZE"]["bytes"] + d2["WRITE_SIZE"]["bytes"]
@@ -301,6 +317,13 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
            "wall_s": round(wall, 2)}
     check = dict(stream=s, H=H, W=W, T=T, times=check_t, plain=plain_kept,
                  **{k: v.cpu().numpy() for k, v in kept.items()})
+    # the scene itself (the generator's per-frame intensity) as a third reference
+    truth = spkgen.blocks_truth(H, W, check_t, 5, vx=vx, vy=vy)
+    check["truth"] = truth
+    res["vs_scene_truth_psnr_db"] = {
+        k: round(_psnr(check[k], truth, np), 2)
+        for k in ("surrogate", "surrogate_with_fallback", "plain_short_window")}
+    res["vs_scene_truth_psnr_db"]["plain_whole_stream"] = round(_psnr(plain_kept, truth, np), 2)
     del ds, kept
     torch.cuda.empty_cache()
     return res, check
@@ -379,6 +402,9 @@ def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
                        "max_abs": {k: float("%.4g" % np.abs(c[k] - r).max())
                                    for k in ("surrogate", "surrogate_with_fallback",
                                              "plain_short_window")}}
+            if name == "causal":
+                res["streaming"]["vs_scene_truth_psnr_db"]["plain_causal"] = round(
+                    _psnr(r, c["truth"], np), 2)
             del r
         res["streaming"]["vs_oracle"] = q
         failures += [] if eq else ["streaming plain"]

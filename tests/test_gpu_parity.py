@@ -127,6 +127,21 @@ def test_edge_cases(spk):
         check_segments(spk, s, 1, 6, T, order, cap=T)
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_unsorted_duplicate_t_out_short_stream_and_no_outputs(spk, order):
+    """t_out in any order with duplicates (plane k is always for t_out[k]),
+    a stream shorter than one 64-frame tile, and n_out = 0."""
+    H, W, T = 7, 45, 30
+    s = spkgen.gratings(H, W, T, seed=71)
+    check_recon(spk, s, H, W, T, [29, 0, 13, 13, 5, 29, 0], order)
+    T = 700
+    s = spkgen.blocks(H, W, T, seed=72, block=3, vx=0.3)
+    check_recon(spk, s, H, W, T, [650, 3, 650, 64, 63, 0, 699, 128, 3], order)
+    out = spk.reconstruct(dev(s), H, W, T, 1.0, [], order=order)
+    torch.cuda.synchronize()
+    assert tuple(out.shape) == (0, H, W)
+
+
 def test_reconstruct_rejects_bad_t_out(spk):
     s = dev(np.zeros((4, 16), dtype=np.uint8))
     with pytest.raises(spk.SpkError):
