@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64) void recon_kernel(ReconParams P, int nblocks, C
         run.cum -= cum_base;
         run.first_idx -= cum_base;
         run.fi1 -= cum_base;
-        if (em.valid) save_run(rec_end(cp, chunk, p, P.HW), fstride, run);
+        if (em.valid) save_run<ORDER>(rec_end(cp, chunk, p, P.HW), fstride, run);
         return;
     }
     if (run.cum >= 2)
@@ -118,13 +118,13 @@ __global__ __launch_bounds__(64) void fixup_kernel(ReconParams P, int nblocks, C
     const int32_t ntiles = (P.T + 63) / 64;
 
     Run tr;
-    if (em.valid) load_run(rec_end(cp, 0, p, P.HW), fstride, tr);
+    if (em.valid) load_run<ORDER>(rec_end(cp, 0, p, P.HW), fstride, tr);
     else tr.reset(0);
     for (int c = 1; c < cp.nchunks; c++) {
         Run rc, sp;
         if (em.valid) {
-            load_run(rec_end(cp, c, p, P.HW), fstride, rc);
-            load_run(rec_start(cp, c, p, P.HW), fstride, sp);
+            load_run<ORDER>(rec_end(cp, c, p, P.HW), fstride, rc);
+            load_run<ORDER>(rec_start(cp, c, p, P.HW), fstride, sp);
         } else {
             rc.reset(0);
             sp.reset(0);

@@ -138,17 +138,20 @@ constexpr int kFastMaxGap = 15;  // word-level shortcut for intervals up to this
 // Segmentation state of one pixel (registers).
 struct SegState {
     int32_t flo, fhi;  // extremes of the open FSR segment's S1 values
-    // SSR: inside the open piece, per interval value (keyed by parity: an
-    // FSR segment holds at most two adjacent values) the piece-local index
-    // of its latest occurrence (-1: none) and the extremes of its S2 gaps
-    int32_t np;        // intervals in the open piece
+    // SSR: intervals are numbered by ii (running count); the open piece
+    // starts at interval ps.  Per interval value (keyed by parity: an FSR
+    // segment holds at most two adjacent values) the number of its latest
+    // occurrence -- meaningful only when >= ps, so a cut needs no clearing --
+    // and the extremes of its S2 gaps inside the piece (reset at the value's
+    // first occurrence in a piece, hence valid whenever the occurrence is).
+    int32_t ii, ps;
     int32_t l0, l1, g0l, g0h, g1l, g1h;
 
     __device__ __forceinline__ void reset()
     {
         flo = kBig;
         fhi = -kBig;
-        np = 0;
+        ii = ps = 0;
         l0 = l1 = -1;
         g0l = g1l = kBig;
         g0h = g1h = -kBig;
@@ -178,10 +181,10 @@ struct SegState {
             if (c > 1 && !gaps_within(w, v, false)) return false;
             const bool odd = v & 1;
             const int32_t l = odd ? l1 : l0;
-            int32_t gl = odd ? g1l : g0l, gh = odd ? g1h : g0h;
-            if (l >= 0) {
-                gl = min(gl, np - l);
-                gh = max(gh, np - l);
+            int32_t gl = kBig, gh = -kBig;
+            if (l >= ps) {
+                gl = min(odd ? g1l : g0l, ii - l);
+                gh = max(odd ? g1h : g0h, ii - l);
             }
             if (c > 1) {
                 gl = min(gl, 1);
@@ -190,18 +193,23 @@ struct SegState {
             if (gh - gl > 1) return false;
             flo = min(flo, v);
             fhi = max(fhi, v);
-            if (odd) {
-                l1 = np + c - 1; g1l = gl; g1h = gh;
-            } else {
-                l0 = np + c - 1; g0l = gl; g0h = gh;
-            }
-            np += c;
+            // selects rather than stores through a chosen member, which
+            // would force the state out of registers
+            const int32_t last = ii + c - 1;
+            l0 = odd ? l0 : last;
+            l1 = odd ? last : l1;
+            g0l = odd ? g0l : gl;
+            g0h = odd ? g0h : gh;
+            g1l = odd ? gl : g1l;
+            g1h = odd ? gh : g1h;
+            ii += c;
             return true;
         }
     }
 
     // Add interval x; returns true if x opens a new segment (the previous
-    // spike then ends the closed one).
+    // spike then ends the closed one).  Written as selects so that the wave
+    // runs one straight path whatever each lane decides.
     template <int ORDER>
     __device__ __forceinline__ bool step(int32_t x)
     {
@@ -214,21 +222,20 @@ struct SegState {
         } else {
             const bool odd = x & 1;
             const int32_t l = odd ? l1 : l0;
-            const int32_t gl = odd ? g1l : g0l, gh = odd ? g1h : g0h;
-            const int32_t d = np - l;  // next element of S2 for value x
-            const int32_t ngl = min(gl, d), ngh = max(gh, d);
-            const bool cut = fcut || (l >= 0 && ngh - ngl > 1);
-            const bool fresh = cut || l < 0;
+            const int32_t d = ii - l;  // next element of S2 for value x
+            const int32_t ngl = min(odd ? g1l : g0l, d), ngh = max(odd ? g1h : g0h, d);
+            const bool seen = l >= ps;  // x already occurred in the open piece
+            const bool cut = fcut || (seen && ngh - ngl > 1);
+            const bool fresh = cut || !seen;
             const int32_t ugl = fresh ? kBig : ngl, ugh = fresh ? -kBig : ngh;
-            const int32_t idx = cut ? 0 : np;
-            if (odd) {
-                l1 = idx; g1l = ugl; g1h = ugh;
-                l0 = cut ? -1 : l0; g0l = cut ? kBig : g0l; g0h = cut ? -kBig : g0h;
-            } else {
-                l0 = idx; g0l = ugl; g0h = ugh;
-                l1 = cut ? -1 : l1; g1l = cut ? kBig : g1l; g1h = cut ? -kBig : g1h;
-            }
-            np = idx + 1;
+            l0 = odd ? l0 : ii;
+            l1 = odd ? ii : l1;
+            g0l = odd ? g0l : ugl;
+            g0h = odd ? g0h : ugh;
+            g1l = odd ? ugl : g1l;
+            g1h = odd ? ugh : g1h;
+            ps = cut ? ii : ps;
+            ii++;
             return cut;
         }
     }
@@ -274,8 +281,14 @@ struct Emitter {
             if (k0 >= kend) return;
             // Eq. 6: theta / ((1/N) sum T0(i)); the N intervals sum to last - first
             const float I = (float)(P.theta * (double)n / (double)(last - first));
+            if constexpr (PMAP == PMAP_IDENT && !WIN) {
+                // planes in time order: step a pointer by one plane per output
+                float *q = P.out + p + (uint64_t)(uint32_t)k0 * (uint32_t)P.HW;
+                for (int32_t k = k0; k < kend; k++, q += (uint32_t)P.HW) *q = I;
+                return;
+            }
             for (int32_t k = k0; k < kend; k++) {
-                const int64_t o = (int64_t)plane(k) * P.HW + p;
+                const int64_t o = (int64_t)(uint64_t)(uint32_t)plane(k) * (uint32_t)P.HW + p;
                 if constexpr (WIN) {
                     if (P.out) P.out[o] = I;
                     if (P.win_first) P.win_first[o] = first;
@@ -442,12 +455,13 @@ struct Run {
 };
 
 // Per-chunk record of the running state at the chunk's end, [field][chunk][pixel].
+// FSR runs keep the fields up to R_NFSR, SSR runs all but the FSR capture.
 enum RecField {
     R_LASTSPK, R_CNTLAST, R_CUM, R_FIRST, R_FIRSTIDX, R_K0, R_LASTB, R_FB1, R_FN1,
-    R_FI1, R_FWLO, R_FWHI,
-    R_FLO, R_FHI, R_NP, R_L0, R_L1, R_G0L, R_G0H, R_G1L, R_G1H, R_NFIELDS
+    R_FI1, R_FLO, R_FHI, R_FWLO, R_FWHI, R_NFSR = R_FWHI + 1,
+    R_II = R_FWLO, R_PS, R_L0, R_L1, R_G0L, R_G0H, R_G1L, R_G1H, R_NFIELDS
 };
-static_assert(R_NFIELDS == kRecFields, "record layout");
+static_assert(R_NFIELDS <= kRecFields, "record layout");
 
 // Records of chunk c: the state at the chunk's end (all chunks) and the
 // warmed-up speculative state at its start (chunks > 0), each [field][chunk][HW].
@@ -457,53 +471,74 @@ __device__ __forceinline__ int32_t *rec_end(const ChunkPlan &cp, int c, int64_t 
 }
 __device__ __forceinline__ int32_t *rec_start(const ChunkPlan &cp, int c, int64_t p, int32_t HW)
 {
-    return cp.rec + (int64_t)R_NFIELDS * cp.nchunks * HW + (int64_t)c * HW + p;
+    return cp.rec + (int64_t)kRecFields * cp.nchunks * HW + (int64_t)c * HW + p;
 }
 
+template <int ORDER>
 __device__ __forceinline__ void save_run(int32_t *rec, int64_t stride, const Run &r)
 {
-    const int32_t v[R_NFIELDS] = {r.lastspk, r.cnt_last, r.cum, r.first, r.first_idx, r.k0,
-                                  r.lastb, r.fb1, r.fn1, r.fi1, r.fwlo, r.fwhi,
-                                  r.st.flo, r.st.fhi, r.st.np,
-                                  r.st.l0, r.st.l1,
-                                  r.st.g0l, r.st.g0h, r.st.g1l, r.st.g1h};
-#pragma unroll
-    for (int f = 0; f < R_NFIELDS; f++) rec[f * stride] = v[f];
+    rec[R_LASTSPK * stride] = r.lastspk;
+    rec[R_CNTLAST * stride] = r.cnt_last;
+    rec[R_CUM * stride] = r.cum;
+    rec[R_FIRST * stride] = r.first;
+    rec[R_FIRSTIDX * stride] = r.first_idx;
+    rec[R_K0 * stride] = r.k0;
+    rec[R_LASTB * stride] = r.lastb;
+    rec[R_FB1 * stride] = r.fb1;
+    rec[R_FN1 * stride] = r.fn1;
+    rec[R_FI1 * stride] = r.fi1;
+    rec[R_FLO * stride] = r.st.flo;
+    rec[R_FHI * stride] = r.st.fhi;
+    if constexpr (ORDER == 1) {
+        rec[R_FWLO * stride] = r.fwlo;
+        rec[R_FWHI * stride] = r.fwhi;
+    } else {
+        rec[R_II * stride] = r.st.ii;
+        rec[R_PS * stride] = r.st.ps;
+        rec[R_L0 * stride] = r.st.l0;
+        rec[R_L1 * stride] = r.st.l1;
+        rec[R_G0L * stride] = r.st.g0l;
+        rec[R_G0H * stride] = r.st.g0h;
+        rec[R_G1L * stride] = r.st.g1l;
+        rec[R_G1H * stride] = r.st.g1h;
+    }
 }
 
+template <int ORDER>
 __device__ __forceinline__ void load_run(const int32_t *rec, int64_t stride, Run &r)
 {
-    int32_t v[R_NFIELDS];
-#pragma unroll
-    for (int f = 0; f < R_NFIELDS; f++) v[f] = rec[f * stride];
-    r.lastspk = v[R_LASTSPK];
-    r.cnt_last = v[R_CNTLAST];
-    r.cum = v[R_CUM];
-    r.first = v[R_FIRST];
-    r.first_idx = v[R_FIRSTIDX];
-    r.k0 = v[R_K0];
-    r.lastb = v[R_LASTB];
-    r.fb1 = v[R_FB1];
-    r.fn1 = v[R_FN1];
-    r.fi1 = v[R_FI1];
-    r.fwlo = v[R_FWLO];
-    r.fwhi = v[R_FWHI];
-    r.cs = 0;
-    r.st.flo = v[R_FLO];
-    r.st.fhi = v[R_FHI];
-    r.st.np = v[R_NP];
-    r.st.l0 = v[R_L0];
-    r.st.l1 = v[R_L1];
-    r.st.g0l = v[R_G0L];
-    r.st.g0h = v[R_G0H];
-    r.st.g1l = v[R_G1L];
-    r.st.g1h = v[R_G1H];
+    r.reset(0);
+    r.lastspk = rec[R_LASTSPK * stride];
+    r.cnt_last = rec[R_CNTLAST * stride];
+    r.cum = rec[R_CUM * stride];
+    r.first = rec[R_FIRST * stride];
+    r.first_idx = rec[R_FIRSTIDX * stride];
+    r.k0 = rec[R_K0 * stride];
+    r.lastb = rec[R_LASTB * stride];
+    r.fb1 = rec[R_FB1 * stride];
+    r.fn1 = rec[R_FN1 * stride];
+    r.fi1 = rec[R_FI1 * stride];
+    r.st.flo = rec[R_FLO * stride];
+    r.st.fhi = rec[R_FHI * stride];
+    if constexpr (ORDER == 1) {
+        r.fwlo = rec[R_FWLO * stride];
+        r.fwhi = rec[R_FWHI * stride];
+    } else {
+        r.st.ii = rec[R_II * stride];
+        r.st.ps = rec[R_PS * stride];
+        r.st.l0 = rec[R_L0 * stride];
+        r.st.l1 = rec[R_L1 * stride];
+        r.st.g0l = rec[R_G0L * stride];
+        r.st.g0h = rec[R_G0H * stride];
+        r.st.g1l = rec[R_G1L * stride];
+        r.st.g1h = rec[R_G1H * stride];
+    }
 }
 
 // Two states make the same cut decisions for every continuation when their
-// FSR extremes agree and, for SSR, each value's S2 gap extremes and the
-// distance back to its latest occurrence agree (piece-local indices differ
-// by a constant shift, which no decision sees).
+// FSR extremes agree and, for SSR, the same values occurred in the open
+// piece, at the same distance back, with the same S2 gap extremes (interval
+// numbers of the two runs differ by a constant shift, which no decision sees).
 template <int ORDER>
 __device__ __forceinline__ bool same_decisions(const SegState &a, const SegState &b)
 {
@@ -511,10 +546,13 @@ __device__ __forceinline__ bool same_decisions(const SegState &a, const SegState
     if constexpr (ORDER == 1) {
         return true;
     } else {
-        const int32_t a0 = a.l0 < 0 ? -1 : a.np - a.l0, b0 = b.l0 < 0 ? -1 : b.np - b.l0;
-        const int32_t a1 = a.l1 < 0 ? -1 : a.np - a.l1, b1 = b.l1 < 0 ? -1 : b.np - b.l1;
-        return a0 == b0 && a1 == b1 && a.g0l == b.g0l && a.g0h == b.g0h && a.g1l == b.g1l &&
-               a.g1h == b.g1h;
+        const bool a0 = a.l0 >= a.ps, b0 = b.l0 >= b.ps, a1 = a.l1 >= a.ps, b1 = b.l1 >= b.ps;
+        if (a0 != b0 || a1 != b1) return false;
+        if (a0 && (a.ii - a.l0 != b.ii - b.l0 || a.g0l != b.g0l || a.g0h != b.g0h))
+            return false;
+        if (a1 && (a.ii - a.l1 != b.ii - b.l1 || a.g1l != b.g1l || a.g1h != b.g1h))
+            return false;
+        return true;
     }
 }
 
@@ -564,7 +602,7 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
             if constexpr (CHUNKED) {
                 if (t == tile0 && rec_start) {
                     // the speculative state the fixup pass starts from
-                    if (em.valid) save_run(rec_start, fstride, run);
+                    if (em.valid) save_run<ORDER>(rec_start, fstride, run);
                     cum_base = run.cum;
                 }
                 // the first tiles of a later chunk keep what the fixup needs

@@ -32,7 +32,7 @@ struct ReconParams {
 enum Mode { MODE_RECON = 0, MODE_SEGMENTS = 1 };
 
 // Fields of one per-chunk state record.
-constexpr int kRecFields = 21;
+constexpr int kRecFields = 20;
 
 // How a stream is cut into time chunks processed by separate waves.
 struct ChunkPlan {
