@@ -242,9 +242,9 @@ enum ConvKind {
 
 struct ConvArgs {
     int B, Hc, Wc;
-    int xtiles, ntiles;
+    int bx, by, nblocks;    // 16x16 output blocks per row / column, in all
     const uint32_t *win;    // CK_FIRST
-    const float *scalar;    // CK_FIRST: estimate; CK_DGRAD_LAST: dL/dy
+    const float *scalar;    // CK_FIRST, CK_LAST: estimate; CK_DGRAD_LAST: dL/dy
     const __bf16 *act;      // source activations / gradients (NHWC, 32 ch)
     const __bf16 *packed;   // this layer's packed B operand
     const float *bias;      // forward layers
@@ -268,44 +268,22 @@ __device__ __forceinline__ bf16x8 bits_to_bf16(uint32_t bits)
     return v;
 }
 
-template <int KIND>
-__device__ __forceinline__ bf16x8 a_operand(const ConvArgs &A, int b, int y, int x, int s, int g)
-{
-    bf16x8 v;
-#pragma unroll
-    for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
-    if constexpr (KIND == CK_FIRST || KIND == CK_DGRAD_LAST) {
-        const bool scalar_step = KIND == CK_DGRAD_LAST || s == 9;
-        if (scalar_step) {
-            // row k = tap k of the scalar channel (estimate or dL/dy)
-#pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int k = g * 8 + e;
-                if (k < 9) {
-                    const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
-                    if (yy >= 0 && yy < A.Hc && xx >= 0 && xx < A.Wc)
-                        v[e] = (__bf16)A.scalar[((int64_t)b * A.Hc + yy) * A.Wc + xx];
-                }
-            }
-            return v;
-        }
-    }
-    const int yy = y + s / 3 - 1, xx = x + s % 3 - 1;
-    if (yy < 0 || yy >= A.Hc || xx < 0 || xx >= A.Wc) return v;
-    const int64_t pix = ((int64_t)b * A.Hc + yy) * A.Wc + xx;
-    if constexpr (KIND == CK_FIRST) {
-        return bits_to_bf16((A.win[pix] >> (8 * g)) & 0xFFu);
-    } else {
-        return *(const bf16x8 *)(A.act + pix * C + 8 * g);
-    }
-}
-
+// A workgroup computes a 16 x 16 block of output pixels, all 32 output
+// channels; wave w takes block rows 4w .. 4w+3.  The 18 x 18 input halo is
+// staged once in LDS (NHWC bfloat16, 64 bytes per pixel, so every A
+// fragment -- 16 pixels x 8 channels -- is one aligned 16-byte read per
+// lane); a scalar input channel (estimate, or dL/dy for the last layer's
+// input gradient) is staged beside it as float.
 template <int KIND>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
 {
     using S = ConvShape<KIND>;
-    __shared__ __bf16 stage[4][16 * C];  // one 16-pixel x 32-channel tile per wave
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr bool VEC_IN = KIND != CK_DGRAD_LAST;              // 32-channel input
+    constexpr bool SCALAR_IN = KIND == CK_FIRST || KIND == CK_DGRAD_LAST;
+    __shared__ __attribute__((aligned(16))) __bf16 tin[VEC_IN ? 18 * 18 * C : 8];
+    __shared__ float tsc[SCALAR_IN ? 18 * 18 : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 stage[4][16 * C];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, g = lane >> 4;
     // this layer's weights, resident in registers
     bf16x8 Bop[S::steps][S::nb];
@@ -321,62 +299,110 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
         if constexpr (KIND == CK_FIRST || KIND == CK_MID) bias[n] = A.bias[n * 16 + i];
         if constexpr (KIND == CK_LAST) bias[n] = A.bias[0];
     }
-    const int nwaves = gridDim.x * 4;
-    for (int t = blockIdx.x * 4 + wave; t < A.ntiles; t += nwaves) {
-        const int b = t / (A.Hc * A.xtiles);
-        const int y = (t / A.xtiles) % A.Hc;
-        const int x0 = (t % A.xtiles) * 16;
-        f32x4 acc[S::nb];
+    for (int blk = blockIdx.x; blk < A.nblocks; blk += gridDim.x) {
+        const int b = blk / (A.bx * A.by);
+        const int y0 = ((blk / A.bx) % A.by) * 16, x0 = (blk % A.bx) * 16;
+        // stage the halo: rows y0-1 .. y0+16, columns x0-1 .. x0+16
+        if constexpr (VEC_IN) {
+            for (int it = tid; it < 18 * 18 * 4; it += 256) {
+                const int q = it >> 2, part = it & 3;
+                const int y = y0 - 1 + q / 18, x = x0 - 1 + q % 18;
+                bf16x8 v;
 #pragma unroll
-        for (int n = 0; n < S::nb; n++) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
+                if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc) {
+                    const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+                    if constexpr (KIND == CK_FIRST) v = bits_to_bf16((A.win[pix] >> (8 * part)) & 0xFFu);
+                    else v = *(const bf16x8 *)(A.act + pix * C + part * 8);
+                }
+                *(bf16x8 *)(&tin[q * C + part * 8]) = v;
+            }
+        }
+        if constexpr (SCALAR_IN) {
+            for (int q = tid; q < 18 * 18; q += 256) {
+                const int y = y0 - 1 + q / 18, x = x0 - 1 + q % 18;
+                float v = 0.0f;
+                if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc)
+                    v = A.scalar[((int64_t)b * A.Hc + y) * A.Wc + x];
+                tsc[q] = v;
+            }
+        }
+        __syncthreads();
+        f32x4 acc[4][S::nb];
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int n = 0; n < S::nb; n++) acc[r][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < S::steps; s++) {
-            const bf16x8 a = a_operand<KIND>(A, b, y, x0 + i, s, g);
 #pragma unroll
-            for (int n = 0; n < S::nb; n++)
-                acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[s][n], acc[n], 0, 0, 0);
+            for (int r = 0; r < 4; r++) {
+                const int oy = 4 * wave + r;  // block row of the output
+                bf16x8 a;
+                const bool scalar_step = KIND == CK_DGRAD_LAST || (KIND == CK_FIRST && s == 9);
+                if (scalar_step) {
+                    // row k of the K block = tap k of the scalar channel
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        const int k = g * 8 + e;
+                        a[e] = k < 9 ? (__bf16)tsc[(oy + k / 3) * 18 + i + k % 3] : (__bf16)0.0f;
+                    }
+                } else {
+                    a = *(const bf16x8 *)(&tin[((oy + s / 3) * 18 + i + s % 3) * C + 8 * g]);
+                }
+#pragma unroll
+                for (int n = 0; n < S::nb; n++)
+                    acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[s][n], acc[r][n], 0, 0, 0);
+            }
         }
-        // lane holds D[pixel 4g + r][channel 16n + i]
-        if constexpr (KIND == CK_LAST) {
-            // residual on the plain short-window estimate
-            if (i == 0) {
+        // lane holds D[pixel 4g + e][channel 16n + i] of each block row
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int x = x0 + 4 * g + r;
-                    if (x < A.Wc) {
-                        const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                        A.out_f32[pix] = A.scalar[pix] + (acc[0][r] + bias[0]);
+        for (int r = 0; r < 4; r++) {
+            const int y = y0 + 4 * wave + r;
+            if constexpr (KIND == CK_LAST) {
+                // residual on the plain short-window estimate
+                if (i == 0 && y < A.Hc) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int x = x0 + 4 * g + e;
+                        if (x < A.Wc) {
+                            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+                            A.out_f32[pix] = A.scalar[pix] + (acc[r][0][e] + bias[0]);
+                        }
                     }
                 }
-            }
-        } else {
+            } else {
 #pragma unroll
-            for (int n = 0; n < S::nb; n++)
+                for (int n = 0; n < S::nb; n++)
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    float v = acc[n][r] + bias[n];
-                    if constexpr (KIND == CK_FIRST || KIND == CK_MID) v = fmaxf(v, 0.0f);
-                    stage[wave][(4 * g + r) * C + 16 * n + i] = to_bf16(v);
+                    for (int e = 0; e < 4; e++) {
+                        float v = acc[r][n][e] + bias[n];
+                        if constexpr (KIND == CK_FIRST || KIND == CK_MID) v = fmaxf(v, 0.0f);
+                        stage[wave][(4 * g + e) * C + 16 * n + i] = to_bf16(v);
+                    }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // each lane writes 8 channels of one pixel: pixel lane/4, part lane%4
+                const int px = lane >> 2, part = lane & 3;
+                const int x = x0 + px;
+                bf16x8 v = *(const bf16x8 *)(&stage[wave][px * C + part * 8]);
+                if (x < A.Wc && y < A.Hc) {
+                    const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+                    if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
+                        const bf16x8 m = *(const bf16x8 *)(A.mask + pix * C + part * 8);
+#pragma unroll
+                        for (int e = 0; e < 8; e++)
+                            if (!((float)m[e] > 0.0f)) v[e] = (__bf16)0.0f;
+                    }
+                    *(bf16x8 *)(A.out + pix * C + part * 8) = v;
                 }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // each lane writes 8 channels of one pixel: pixel lane/4, part lane%4
-            const int px = lane >> 2, part = lane & 3;
-            const int x = x0 + px;
-            bf16x8 v = *(const bf16x8 *)(&stage[wave][px * C + part * 8]);
-            if (x < A.Wc) {
-                const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
-                    const bf16x8 m = *(const bf16x8 *)(A.mask + pix * C + part * 8);
-#pragma unroll
-                    for (int e = 0; e < 8; e++)
-                        if (!((float)m[e] > 0.0f)) v[e] = (__bf16)0.0f;
-                }
-                *(bf16x8 *)(A.out + pix * C + part * 8) = v;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __builtin_amdgcn_wave_barrier();
         }
+        __syncthreads();
     }
 }
 
@@ -405,8 +431,21 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *
 }
 
 // ---------------------------------------------------------------------------
-// weight gradients: dW[co][tap][ci] = sum_p g[p][co] * a[p + off(tap)][ci],
-// db[co] = sum_p g[p][co].  One block per 16x16 pixel tile of one image.
+// weight gradients on MFMA: for each tap, dW[co][tap][ci] = sum_p g[p][co] *
+// a[p + off(tap)][ci] is a GEMM with M = output channels, N = input
+// channels and K = pixels.  A workgroup walks 16x16-pixel tiles (grid
+// stride) and stages per tile, channel-major in LDS:
+//   gT[co][px]            the tile's gradients (K contiguous for A);
+//   aT[dx][ci][row][col]  the 18x18 activation halo, once per horizontal
+//                         tap offset dx, so that every B fragment (8
+//                         consecutive pixels of one channel) is an aligned
+//                         16-byte LDS read.
+// Wave w owns output-channel block w>>1 and input-channel block w&1 for all
+// 9 taps (accumulators stay in registers across tiles).  Layer 1 adds a
+// third input block whose column 0 is the estimate channel; layer 4 (one
+// output channel) pads M to 16 and splits the taps over the waves.  Bias
+// gradients are column sums of gT.  Each workgroup writes one partial
+// gradient; reduce_kernel adds the partials in a fixed order.
 
 enum WgKind { WG_FIRST = 0, WG_MID, WG_LAST };
 
@@ -420,71 +459,151 @@ struct WgShape {
 
 struct WgArgs {
     int B, Hc, Wc, tx, ty;       // tiles per row / column
+    int ntiles;
     const __bf16 *g;             // NHWC 32 ch gradients (WG_FIRST, WG_MID)
     const float *gy;             // dL/dy (WG_LAST)
     const __bf16 *a;             // NHWC 32 ch activations (WG_MID, WG_LAST)
     const uint32_t *win;         // WG_FIRST
     const float *est;            // WG_FIRST
-    float *partial;              // [nblocks][np]
+    float *partial;              // [gridDim.x][np]
 };
+
+constexpr int kWgMaxBlocks = 1024;
 
 template <int K>
 __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
 {
     using S = WgShape<K>;
-    // bfloat16 tiles (the values are bfloat16 already): gradients of the
-    // 256 pixels, activations of the 18 x 18 pixels around them
-    __shared__ __bf16 gs[256][S::cout == 1 ? 1 : 34];
-    __shared__ __bf16 as[18 * 18][S::cin + 1];
-    const int tid = threadIdx.x;
-    const int blk = blockIdx.x;
-    const int b = blk / (A.tx * A.ty);
-    const int ty0 = ((blk / A.tx) % A.ty) * 16, tx0 = (blk % A.tx) * 16;
-    // gradient tile
-    for (int idx = tid; idx < 256 * S::cout; idx += 256) {
-        const int px = idx / S::cout, c = idx % S::cout;
-        const int y = ty0 + px / 16, x = tx0 + px % 16;
-        float v = 0.0f;
-        if (y < A.Hc && x < A.Wc) {
-            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-            if constexpr (K == WG_LAST) v = A.gy[pix];
-            else v = (float)A.g[pix * C + c];
-        }
-        gs[px][c] = to_bf16(v);
-    }
-    // activation tile, rows ty0-1 .. ty0+16, columns tx0-1 .. tx0+16
-    for (int idx = tid; idx < 18 * 18 * S::cin; idx += 256) {
-        const int q = idx / S::cin, c = idx % S::cin;
-        const int y = ty0 - 1 + q / 18, x = tx0 - 1 + q % 18;
-        float v = 0.0f;
-        if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc) {
-            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-            if constexpr (K == WG_FIRST) {
-                v = c < 32 ? (float)((A.win[pix] >> c) & 1u) : (float)to_bf16(A.est[pix]);
-            } else {
-                v = (float)A.a[pix * C + c];
-            }
-        }
-        as[q][c] = to_bf16(v);
-    }
-    __syncthreads();
-    float *out = A.partial + (int64_t)blk * S::np;
-    // each thread owns weights w = tid, tid + 256, ... (fixed summation order)
-    for (int w = tid; w < S::np; w += 256) {
-        float acc = 0.0f;
-        if (w < S::nw) {
-            const int co = w / (9 * S::cin), tap = (w / S::cin) % 9, ci = w % S::cin;
-            const int dy = tap / 3, dx = tap % 3;
-            for (int px = 0; px < 256; px++) {
-                const int q = (px / 16 + dy) * 18 + (px % 16 + dx);
-                acc += (float)gs[px][co] * (float)as[q][ci];
-            }
+    constexpr int CO = S::cout;                   // staged gradient channels
+    constexpr int NE = K == WG_FIRST ? 1 : 0;     // estimate channel planes
+    __shared__ __attribute__((aligned(16))) __bf16 gT[CO][256];
+    __shared__ __attribute__((aligned(16))) __bf16 aT[3][32 + NE][18][16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = lane & 15, gq = lane >> 4;
+    // this wave's blocks
+    const int cb = K == WG_LAST ? 0 : wave >> 1;
+    const int jb = wave & 1;
+    const int tap0 = K == WG_LAST ? (wave >> 1) * 5 : 0;
+    const int tap1 = K == WG_LAST ? (wave >> 1 ? 9 : 5) : 9;
+    f32x4 acc[9], acce[9];
+#pragma unroll
+    for (int t = 0; t < 9; t++) acc[t] = acce[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;  // bias partial of thread tid: channel tid / 8, pixels (tid % 8) * 32 ..
+
+    for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+        const int b = tile / (A.tx * A.ty);
+        const int ty0 = ((tile / A.tx) % A.ty) * 16, tx0 = (tile % A.tx) * 16;
+        // gradients of the tile, channel-major
+        if constexpr (K == WG_LAST) {
+            const int px = tid, y = ty0 + px / 16, x = tx0 + px % 16;
+            float v = 0.0f;
+            if (y < A.Hc && x < A.Wc) v = A.gy[((int64_t)b * A.Hc + y) * A.Wc + x];
+            gT[0][px] = to_bf16(v);
         } else {
-            const int co = w - S::nw;
-            for (int px = 0; px < 256; px++) acc += (float)gs[px][co];
+            for (int it = tid; it < 256 * 4; it += 256) {
+                const int px = it >> 2, part = it & 3;
+                const int y = ty0 + px / 16, x = tx0 + px % 16;
+                bf16x8 v;
+#pragma unroll
+                for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
+                if (y < A.Hc && x < A.Wc)
+                    v = *(const bf16x8 *)(A.g + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8);
+#pragma unroll
+                for (int e = 0; e < 8; e++) gT[part * 8 + e][px] = v[e];
+            }
         }
-        out[w] = acc;
+        // activation halo, rows ty0-1 .. ty0+16, columns tx0-1 .. tx0+16,
+        // written once per horizontal tap offset
+        for (int it = tid; it < 18 * 18 * (4 + NE); it += 256) {
+            const int q = it / (4 + NE), part = it % (4 + NE);
+            const int r = q / 18, c = q % 18;
+            const int y = ty0 - 1 + r, x = tx0 - 1 + c;
+            const bool in = y >= 0 && y < A.Hc && x >= 0 && x < A.Wc;
+            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+            if (part < 4) {
+                bf16x8 v;
+#pragma unroll
+                for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
+                if (in) {
+                    if constexpr (K == WG_FIRST) v = bits_to_bf16((A.win[pix] >> (8 * part)) & 0xFFu);
+                    else v = *(const bf16x8 *)(A.a + pix * C + part * 8);
+                }
+#pragma unroll
+                for (int dx = 0; dx < 3; dx++) {
+                    const int cc = c - dx;
+                    if (cc >= 0 && cc < 16)
+#pragma unroll
+                        for (int e = 0; e < 8; e++) aT[dx][part * 8 + e][r][cc] = v[e];
+                }
+            } else if constexpr (NE) {
+                const __bf16 v = in ? to_bf16(A.est[pix]) : (__bf16)0.0f;
+#pragma unroll
+                for (int dx = 0; dx < 3; dx++) {
+                    const int cc = c - dx;
+                    if (cc >= 0 && cc < 16) aT[dx][32][r][cc] = v;
+                }
+            }
+        }
+        __syncthreads();
+        // A fragments: gradients of channel cb*16 + i, pixels 32s + 8gq .. +7
+        bf16x8 Af[8];
+#pragma unroll
+        for (int s = 0; s < 8; s++) {
+            if constexpr (K == WG_LAST) {
+#pragma unroll
+                for (int e = 0; e < 8; e++) Af[s][e] = (__bf16)0.0f;
+                if (i == 0) Af[s] = *(const bf16x8 *)(&gT[0][32 * s + 8 * gq]);
+            } else {
+                Af[s] = *(const bf16x8 *)(&gT[cb * 16 + i][32 * s + 8 * gq]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 9; t++) {
+            if (t < tap0 || t >= tap1) continue;
+            const int dy = t / 3, dx = t % 3;
+#pragma unroll
+            for (int s = 0; s < 8; s++) {
+                // pixels 32s + 8gq .. +7: tile row 2s + gq/2, columns 8(gq&1) ..
+                const int row = 2 * s + (gq >> 1) + dy, col = 8 * (gq & 1);
+                const bf16x8 Bf = *(const bf16x8 *)(&aT[dx][jb * 16 + i][row][col]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[s], Bf, acc[t], 0, 0, 0);
+                if constexpr (NE) {
+                    if (jb == 0) {
+                        // estimate channel in column 0 of a third input block
+                        bf16x8 Be;
+#pragma unroll
+                        for (int e = 0; e < 8; e++) Be[e] = (__bf16)0.0f;
+                        if (i == 0) Be = *(const bf16x8 *)(&aT[dx][32][row][col]);
+                        acce[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[s], Be, acce[t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // bias: column sums of the gradient tile
+        if (tid < CO * 8) {
+#pragma unroll 8
+            for (int k = 0; k < 256 / 8; k++) bsum += (float)gT[tid / 8][(tid % 8) * 32 + k];
+        }
+        __syncthreads();
     }
+    // partial gradient of this workgroup, in the parameter blob's order
+    float *out = A.partial + (int64_t)blockIdx.x * S::np;
+#pragma unroll
+    for (int t = 0; t < 9; t++) {
+        if (t < tap0 || t >= tap1) continue;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            // D[co 4*(lane/16) + r][ci lane%16] of this wave's blocks
+            const int co = cb * 16 + 4 * gq + r, ci = jb * 16 + i;
+            if (co < CO) out[(co * 9 + t) * S::cin + ci] = acc[t][r];
+            if constexpr (NE)
+                if (jb == 0 && i == 0) out[(co * 9 + t) * S::cin + 32] = acce[t][r];
+        }
+    }
+    // bias sums: 8 threads per channel, combined in a fixed order
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) bsum += __shfl_xor(bsum, m, 64);
+    if (tid < CO * 8 && tid % 8 == 0) out[S::nw + tid / 8] = bsum;
 }
 
 // dst[j] = sum over blocks of partial[blk][j], blocks in order
@@ -575,22 +694,26 @@ ConvArgs conv_args(int B, int Hc, int Wc)
     a.B = B;
     a.Hc = Hc;
     a.Wc = Wc;
-    a.xtiles = (Wc + 15) / 16;
-    a.ntiles = B * Hc * a.xtiles;
+    a.bx = (Wc + 15) / 16;
+    a.by = (Hc + 15) / 16;
+    a.nblocks = B * a.bx * a.by;
     return a;
 }
+
+constexpr int kConvMaxBlocks = 2048;
 
 template <int KIND>
 void launch_conv(const ConvArgs &a, hipStream_t st)
 {
-    const int blocks = (a.ntiles + 3) / 4 < 2048 ? (a.ntiles + 3) / 4 : 2048;
+    const int blocks = a.nblocks < kConvMaxBlocks ? a.nblocks : kConvMaxBlocks;
     hipLaunchKernelGGL(conv_kernel<KIND>, dim3(blocks), dim3(256), 0, st, a);
 }
 
 template <int K>
 void launch_wgrad(WgArgs a, float *dst, hipStream_t st)
 {
-    const int nblk = a.B * a.tx * a.ty;
+    a.ntiles = a.B * a.tx * a.ty;
+    const int nblk = a.ntiles < kWgMaxBlocks ? a.ntiles : kWgMaxBlocks;
     hipLaunchKernelGGL(wgrad_kernel<K>, dim3(nblk), dim3(256), 0, st, a);
     const int np = WgShape<K>::np;
     hipLaunchKernelGGL(reduce_kernel, dim3((np + 255) / 256), dim3(256), 0, st, a.partial, nblk,
