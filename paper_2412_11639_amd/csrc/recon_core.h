@@ -162,8 +162,9 @@ struct SegState {
     // inside the nonzero word w, c spikes in all -- opens a new segment,
     // apply them all and return true; otherwise change nothing and return
     // false.  FSR: all intervals in [flo, flo + 1] keep the segment stable.
-    // SSR: only words whose intervals all equal one value v, with the S2
-    // gaps of v staying stable (the gaps inside the word are all 1).
+    // SSR: words whose intervals take the values flo and flo + 1 (see
+    // two_values), or all equal one value just below a single-valued
+    // segment.
     template <int ORDER>
     __device__ __forceinline__ bool fast_word(uint64_t w, int32_t x0, int32_t c)
     {
@@ -177,7 +178,20 @@ struct SegState {
             return true;
         } else {
             const int32_t v = x0;
-            if (v < 1 || v > kFastMaxGap || max(fhi, v) - min(flo, v) > 1) return false;
+            if (v >= flo) {
+                // the two-value walk pays off only when most of the wave can
+                // take it (a lane left on the spike path keeps the others
+                // waiting): vote on its cheap preconditions first
+                const int32_t a = flo;
+                const bool pre = a >= 1 && a <= kFastMaxGap && fhi <= a + 1 && x0 <= a + 1 &&
+                                 gaps_within(w, a, true);
+                if (popc64(__ballot(pre)) * 4 < popc64(__ballot(1)) * 3) return false;
+                return pre && two_values(w, x0, c);
+            }
+            if (v < 1 || fhi - v > 1) return false;
+            // the word opens with a value below the segment's single value:
+            // only words of that one value (all S2 gaps inside are 1)
+            if (v > kFastMaxGap) return false;
             if (c > 1 && !gaps_within(w, v, false)) return false;
             const bool odd = v & 1;
             const int32_t l = odd ? l1 : l0;
@@ -205,6 +219,106 @@ struct SegState {
             ii += c;
             return true;
         }
+    }
+
+    // SSR shortcut for a word whose intervals take the values a = flo and
+    // a + 1 (no FSR cut; one of them may be absent), called A and B.  When
+    // one value never occurs twice in a row (it is "isolated"; a
+    // constant-rate pixel always has one, Lemma 2), every S2 gap of the
+    // other value is 1 or 2, so only the
+    // isolated value's gaps need a walk -- over its own occurrences, from
+    // the frame distances between them (k intervals apart means k*a + 1
+    // frames for an isolated B, k*(a+1) - 1 for an isolated A).  All new
+    // gaps of both values must keep each value's S2 span within 1 together
+    // with the piece's gaps so far; then nothing is cut and the state
+    // advances by the whole word.  Otherwise nothing changes (false).
+    // Precondition: 1 <= a <= kFastMaxGap, fhi <= a + 1, x0 in {a, a + 1} and
+    // every gap inside w is a or a + 1.
+    __device__ __forceinline__ bool two_values(uint64_t w, int32_t x0, int32_t c)
+    {
+        const int32_t a = flo;
+        const uint64_t f = w & (~w + 1);             // the word's first spike
+        // spikes whose interval is B: predecessor a + 1 frames back (and not a)
+        uint64_t MB = w & (w << (a + 1)) & ~(w << a) & ~f;
+        if (x0 == a + 1) MB |= f;
+        const uint64_t MA = w & ~MB;
+        const bool oddA = a & 1;
+        const int32_t lA = oddA ? l1 : l0, lB = oddA ? l0 : l1;
+        const bool seenA = lA >= ps, seenB = lB >= ps;
+        // two B (or two A) in a row, inside the word or across its start
+        const bool BB = (MB & (MB << (a + 1))) != 0 || (seenB && lB == ii - 1 && x0 == a + 1);
+        const bool AA = (MA & (MA << a)) != 0 || (seenA && lA == ii - 1 && x0 == a);
+        if (BB && AA) return false;
+        const bool isoB = !BB;  // the walked (isolated) value is B, else A
+        const uint64_t MM = isoB ? MB : MA, MJ = isoB ? MA : MB;
+        const int32_t xM = isoB ? a + 1 : a, xJ = isoB ? a : a + 1;
+        const int32_t lM = isoB ? lB : lA, lJ = isoB ? lA : lB;
+        const bool seenM = isoB ? seenB : seenA, seenJ = isoB ? seenA : seenB;
+        const bool oddM = isoB ? !oddA : oddA;
+        int32_t gMl = oddM ? g1l : g0l, gMh = oddM ? g1h : g0h;
+        int32_t gJl = oddM ? g0l : g1l, gJh = oddM ? g0h : g1h;
+        if (!seenM) { gMl = kBig; gMh = -kBig; }
+        if (!seenJ) { gJl = kBig; gJh = -kBig; }
+        int32_t nlM = lM, nlJ = lJ;
+        // the other value: gaps 1 (twice in a row) and 2 (around one isolated
+        // occurrence) inside the word, and the gap back to its last occurrence
+        if (MJ) {
+            const uint64_t fJ = MJ & (~MJ + 1);
+            const int32_t first = ii + popc64(w & (fJ - 1));
+            if (seenJ) {
+                gJl = min(gJl, first - lJ);
+                gJh = max(gJh, first - lJ);
+            }
+            if (MJ & (MJ << xJ)) {
+                gJl = min(gJl, 1);
+                gJh = max(gJh, 1);
+            }
+            if (MJ & (MM << xJ) & (MJ << (xJ + xM))) {
+                gJl = min(gJl, 2);
+                gJh = max(gJh, 2);
+            }
+            nlJ = ii + popc64(w & ((1ull << hibit64(MJ)) - 1));
+        }
+        if (gJh - gJl > 1) return false;
+        // the isolated value: walk its occurrences
+        if (MM) {
+            const uint64_t fM = MM & (~MM + 1);
+            const int32_t first = ii + popc64(w & (fM - 1));
+            if (seenM) {
+                gMl = min(gMl, first - lM);
+                gMh = max(gMh, first - lM);
+            }
+            uint64_t m = MM & (MM - 1);
+            int32_t prev = ctz64(MM), dmin = kBig, dmax = -kBig;
+            while (m) {
+                const int32_t q = ctz64(m);
+                m &= m - 1;
+                dmin = min(dmin, q - prev);
+                dmax = max(dmax, q - prev);
+                prev = q;
+            }
+            if (dmax >= 0) {
+                // frame distances -> interval counts (exact multiples)
+                const float r = __builtin_amdgcn_rcpf((float)xJ);
+                const int32_t off = isoB ? -1 : 1;
+                gMl = min(gMl, (int32_t)rintf((float)(dmin + off) * r));
+                gMh = max(gMh, (int32_t)rintf((float)(dmax + off) * r));
+            }
+            nlM = ii + popc64(w & ((1ull << prev) - 1));
+        }
+        if (gMh - gMl > 1) return false;
+        fhi = max(fhi, MB ? a + 1 : a);
+        const int32_t nlA = isoB ? nlJ : nlM, nlB = isoB ? nlM : nlJ;
+        const int32_t nAl = isoB ? gJl : gMl, nAh = isoB ? gJh : gMh;
+        const int32_t nBl = isoB ? gMl : gJl, nBh = isoB ? gMh : gJh;
+        l0 = oddA ? nlB : nlA;
+        l1 = oddA ? nlA : nlB;
+        g0l = oddA ? nBl : nAl;
+        g0h = oddA ? nBh : nAh;
+        g1l = oddA ? nAl : nBl;
+        g1h = oddA ? nAh : nBh;
+        ii += c;
+        return true;
     }
 
     // Add interval x; returns true if x opens a new segment (the previous

@@ -26,6 +26,12 @@ def spk():
     return m
 
 
+@pytest.fixture
+def chunks(spk):
+    yield spk.set_time_chunks
+    spk.set_time_chunks(0)
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -101,6 +107,48 @@ def test_gratings_ragged(spk, order):
     check_segments(spk, s, H, W, T, order, cap=400)
 
 
+def _two_value_streams(rng, P, T):
+    """Per pixel an interval sequence over {a, a+1} (a = 1..15): balanced
+    (constant-rate) sequences, balanced ones with two neighbours swapped,
+    i.i.d. ones and long runs -- so the two values' S2 streams are stable
+    over long stretches and then break at all kinds of places."""
+    bits = np.zeros((T, P), dtype=np.uint8)
+    for p in range(P):
+        a = 1 + p % 15
+        kind = (p // 15) % 4
+        n = T // a + 2
+        if kind == 0 or kind == 1:
+            frac = rng.uniform(0.02, 0.98)
+            ph = rng.uniform(0, 1)
+            xs = a + (np.floor(frac * np.arange(1, n + 1) + ph)
+                      - np.floor(frac * np.arange(n) + ph)).astype(int)
+            if kind == 1:
+                j = int(rng.integers(1, max(2, n - 2)))
+                xs[j], xs[j + 1] = xs[j + 1], xs[j]
+        elif kind == 2:
+            xs = a + (rng.random(n) < rng.choice([0.1, 0.5, 0.9])).astype(int)
+        else:
+            xs = a + (np.arange(n) // int(rng.integers(1, 6)) % 2)
+        tau = int(rng.integers(0, a + 1)) + np.concatenate([[0], np.cumsum(xs)])
+        tau = tau[tau < T]
+        bits[tau, p] = 1
+    return bits
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("n_chunks", [0, 3, 24])
+def test_two_value_words(spk, chunks, order, n_chunks):
+    """Streams whose intervals take two adjacent values (the word-level SSR
+    shortcut's domain), against the oracle, unchunked and chunked."""
+    chunks(n_chunks)
+    rng = np.random.default_rng(11)
+    H, W, T = 6, 120, 1500
+    bits = _two_value_streams(rng, H * W, T)
+    s = spkgen.pack(bits)
+    check_recon(spk, s, H, W, T, list(range(0, T, 7)) + [T - 1], order)
+    check_segments(spk, s, H, W, T, order, cap=T)
+
+
 @pytest.mark.parametrize("order", [1, 2])
 def test_moving_blocks(spk, order):
     H, W, T = 64, 80, 2048
@@ -173,12 +221,6 @@ def _full_gratings():
     if "g" not in _CACHE:
         _CACHE["g"] = spkgen.gratings(250, 400, 20000, seed=2)
     return _CACHE["g"]
-
-
-@pytest.fixture
-def chunks(spk):
-    yield spk.set_time_chunks
-    spk.set_time_chunks(0)
 
 
 @pytest.mark.parametrize("order", [1, 2])
