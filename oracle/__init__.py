@@ -16,6 +16,7 @@ import numpy as np
 
 FSR = 1
 SSR = 2
+TFI = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -48,6 +49,9 @@ def _bind(lib):
         ctypes.c_int32, ctypes.c_int32, P_f64, P_i32, P_i32, P_i32, ctypes.c_int32]
     lib.spk_oracle_reconstruct_causal.restype = ctypes.c_int32
     lib.spk_oracle_reconstruct_causal.argtypes = lib.spk_oracle_reconstruct.argtypes
+    lib.spk_oracle_tfp.restype = ctypes.c_int32
+    lib.spk_oracle_tfp.argtypes = [P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_double, ctypes.c_int32, P_i32, ctypes.c_int32, P_f64]
     lib.spk_oracle_window.restype = ctypes.c_int32
     lib.spk_oracle_window.argtypes = [P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, P_f64,
@@ -115,6 +119,20 @@ def reconstruct(stream, H, W, T, theta, t_out, order=FSR, windows=False, nthread
     if rc != 0:
         raise ValueError("spk_oracle_reconstruct: bad arguments")
     return (out, wf, wl, wn) if windows else out
+
+
+def tfp(stream, H, W, T, theta, window, t_out, lib=None):
+    """TFP: theta * (spikes in the window of ``window`` frames ending at t)
+    / window length, [n_out, H, W] float64."""
+    lib = lib or load()
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    t_out = np.ascontiguousarray(t_out, dtype=np.int32)
+    out = np.zeros((len(t_out), H, W), dtype=np.float64)
+    rc = lib.spk_oracle_tfp(_ptr(stream, P_u8), H, W, T, float(theta), int(window),
+                            _ptr(t_out, P_i32), len(t_out), _ptr(out, P_f64))
+    if rc != 0:
+        raise ValueError("spk_oracle_tfp: bad arguments")
+    return out
 
 
 def segments(stream, H, W, T, order=FSR, cap=64, nthreads=None, lib=None):

@@ -21,6 +21,9 @@
  *                                                    (Sec. III-B, Fig. 1 caption)
  *   O-6 output time   the segment holding the interval in progress at t
  *   O-7 intensity     I = theta * N / sum_i T0(i)                 (Eq. 6)
+ * Baselines the paper compares against (Sec. II): TFI (every interval its
+ * own segment, so I = theta / T0) as a third segmentation order, and TFP
+ * (spike count over a fixed window).
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes of the repository):
@@ -42,6 +45,8 @@
 
 #define ORACLE_FSR 1
 #define ORACLE_SSR 2
+#define ORACLE_TFI 3
+#define ORACLE_ORDER_OK(o) ((o) == ORACLE_FSR || (o) == ORACLE_SSR || (o) == ORACLE_TFI)
 
 /* ---- O-1: spike frames of pixel p (Eq. 2: P(n) = 1 marks a spike) ------ */
 static int32_t spikes_of_pixel(const uint8_t *stream, size_t fb, int32_t T, int64_t p,
@@ -142,6 +147,11 @@ static int32_t ssr_refine(const int32_t *x, int32_t s, int32_t e, int32_t *start
 static int32_t segment_intervals(const int32_t *x, int32_t n, int32_t order, int32_t *start,
                                  int32_t *work)
 {
+    if (order == ORACLE_TFI) {
+        /* TFI (Sec. II): every interval on its own, intensity theta / T0(i) */
+        for (int32_t i = 0; i < n; i++) start[i] = i;
+        return n;
+    }
     int32_t nf = fsr_segments(x, n, order == ORACLE_FSR ? start : work);
     if (order == ORACLE_FSR) return nf;
     int32_t ns = 0;
@@ -157,7 +167,7 @@ static int32_t segment_intervals(const int32_t *x, int32_t n, int32_t order, int
 int32_t spk_oracle_segment_intervals(const int32_t *x, int32_t n, int32_t order,
                                      int32_t *start)
 {
-    if (n < 0 || (n > 0 && (!x || !start)) || (order != ORACLE_FSR && order != ORACLE_SSR))
+    if (n < 0 || (n > 0 && (!x || !start)) || !ORACLE_ORDER_OK(order))
         return -1;
     int32_t *work = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     if (!work) return -2;
@@ -323,7 +333,7 @@ int32_t spk_oracle_reconstruct(const uint8_t *stream, int32_t H, int32_t W, int3
                                int32_t *win_last, int32_t *win_n, int32_t nthreads)
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0 || n_out < 0 || (n_out > 0 && !t_out) ||
-        (order != ORACLE_FSR && order != ORACLE_SSR))
+        !ORACLE_ORDER_OK(order))
         return -1;
     for (int32_t k = 0; k < n_out; k++)
         if (t_out[k] < 0 || t_out[k] >= T) return -1;
@@ -355,7 +365,7 @@ int32_t spk_oracle_reconstruct_causal(const uint8_t *stream, int32_t H, int32_t 
                                       int32_t *win_last, int32_t *win_n, int32_t nthreads)
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0 || n_out < 0 || (n_out > 0 && !t_out) ||
-        (order != ORACLE_FSR && order != ORACLE_SSR))
+        !ORACLE_ORDER_OK(order))
         return -1;
     for (int32_t k = 0; k < n_out; k++)
         if (t_out[k] < 0 || t_out[k] >= T) return -1;
@@ -389,7 +399,7 @@ int32_t spk_oracle_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0 || cap < 0 || !count ||
         (cap > 0 && (!seg_first || !seg_last || !seg_n)) ||
-        (order != ORACLE_FSR && order != ORACLE_SSR))
+        !ORACLE_ORDER_OK(order))
         return -1;
     task_t tk;
     memset(&tk, 0, sizeof(tk));
@@ -440,6 +450,33 @@ int32_t spk_oracle_window(const uint8_t *stream, int32_t H, int32_t W, int32_t T
         int32_t cnt = (K - 1) - a;
         est[p] = theta * (double)cnt / (double)(tau[K - 1] - tau[a]);
         stable[p] = nseg == 1;
+    }
+    return 0;
+}
+
+/* ---- TFP (Sec. II): spikes counted in a virtual exposure window of L
+ * frames ending at the output frame, intensity theta * N_spk / L.  The
+ * window is clipped at the stream's start (L = min(window, t + 1)).
+ * out is [n_out][H*W]. */
+int32_t spk_oracle_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, double theta,
+                       int32_t window, const int32_t *t_out, int32_t n_out, double *out)
+{
+    if (!stream || H <= 0 || W <= 0 || T <= 0 || window < 1 || n_out < 0 ||
+        (n_out > 0 && (!t_out || !out)))
+        return -1;
+    for (int32_t k = 0; k < n_out; k++)
+        if (t_out[k] < 0 || t_out[k] >= T) return -1;
+    size_t fb = frame_bytes(H, W);
+    int64_t hw = (int64_t)H * W;
+    for (int32_t k = 0; k < n_out; k++) {
+        int32_t t = t_out[k];
+        int32_t f0 = t - window + 1 < 0 ? 0 : t - window + 1;
+        for (int64_t p = 0; p < hw; p++) {
+            int32_t cnt = 0;
+            for (int32_t f = f0; f <= t; f++)
+                cnt += (stream[(size_t)f * fb + (size_t)(p >> 3)] >> (p & 7)) & 1;
+            out[(int64_t)k * hw + p] = theta * (double)cnt / (double)(t - f0 + 1);
+        }
     }
     return 0;
 }

@@ -36,6 +36,10 @@ MUTANTS = {
                                    "spikes_before(sc->tau, K, tk->t_out[k])"),
     "causal_untruncated": ("                last = sc->tau[i + 1];",
                            "                last = sc->tau[i + 1 < K - 1 ? i + 2 : i + 1];"),
+    "tfi_merges_pairs": ("for (int32_t i = 0; i < n; i++) start[i] = i;\n        return n;",
+                         "for (int32_t i = 0; i < n; i++) start[i / 2] = i & ~1;\n        return (n + 1) / 2;"),
+    "tfp_window_off_by_one": ("int32_t f0 = t - window + 1 < 0 ? 0 : t - window + 1;",
+                              "int32_t f0 = t - window < 0 ? 0 : t - window;"),
     "first_segment_start": ("    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0];",
                             "    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0] + 1;"),
 }
@@ -90,6 +94,24 @@ def _battery(lib):
     out = oracle.reconstruct(s, 1, 8, 300, 1.0, [0, 150, 299], lib=lib)
     if not np.all(out[:, 0, :] == (Q / th)[None, :]):
         failed.append("exact_intensity")
+    # TFI = reciprocal of the interval in progress; TFP = windowed count
+    Qv = np.array([3, 5, 7, 11, 13, 17, 19, 23], dtype=np.int64)
+    s = spkgen.from_increments(Qv, v0, th, 1, 8, T=300)
+    t_chk = list(range(100, 160))
+    tfi = oracle.reconstruct(s, 1, 8, 300, 1.0, t_chk, order=oracle.TFI, lib=lib)
+    bits = spkgen.unpack(s, 1, 8).reshape(300, -1)
+    ok = True
+    for q in range(8):
+        tau = np.flatnonzero(bits[:, q]).tolist()
+        for k, t in enumerate(t_chk):
+            m = brute.interval_in_progress(tau, t)
+            ok = ok and tfi[k, 0, q] == 1.0 / (tau[m] - tau[m - 1])
+    if not ok:
+        failed.append("tfi")
+    tp = oracle.tfp(s, 1, 8, 300, 1.0, 10, [100], lib=lib)
+    cnt = bits[91:101].sum(axis=0)
+    if not np.array_equal(tp[0, 0], cnt / 10.0):
+        failed.append("tfp")
     # causal reading == the method on each prefix
     H, W, T = 4, 9, 60
     s = spkgen.blocks(H, W, T, seed=62, block=3, vx=0.7)

@@ -335,7 +335,9 @@ def test_argument_errors():
     with pytest.raises(ValueError):
         oracle.reconstruct(s, 1, 8, 4, 1.0, [4])          # t out of range
     with pytest.raises(ValueError):
-        oracle.reconstruct(s, 1, 8, 4, 1.0, [0], order=3)  # unknown order
+        oracle.reconstruct(s, 1, 8, 4, 1.0, [0], order=4)  # unknown order
+    with pytest.raises(ValueError):
+        oracle.tfp(s, 1, 8, 4, 1.0, 0, [0])                # empty window
 
 
 @pytest.mark.parametrize("order", [oracle.FSR, oracle.SSR])
@@ -377,3 +379,84 @@ def test_causal_reading_bruteforce():
             parts = brute.enumerate_partitions(x, lambda st: brute.is_fsr_partition(x, st))
             a = parts[0][-1]
             assert got[t, p] == len(x[a:]) / (tt[-1] - tt[a]), (p, t, tt)
+
+
+# --------------------------------------------------------------------------
+# the baselines themselves (Sec. II): TFI as the order that keeps every
+# interval on its own, TFP as a windowed spike count
+
+def test_tfi_order_is_reciprocal_interval():
+    """TFI: the estimate at t is theta / T0(m(t)) with window (tau_m,
+    tau_m+1, 1), on streams whose intervals repeat and alternate (where FSR
+    and SSR merge them) as well as on noisy ones; fewer than two spikes give
+    0 and (-1, -1, 0)."""
+    H, W, T = 3, 40, 300
+    s = spkgen.gratings(H, W, T, seed=41)
+    bits = spkgen.unpack(s, H, W).reshape(T, -1)
+    bits[:, 0] = 0
+    bits[:, 1] = 0
+    bits[7, 1] = 1
+    bits[:, 2] = 0
+    bits[::3, 2] = 1
+    s = spkgen.pack(bits)
+    t_out = np.arange(T, dtype=np.int32)
+    out, wf, wl, wn = oracle.reconstruct(s, H, W, T, 2.0, t_out, order=oracle.TFI, windows=True)
+    out, wf, wl, wn = (a.reshape(T, -1) for a in (out, wf, wl, wn))
+    for p in range(H * W):
+        tau = _spike_frames(bits[:, p])
+        for t in range(T):
+            if len(tau) < 2:
+                assert (out[t, p], wf[t, p], wl[t, p], wn[t, p]) == (0.0, -1, -1, 0)
+                continue
+            m = brute.interval_in_progress(tau, t)
+            x = tau[m] - tau[m - 1]
+            assert (wf[t, p], wl[t, p], wn[t, p]) == (tau[m - 1], tau[m], 1)
+            assert out[t, p] == 2.0 / x
+
+
+def test_tfi_equals_fsr_when_neighbours_differ_by_two():
+    """Where no two neighbouring intervals are within 1 of each other, FSR
+    and SSR keep every interval alone: all three orders agree exactly."""
+    rng = np.random.default_rng(6)
+    T = 800
+    bits = np.zeros((T, 64), dtype=np.uint8)
+    for p in range(64):
+        t, prev = int(rng.integers(0, 5)), None
+        while t < T:
+            bits[t, p] = 1
+            while True:
+                x = int(rng.integers(1, 40))
+                if prev is None or abs(x - prev) >= 2:
+                    break
+            prev = x
+            t += x
+    s = spkgen.pack(bits)
+    t_out = np.arange(0, T, 3, dtype=np.int32)
+    ref = oracle.reconstruct(s, 1, 64, T, 1.0, t_out, order=oracle.TFI)
+    for order in (oracle.FSR, oracle.SSR):
+        np.testing.assert_array_equal(oracle.reconstruct(s, 1, 64, T, 1.0, t_out, order=order), ref)
+
+
+@pytest.mark.parametrize("window", [1, 7, 32, 64, 300])
+def test_tfp_constant_rate_closed_form(window):
+    """TFP on constant light (Eq. 2 with a constant increment): the window
+    count is C(t) - C(t - L), C(n) = floor((V0 + (n+1) Q) / theta) spikes
+    up to frame n, and the estimate is within theta / L of the rate."""
+    rng = np.random.default_rng(window)
+    H, W, T = 2, 64, 500
+    th = 1009
+    Q = rng.integers(1, th + 1, size=H * W)
+    v0 = rng.integers(0, th, size=H * W)
+    s = spkgen.from_increments(Q, v0, th, H, W, T=T)
+    t_out = np.array(sorted(set(rng.integers(0, T, 60).tolist() + [0, window - 1, T - 1]) & set(range(T))),
+                     dtype=np.int32)
+    out = oracle.tfp(s, H, W, T, 3.0, window, t_out).reshape(len(t_out), -1)
+
+    def C(n):
+        return np.where(n < 0, 0, (v0 + (n + 1) * Q) // th)
+
+    for k, t in enumerate(t_out):
+        L = min(window, int(t) + 1)
+        cnt = C(int(t)) - C(int(t) - L)
+        np.testing.assert_array_equal(out[k], 3.0 * cnt / L)
+        assert np.all(np.abs(out[k] - 3.0 * Q / th) < 3.0 / L + 1e-12)
