@@ -54,7 +54,14 @@ enum {
     SPK_EUNSUPPORTED = -4 /* no usable gfx950 device                       */
 };
 
-enum { SPK_FSR = 1, SPK_SSR = 2 };
+/*
+ * Segmentation orders: SPK_FSR and SPK_SSR are the paper's first- and
+ * second-order stable reconstructions (Sec. III-B).  SPK_TFI is the TFI
+ * baseline the paper compares against (Sec. II: the reciprocal of the
+ * interval between the two spikes around the output frame), run as the
+ * order that keeps every interval on its own (windows have N = 1).
+ */
+enum { SPK_FSR = 1, SPK_SSR = 2, SPK_TFI = 3 };
 
 /* Bytes per packed frame: ceil(H*W / 128) * 16.  0 if H or W <= 0. */
 size_t spk_frame_bytes(int32_t H, int32_t W);
@@ -112,6 +119,16 @@ int spk_reconstruct_windows(const uint8_t *stream, int32_t H, int32_t W, int32_t
 int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
                  int32_t cap, int32_t *seg_first, int32_t *seg_last, int32_t *seg_n,
                  int32_t *count, void *hip_stream);
+
+/*
+ * TFP baseline (Sec. II): theta * (spikes in the `window` frames ending at
+ * t_out[k]) / (window length), the window clipped at the stream's start
+ * (length min(window, t + 1)); computed as (double)theta * count / length
+ * and rounded once to float.  window >= 1.  out: device float
+ * [n_out][H][W].  Arguments and errors as spk_reconstruct.
+ */
+int spk_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
+            int32_t window, const int32_t *t_out, int32_t n_out, float *out, void *hip_stream);
 
 /*
  * Batched plans: many streams of uneven size reconstructed by one

@@ -6,7 +6,8 @@ device memory and the current HIP stream only.
 
 Method: arXiv 2412.11639 -- inter-spike intervals cut into zero-order stable
 segments at first (FSR) or second (SSR) order, intensity theta*N/duration
-per segment (Eq. 6).
+per segment (Eq. 6).  The baselines it is compared with (Sec. II): TFI as a
+third order (every interval alone) and TFP (``tfp``, windowed spike counts).
 """
 from __future__ import annotations
 
@@ -18,8 +19,9 @@ from ._lib import SpkError
 
 FSR = 1
 SSR = 2
+TFI = 3
 
-__all__ = ["FSR", "SSR", "SpkError", "frame_bytes", "reconstruct", "reconstruct_windows",
+__all__ = ["FSR", "SSR", "TFI", "SpkError", "tfp", "frame_bytes", "reconstruct", "reconstruct_windows",
            "segments", "version", "set_time_chunks", "get_time_chunks", "Plan",
            "PLAN_AUTOTUNE", "PLAN_NO_GRAPH"]
 
@@ -84,6 +86,21 @@ def reconstruct(stream_t: torch.Tensor, H: int, W: int, T: int, theta: float, t_
     rc = _lib.load().spk_reconstruct(stream_t.data_ptr(), H, W, T, float(theta), tp, n_out,
                                      out.data_ptr(), order, _stream_handle(stream))
     _lib.check("spk_reconstruct", rc)
+    return out
+
+
+def tfp(stream_t, H, W, T, theta, window, t_out, out=None, stream=None):
+    """TFP baseline: theta * (spikes in the ``window`` frames ending at t) /
+    window length (clipped at frame 0), float32 [n_out, H, W]."""
+    _check_stream_tensor(stream_t, H, W, T)
+    t, tp = _host_times(t_out)
+    n_out = len(t)
+    if out is None:
+        out = torch.empty((n_out, H, W), dtype=torch.float32, device=stream_t.device)
+    assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n_out * H * W
+    rc = _lib.load().spk_tfp(stream_t.data_ptr(), H, W, T, float(theta), int(window), tp, n_out,
+                             out.data_ptr(), _stream_handle(stream))
+    _lib.check("spk_tfp", rc)
     return out
 
 

@@ -190,7 +190,7 @@ int check_common(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0) return SPK_EINVAL;
     if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
-    if (order != SPK_FSR && order != SPK_SSR) return SPK_EINVAL;
+    if (order != SPK_FSR && order != SPK_SSR && order != SPK_TFI) return SPK_EINVAL;
     const size_t fb = spk_frame_bytes(H, W);
     if ((size_t)T > SIZE_MAX / fb) return SPK_EINVAL;
     return SPK_OK;

@@ -188,21 +188,19 @@ void tune_store()
 hipError_t launch_batch(const spk_plan_s *pl, int grid, int grab, hipStream_t st)
 {
     hipLaunchKernelGGL(spk::reset_counters, dim3(1), dim3(64), 0, st, pl->d_counters);
-    if (pl->order == SPK_FSR) {
-        if (pl->identity)
-            hipLaunchKernelGGL((spk::batch_kernel<1, spk::PMAP_IDENT>), dim3(grid), dim3(64), 0,
-                               st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);
-        else
-            hipLaunchKernelGGL((spk::batch_kernel<1, spk::PMAP_GLOBAL>), dim3(grid), dim3(64), 0,
-                               st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);
-    } else {
-        if (pl->identity)
-            hipLaunchKernelGGL((spk::batch_kernel<2, spk::PMAP_IDENT>), dim3(grid), dim3(64), 0,
-                               st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);
-        else
-            hipLaunchKernelGGL((spk::batch_kernel<2, spk::PMAP_GLOBAL>), dim3(grid), dim3(64), 0,
-                               st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);
+#define SPK_BATCH_LAUNCH(O)                                                                  \
+    if (pl->identity)                                                                          \
+        hipLaunchKernelGGL((spk::batch_kernel<O, spk::PMAP_IDENT>), dim3(grid), dim3(64), 0,   \
+                           st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);      \
+    else                                                                                       \
+        hipLaunchKernelGGL((spk::batch_kernel<O, spk::PMAP_GLOBAL>), dim3(grid), dim3(64), 0,  \
+                           st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);
+    switch (pl->order) {
+    case SPK_FSR: SPK_BATCH_LAUNCH(1) break;
+    case SPK_SSR: SPK_BATCH_LAUNCH(2) break;
+    default: SPK_BATCH_LAUNCH(3) break;
     }
+#undef SPK_BATCH_LAUNCH
     return hipGetLastError();
 }
 
@@ -261,7 +259,8 @@ int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32
 {
     if (!plan) return SPK_EINVAL;
     *plan = nullptr;
-    if (!jobs || n_jobs <= 0 || (order != SPK_FSR && order != SPK_SSR)) return SPK_EINVAL;
+    if (!jobs || n_jobs <= 0 || (order != SPK_FSR && order != SPK_SSR && order != SPK_TFI))
+        return SPK_EINVAL;
     if (flags & ~(SPK_PLAN_AUTOTUNE | SPK_PLAN_NO_GRAPH)) return SPK_EINVAL;
     // validate every job before touching the device
     int64_t items = 0;
@@ -299,7 +298,7 @@ int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32
     size_t off = 0;
     int32_t strip = 0;
     char sig[64];
-    pl->signature = order == SPK_FSR ? "fsr" : "ssr";
+    pl->signature = order == SPK_FSR ? "fsr" : (order == SPK_SSR ? "ssr" : "tfi");
     for (int32_t j = 0; j < n_jobs; j++) {
         const spk_job &J = jobs[j];
         std::vector<int32_t> ord(J.n_out);

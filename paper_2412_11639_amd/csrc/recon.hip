@@ -293,14 +293,20 @@ hipError_t launch_recon(const ReconParams &p, int order, Mode mode, const ChunkP
     const bool win = p.win_first || p.win_last || p.win_n || !p.out;
     if (mode == MODE_SEGMENTS) {
         ChunkPlan one;
-        return order == 1 ? launch_one<1, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream)
-                          : launch_one<2, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
+        switch (order) {
+        case 1: return launch_one<1, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
+        case 2: return launch_one<2, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
+        default: return launch_one<3, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
+        }
     }
-    if (win)
-        return order == 1 ? launch_pmap<1, MODE_RECON, true>(p, cp, stream)
-                          : launch_pmap<2, MODE_RECON, true>(p, cp, stream);
-    return order == 1 ? launch_pmap<1, MODE_RECON, false>(p, cp, stream)
-                      : launch_pmap<2, MODE_RECON, false>(p, cp, stream);
+    switch (order) {
+    case 1: return win ? launch_pmap<1, MODE_RECON, true>(p, cp, stream)
+                       : launch_pmap<1, MODE_RECON, false>(p, cp, stream);
+    case 2: return win ? launch_pmap<2, MODE_RECON, true>(p, cp, stream)
+                       : launch_pmap<2, MODE_RECON, false>(p, cp, stream);
+    default: return win ? launch_pmap<3, MODE_RECON, true>(p, cp, stream)
+                        : launch_pmap<3, MODE_RECON, false>(p, cp, stream);
+    }
 }
 
 }  // namespace spk

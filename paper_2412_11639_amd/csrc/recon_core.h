@@ -164,11 +164,13 @@ struct SegState {
     // false.  FSR: all intervals in [flo, flo + 1] keep the segment stable.
     // SSR: words whose intervals take the values flo and flo + 1 (see
     // two_values), or all equal one value just below a single-valued
-    // segment.
+    // segment.  TFI has no shortcut.
     template <int ORDER>
     __device__ __forceinline__ bool fast_word(uint64_t w, int32_t x0, int32_t c)
     {
-        if constexpr (ORDER == 1) {
+        if constexpr (ORDER == 3) {
+            return false;  // TFI: every interval is cut
+        } else if constexpr (ORDER == 1) {
             const int32_t a = flo;
             if (a < 1 || a > kFastMaxGap || x0 < a || x0 > a + 1) return false;
             if (!gaps_within(w, a, true)) return false;
@@ -327,6 +329,12 @@ struct SegState {
     template <int ORDER>
     __device__ __forceinline__ bool step(int32_t x)
     {
+        if constexpr (ORDER == 3) {
+            // TFI (Sec. II): every interval after the first opens a segment
+            const bool cut = flo != kBig;
+            flo = fhi = x;
+            return cut;
+        }
         const int32_t nlo = min(flo, x), nhi = max(fhi, x);
         const bool fcut = nhi - nlo > 1;  // S1 leaves zero-order stability
         flo = fcut ? x : nlo;
@@ -569,7 +577,8 @@ struct Run {
 };
 
 // Per-chunk record of the running state at the chunk's end, [field][chunk][pixel].
-// FSR runs keep the fields up to R_NFSR, SSR runs all but the FSR capture.
+// FSR and TFI runs keep the fields up to R_NFSR, SSR runs all but the FSR
+// capture.
 enum RecField {
     R_LASTSPK, R_CNTLAST, R_CUM, R_FIRST, R_FIRSTIDX, R_K0, R_LASTB, R_FB1, R_FN1,
     R_FI1, R_FLO, R_FHI, R_FWLO, R_FWHI, R_NFSR = R_FWHI + 1,
@@ -603,7 +612,7 @@ __device__ __forceinline__ void save_run(int32_t *rec, int64_t stride, const Run
     rec[R_FI1 * stride] = r.fi1;
     rec[R_FLO * stride] = r.st.flo;
     rec[R_FHI * stride] = r.st.fhi;
-    if constexpr (ORDER == 1) {
+    if constexpr (ORDER != 2) {
         rec[R_FWLO * stride] = r.fwlo;
         rec[R_FWHI * stride] = r.fwhi;
     } else {
@@ -634,7 +643,7 @@ __device__ __forceinline__ void load_run(const int32_t *rec, int64_t stride, Run
     r.fi1 = rec[R_FI1 * stride];
     r.st.flo = rec[R_FLO * stride];
     r.st.fhi = rec[R_FHI * stride];
-    if constexpr (ORDER == 1) {
+    if constexpr (ORDER != 2) {
         r.fwlo = rec[R_FWLO * stride];
         r.fwhi = rec[R_FWHI * stride];
     } else {
@@ -656,6 +665,7 @@ __device__ __forceinline__ void load_run(const int32_t *rec, int64_t stride, Run
 template <int ORDER>
 __device__ __forceinline__ bool same_decisions(const SegState &a, const SegState &b)
 {
+    if constexpr (ORDER == 3) return (a.flo == kBig) == (b.flo == kBig);  // TFI
     if (a.flo != b.flo || a.fhi != b.fhi) return false;
     if constexpr (ORDER == 1) {
         return true;

@@ -65,7 +65,7 @@ FAKE = 4096  # a non-null pointer value; validation must fail before any use
     dict(n_out=-1),
     dict(t_out=[5, 10]),          # 10 >= T
     dict(t_out=[-1]),
-    dict(order=0), dict(order=3),
+    dict(order=0), dict(order=4),
     dict(out=0),
     dict(H=65536, W=65536),       # H*W overflows int32
 ])
@@ -85,6 +85,22 @@ def test_segments_rejects_bad_arguments(lib):
     assert lib.spk_segments(FAKE, 4, 4, 10, 1, 4, 0, FAKE, FAKE, FAKE, None) == -1
     assert lib.spk_segments(FAKE, 4, 4, 10, 1, 4, FAKE, FAKE, FAKE, 0, None) == -1
     assert lib.spk_segments(FAKE, 4, 4, 10, 5, 4, FAKE, FAKE, FAKE, FAKE, None) == -1
+
+
+@pytest.mark.parametrize("args", [
+    dict(stream=0), dict(H=0), dict(T=-1), dict(theta=0.0), dict(theta=float("nan")),
+    dict(window=0), dict(window=-3), dict(n_out=-1), dict(t_out=[10]), dict(t_out=[-1]),
+    dict(out=0),
+])
+def test_tfp_rejects_bad_arguments(lib, args):
+    a = dict(stream=FAKE, H=4, W=4, T=10, theta=1.0, window=5, t_out=[0, 5], n_out=None,
+             out=FAKE)
+    a.update(args)
+    t = (ctypes.c_int32 * max(1, len(a["t_out"])))(*a["t_out"])
+    n_out = len(a["t_out"]) if a["n_out"] is None else a["n_out"]
+    rc = lib.spk_tfp(a["stream"], a["H"], a["W"], a["T"], a["theta"], a["window"],
+                     ctypes.addressof(t), n_out, a["out"], None)
+    assert rc == -1
 
 
 def test_zero_outputs_is_noop(lib):
@@ -123,7 +139,7 @@ def test_plan_create_rejects_bad_arguments(lib):
     h = ctypes.c_void_p()
     assert lib.spk_plan_create(None, arr, 1, 1, 0) == -1
     assert lib.spk_plan_create(ctypes.byref(h), arr, 0, 1, 0) == -1
-    assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 3, 0) == -1
+    assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 4, 0) == -1
     assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 1, 8) == -1
     assert lib.spk_plan_execute(None, None) == -1
     assert lib.spk_plan_destroy(None) == 0

@@ -274,3 +274,30 @@ def test_time_chunks_sparse_and_edge_pixels(spk, chunks, n_chunks):
     t_out = rng.integers(0, T, 400).tolist() + [0, T - 1, T - 1]
     for order in (1, 2):
         check_recon(spk, s, 1, 200, T, t_out, order)
+
+
+# --------------------------------------------------------------------------
+# the baselines (Sec. II): TFI as a third order, TFP windowed counts
+
+@pytest.mark.parametrize("n_chunks", [0, 5])
+def test_tfi_order(spk, chunks, n_chunks):
+    chunks(n_chunks)
+    H, W, T = 37, 91, 3001
+    s = spkgen.gratings(H, W, T, seed=12)
+    check_recon(spk, s, H, W, T, list(range(0, T, 5)) + [T - 1, 0], spk.TFI)
+    check_segments(spk, s, H, W, T, spk.TFI, cap=T)
+    s, H, W, T = worked_example_stream()
+    check_recon(spk, s, H, W, T, list(range(T)), spk.TFI)
+
+
+@pytest.mark.parametrize("window", [1, 7, 32, 64, 65, 300])
+def test_tfp(spk, window):
+    H, W, T = 33, 70, 700
+    s = spkgen.gratings(H, W, T, seed=13)
+    t_out = [0, 1, window - 1, window, T - 1, 350, 13] + list(range(2, T, 37))
+    t_out = [t for t in t_out if 0 <= t < T]
+    print("tfp window=%d n_out=%d" % (window, len(t_out)), flush=True)
+    got = spk.tfp(dev(s), H, W, T, 1.5, window, t_out)
+    torch.cuda.synchronize()
+    ref = oracle.tfp(s, H, W, T, 1.5, window, t_out)
+    np.testing.assert_array_equal(got.cpu().numpy(), ref.astype(np.float32))
