@@ -15,6 +15,7 @@ Prints one JSON line.  Also:
 from __future__ import annotations
 
 import argparse
+import ctypes
 import csv
 import glob
 import hashlib
@@ -48,18 +49,22 @@ def algorithmic_bytes(H, W, T, n_out) -> int:
     return T * H * W // 8 + n_out * H * W * 4
 
 
-def load_traffic(order_name):
-    """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
+def load_counters(order_name):
+    """Counter figures per step (HBM bytes, VALU instructions) from the
+    committed summary, if it was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if t.get("kernel_sha") != kernel_sha():
-        return None
-    v = t.get("per_order", {}).get(order_name, {}).get("hbm_bytes_per_launch")
-    return None if v is None else round(v)
+        return {}
+    return t.get("per_order", {}).get(order_name, {})
+
+
+# integer VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
+# 4 cycles (16 lanes wide), 2.4 GHz
+VALU_PEAK_PER_S = 256 * 2.4e9
 
 
 COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB each way
@@ -108,6 +113,15 @@ def traffic_from_counters(d: str):
                         e = out.setdefault(key, {}).setdefault(cname, {"factor": factor})
                         e[kern + "_kib"] = v
                         e["bytes"] = e.get("bytes", 0.0) + v * 1024.0 * factor
+    # VALU instructions (wave64) per step, when an SQ pass is present
+    for (n, c), v in vals.items():
+        if c != "SQ_INSTS_VALU":
+            continue
+        for kern in ("recon_kernel", "fixup_kernel"):
+            for o, key in (("1", "FSR"), ("2", "SSR")):
+                if kern + "<" + o in n:
+                    e = out.setdefault(key, {})
+                    e["valu_per_launch"] = e.get("valu_per_launch", 0.0) + v
     for key, d2 in out.items():
         if "FETCH_SIZE" in d2 and "WRITE_SIZE" in d2:
             d2["hbm_bytes_per_launch"] = d2["FETCH_SIZE"]["bytes"] + d2["WRITE_SIZE"]["bytes"]
@@ -286,7 +300,36 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1)
     plain_kept = plain_out[[t - 31 for t in check_t]].cpu().numpy()
-    del plain_out
+    # the same through the segment encoding: one pass writes each pixel's
+    # segment list, a second expands it to every frame
+    cnt = spk.segments(ds, H, W, T, order=spk.FSR, cap=0)[3]
+    cap = max(1, int(cnt.max().item()))
+    seg = [torch.empty((cap, H * W), dtype=torch.int32, device="cuda") for _ in range(3)]
+    lib = spk._lib.load()
+    tp = (ctypes.c_int32 * len(frames))(*frames)
+
+    def encoded():
+        rc = lib.spk_segments(ds.data_ptr(), H, W, T, spk.FSR, cap, seg[0].data_ptr(),
+                              seg[1].data_ptr(), seg[2].data_ptr(), cnt.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+        e_mid.record()
+        rc |= lib.spk_decode(seg[0].data_ptr(), seg[1].data_ptr(), seg[2].data_ptr(),
+                             cnt.data_ptr(), cap, H, W, T, 1.0, tp, len(frames),
+                             plain_out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        assert rc == 0
+
+    e_mid = torch.cuda.Event(enable_timing=True)
+    encoded()
+    torch.cuda.synchronize()
+    e0.record()
+    encoded()
+    e1.record()
+    torch.cuda.synchronize()
+    enc_ms, dec_ms = e0.elapsed_time(e_mid), e_mid.elapsed_time(e1)
+    enc_same = bool(torch.equal(plain_out[[t - 31 for t in check_t]].cpu(),
+                                torch.from_numpy(plain_kept)))
+    seg_bytes = int(cnt.sum().item()) * 12
+    del plain_out, seg
     # plain, latency-bound: re-scan the last Wn frames for one output frame
     Wn = min(4096, T)
     one = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
@@ -312,6 +355,10 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
            "plain_single_pass": {"mpx_frames_per_s": round(H * W * T / (plain_ms * 1e-3) / 1e6, 1),
                                  "ms": round(plain_ms, 3),
                                  "outputs": "every frame 31..%d" % (T - 1)},
+           "plain_encoded": {"mpx_frames_per_s": round(H * W * T / ((enc_ms + dec_ms) * 1e-3) / 1e6, 1),
+                             "segments_ms": round(enc_ms, 3), "decode_ms": round(dec_ms, 3),
+                             "segment_bytes": seg_bytes, "cap": cap,
+                             "equals_single_pass": enc_same},
            "plain_rescan_%d" % Wn: {"mpx_frames_per_s": round(H * W / (rs_ms * 1e-3) / 1e6, 1),
                                     "latency_ms": round(rs_ms, 4)},
            "wall_s": round(wall, 2)}
@@ -327,6 +374,36 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     del ds, kept
     torch.cuda.empty_cache()
     return res, check
+
+
+def run_accuracy(spk, spkgen, torch, np):
+    """Synthetic analogue of the paper's quality comparison (Sec. IV):
+    PSNR of FSR, SSR and the TFI / TFP baselines against the scene's true
+    intensity (the generator's per-frame rate), at 16 output frames."""
+    H, W, T = 250, 400, 4096
+    t_out = np.linspace(128, T - 1, 16).astype(int).tolist()
+    scenes = {
+        "static_blocks": (spkgen.blocks(H, W, T, 1),
+                          lambda: spkgen.blocks_truth(H, W, t_out, 1)),
+        "moving_blocks_v0.25": (spkgen.blocks(H, W, T, 4, vx=0.25, vy=0.1),
+                                lambda: spkgen.blocks_truth(H, W, t_out, 4, vx=0.25, vy=0.1)),
+        "gratings_poisson": (spkgen.gratings(H, W, T, 2),
+                             lambda: spkgen.gratings_truth(H, W, t_out, 2)),
+    }
+    res = {}
+    for name, (s, truth_fn) in scenes.items():
+        ds = torch.from_numpy(s).cuda()
+        truth = truth_fn()
+        outs = {"FSR": spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.FSR),
+                "SSR": spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.SSR),
+                "TFI": spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.TFI),
+                "TFP-32": spk.tfp(ds, H, W, T, 1.0, 32, t_out),
+                "TFP-64": spk.tfp(ds, H, W, T, 1.0, 64, t_out)}
+        torch.cuda.synchronize()
+        res[name] = {k: round(_psnr(v.cpu().numpy(), truth, np), 2) for k, v in outs.items()}
+        del ds
+    return {"workload": "250x400x4096 scenes, 16 outputs t=128..4095, PSNR (dB, peak 1) "
+                        "against the generator's true intensity", "psnr_db": res}
 
 
 def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
@@ -473,6 +550,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip surrogate training/evaluation and the streaming run")
     ap.add_argument("--only-surrogate", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FSR/SSR/TFI/TFP quality comparison")
     ap.add_argument("--sur-steps", type=int, default=3000)
     ap.add_argument("--sur-scenes", type=int, default=256)
     ap.add_argument("--stream-frames", type=int, default=4000,
@@ -557,7 +636,10 @@ def main():
     value = px_frames / (ms * 1e-3) / 1e6
     alg = algorithmic_bytes(H, W, T, n_out)
     achieved = alg / (ms * 1e-3) / 1e9
-    traffic = load_traffic(args.order.upper())
+    counters = load_counters(args.order.upper())
+    traffic = counters.get("hbm_bytes_per_launch")
+    traffic = None if traffic is None else round(traffic)
+    valu = counters.get("valu_per_launch")
 
     res = {
         "metric": METRIC,
@@ -579,6 +661,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
+        "valu": None if valu is None else {
+            "note": "the kernel is bound by integer VALU issue, not HBM",
+            "instr_per_step": round(valu), "issue_per_s": round(valu / (ms * 1e-3)),
+            "peak_per_s": VALU_PEAK_PER_S, "frac": round(valu / (ms * 1e-3) / VALU_PEAK_PER_S, 3)},
         "cpu_baseline": None,
         "other_order": {"order": "FSR" if order == spk.SSR else "SSR",
                         "ms_per_step": round(ms_other, 4),
@@ -590,6 +676,9 @@ def main():
     bcheck, schecks = None, None
     if not args.no_batched:
         res["batched"], bcheck = run_batched(args, spk, spkgen, torch, np)
+    if not args.no_accuracy:
+        print("accuracy: FSR / SSR / TFI / TFP against scene truth", file=sys.stderr, flush=True)
+        res["accuracy"] = run_accuracy(spk, spkgen, torch, np)
     if not args.no_surrogate:
         sres, schecks = run_surrogate(args, spk, spkgen, torch, np)
         res.update(sres)

@@ -131,6 +131,21 @@ int spk_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
             int32_t window, const int32_t *t_out, int32_t n_out, float *out, void *hip_stream);
 
 /*
+ * Decoder of the segment encoding (the encoder/decoder split of the
+ * paper's hardware design, Sec. III-C): the intensity at each requested
+ * frame from segment lists as spk_segments writes them (seg_first,
+ * seg_last, seg_n [cap][H*W], count [H*W], all device), without the stream.
+ * The output for t is Eq. 6 on the segment holding the interval in progress
+ * at t, exactly as spk_reconstruct computes it from the stream the lists
+ * came from (same order, same T).  A pixel whose list was cut at cap
+ * (count > cap) decodes to NaN from the first frame its stored segments do
+ * not reach.  t_out, n_out, out, theta, errors as spk_reconstruct.
+ */
+int spk_decode(const int32_t *seg_first, const int32_t *seg_last, const int32_t *seg_n,
+               const int32_t *count, int32_t cap, int32_t H, int32_t W, int32_t T, float theta,
+               const int32_t *t_out, int32_t n_out, float *out, void *hip_stream);
+
+/*
  * Batched plans: many streams of uneven size reconstructed by one
  * persistent kernel (one wave per 64-pixel strip of a stream at a time,
  * strips taken from per-XCD work counters), captured once in a HIP graph.

@@ -21,7 +21,7 @@ FSR = 1
 SSR = 2
 TFI = 3
 
-__all__ = ["FSR", "SSR", "TFI", "SpkError", "tfp", "frame_bytes", "reconstruct", "reconstruct_windows",
+__all__ = ["FSR", "SSR", "TFI", "SpkError", "tfp", "decode", "frame_bytes", "reconstruct", "reconstruct_windows",
            "segments", "version", "set_time_chunks", "get_time_chunks", "Plan",
            "PLAN_AUTOTUNE", "PLAN_NO_GRAPH"]
 
@@ -101,6 +101,25 @@ def tfp(stream_t, H, W, T, theta, window, t_out, out=None, stream=None):
     rc = _lib.load().spk_tfp(stream_t.data_ptr(), H, W, T, float(theta), int(window), tp, n_out,
                              out.data_ptr(), _stream_handle(stream))
     _lib.check("spk_tfp", rc)
+    return out
+
+
+def decode(seg_first, seg_last, seg_n, count, H, W, T, theta, t_out, out=None, stream=None):
+    """Intensity at the requested frames from segment lists (as returned by
+    ``segments``), float32 [n_out, H, W]; NaN where a list was cut at cap."""
+    cap = seg_first.shape[0]
+    for a in (seg_first, seg_last, seg_n):
+        assert a.dtype == torch.int32 and a.is_contiguous() and a.shape == (cap, H * W)
+    assert count.dtype == torch.int32 and count.numel() == H * W
+    t, tp = _host_times(t_out)
+    n_out = len(t)
+    if out is None:
+        out = torch.empty((n_out, H, W), dtype=torch.float32, device=count.device)
+    assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n_out * H * W
+    rc = _lib.load().spk_decode(seg_first.data_ptr(), seg_last.data_ptr(), seg_n.data_ptr(),
+                                count.data_ptr(), cap, H, W, T, float(theta), tp, n_out,
+                                out.data_ptr(), _stream_handle(stream))
+    _lib.check("spk_decode", rc)
     return out
 
 

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "libspk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["abi.hip", "recon.hip", "batch.hip", "tfp.hip", "surrogate.hip"]
+SOURCES = ["abi.hip", "recon.hip", "batch.hip", "tfp.hip", "decode.hip", "surrogate.hip"]
 
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -15,8 +15,8 @@
 namespace {
 
 // Device tables derived from one t_out list: cnt_le[t] = number of output
-// times <= t (t in [0, T)) and the sorted-index -> plane map (absent when
-// t_out is already strictly increasing).  Kept in a small per-device cache
+// times <= t (t in [0, T)), the sorted-index -> plane map and the sorted
+// times.  Kept in a small per-device cache
 // so repeated calls with the same output times upload nothing; a slot is
 // only overwritten after the device has drained (hipDeviceSynchronize), so
 // a kernel still reading it on another stream is never disturbed.
@@ -24,7 +24,7 @@ struct TableSlot {
     int dev = -1;
     int32_t T = 0;
     std::vector<int32_t> key;  // the t_out list as given
-    int32_t *d_buf = nullptr;  // [T] cnt_le followed by [n_out] plane map
+    int32_t *d_buf = nullptr;  // [T] cnt_le, [n_out] plane map, [n_out] sorted times
     int32_t *h_buf = nullptr;  // pinned staging of the same
     size_t cap = 0;            // ints allocated in both buffers
     bool identity = true;
@@ -75,7 +75,7 @@ int get_tables(int dev, int32_t T, const int32_t *t_out, int32_t n_out, hipStrea
         hipError_t e = hipDeviceSynchronize();
         if (hipSetDevice(cur) != hipSuccess || e != hipSuccess) return SPK_EHIP;
     }
-    const size_t need = (size_t)T + (size_t)n_out;
+    const size_t need = (size_t)T + 2 * (size_t)n_out;
     if (victim->cap < need || victim->dev != dev) {
         if (victim->d_buf) {
             int cur = dev;
@@ -107,13 +107,16 @@ int get_tables(int dev, int32_t T, const int32_t *t_out, int32_t n_out, hipStrea
         if (order[k] != k) identity = false;
         if (k > 0 && t_out[order[k]] == t_out[order[k - 1]]) identity = false;
     }
-    int32_t *cnt = victim->h_buf, *plane = victim->h_buf + T;
+    int32_t *cnt = victim->h_buf, *plane = victim->h_buf + T, *tsort = plane + n_out;
     int32_t k = 0;
     for (int32_t t = 0; t < T; t++) {
         while (k < n_out && t_out[order[k]] <= t) k++;
         cnt[t] = k;
     }
-    for (int32_t j = 0; j < n_out; j++) plane[j] = order[j];
+    for (int32_t j = 0; j < n_out; j++) {
+        plane[j] = order[j];
+        tsort[j] = t_out[order[j]];
+    }
     if (hipMemcpyAsync(victim->d_buf, victim->h_buf, need * sizeof(int32_t),
                        hipMemcpyHostToDevice, stream) != hipSuccess)
         return SPK_EHIP;
@@ -237,6 +240,27 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
 }
 
 }  // namespace
+
+namespace spk {
+
+int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
+               OutTables *out)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    TableSlot *slot = nullptr;
+    rc = get_tables(dev, T, t_out, n_out, stream, &slot);
+    if (rc) return rc;
+    out->cnt_le = slot->d_buf;
+    out->plane = slot->d_buf + T;
+    out->t_sorted = slot->d_buf + T + n_out;
+    out->identity = slot->identity;
+    return SPK_OK;
+}
+
+}  // namespace spk
 
 extern "C" {
 

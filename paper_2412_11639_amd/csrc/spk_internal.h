@@ -52,6 +52,18 @@ inline size_t chunk_record_ints(const ChunkPlan &cp, int32_t HW)
     return cp.nchunks > 1 ? (size_t)2 * kRecFields * cp.nchunks * (size_t)HW : 0;
 }
 
+// Device tables of one output-time list (cached per device; a table stays
+// valid for the kernels queued after this call): cnt_le[t] = number of
+// output times <= t for t < T, plane[j] = the output slot of the j-th time
+// in time order (stable), t_sorted[j] = that time; identity when t_out is
+// strictly increasing.  Checks for a gfx950 device.  Returns an SPK code.
+struct OutTables {
+    const int32_t *cnt_le, *plane, *t_sorted;
+    bool identity;
+};
+int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
+               OutTables *out);
+
 // Enqueue the plain FSR/SSR reconstruction (or segment listing) on stream.
 hipError_t launch_recon(const ReconParams &p, int order, Mode mode, const ChunkPlan &cp,
                         hipStream_t stream);

@@ -13,12 +13,13 @@ namespace {
 
 __global__ __launch_bounds__(64) void tfp_kernel(const uint8_t *stream, int64_t HW, size_t fb,
                                                  int32_t nstrips, double theta, int32_t window,
-                                                 const int32_t *t_out, float *out)
+                                                 const int32_t *t_sorted, const int32_t *plane,
+                                                 float *out)
 {
     const int lane = threadIdx.x;
     const int32_t strip = xcd_strip(blockIdx.x % nstrips, nstrips);
-    const int32_t k = blockIdx.x / nstrips;
-    const int32_t t = t_out[k];
+    const int32_t j = blockIdx.x / nstrips;
+    const int32_t t = t_sorted[j];
     const int32_t f0 = max(0, t - window + 1);
     const int64_t p0 = (int64_t)strip * 64;
     const uint8_t *base = stream + (p0 >> 3);
@@ -31,7 +32,8 @@ __global__ __launch_bounds__(64) void tfp_kernel(const uint8_t *stream, int64_t 
         cnt += popc64(transpose64(v.x, v.y, X, lane));
     }
     const int64_t p = p0 + lane;
-    if (p < HW) out[(int64_t)k * HW + p] = (float)(theta * (double)cnt / (double)(t - f0 + 1));
+    if (p < HW)
+        out[(int64_t)plane[j] * HW + p] = (float)(theta * (double)cnt / (double)(t - f0 + 1));
 }
 
 }  // namespace
@@ -53,17 +55,12 @@ extern "C" int spk_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, f
     const int32_t nstrips = (int32_t)((HW + 63) / 64);
     if ((int64_t)nstrips * n_out > INT32_MAX) return SPK_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
-    int32_t *d_t = nullptr;
-    if (hipMallocAsync((void **)&d_t, sizeof(int32_t) * (size_t)n_out, st) != hipSuccess)
-        return SPK_ENOMEM;
-    hipError_t e = hipMemcpyAsync(d_t, t_out, sizeof(int32_t) * (size_t)n_out,
-                                  hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(spk::tfp_kernel, dim3((unsigned)(nstrips * n_out)), dim3(64), 0, st,
-                           stream, HW, spk_frame_bytes(H, W), nstrips, (double)theta,
-                           window, d_t, out);
-        e = hipGetLastError();
-    }
-    hipFreeAsync(d_t, st);
+    spk::OutTables tab;
+    const int rc = spk::out_tables(T, t_out, n_out, st, &tab);
+    if (rc) return rc;
+    hipLaunchKernelGGL(spk::tfp_kernel, dim3((unsigned)(nstrips * n_out)), dim3(64), 0, st,
+                       stream, HW, spk_frame_bytes(H, W), nstrips, (double)theta, window,
+                       tab.t_sorted, tab.plane, out);
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPK_OK : SPK_EHIP;
 }

@@ -103,6 +103,21 @@ def test_tfp_rejects_bad_arguments(lib, args):
     assert rc == -1
 
 
+@pytest.mark.parametrize("args", [
+    dict(count=0), dict(cap=-1), dict(sf=0), dict(H=0), dict(T=0), dict(theta=-2.0),
+    dict(n_out=-1), dict(t_out=[10]), dict(t_out=[-1]), dict(out=0),
+])
+def test_decode_rejects_bad_arguments(lib, args):
+    a = dict(sf=FAKE, sl=FAKE, sn=FAKE, count=FAKE, cap=4, H=4, W=4, T=10, theta=1.0,
+             t_out=[0, 5], n_out=None, out=FAKE)
+    a.update(args)
+    t = (ctypes.c_int32 * max(1, len(a["t_out"])))(*a["t_out"])
+    n_out = len(a["t_out"]) if a["n_out"] is None else a["n_out"]
+    rc = lib.spk_decode(a["sf"], a["sl"], a["sn"], a["count"], a["cap"], a["H"], a["W"], a["T"],
+                        a["theta"], ctypes.addressof(t), n_out, a["out"], None)
+    assert rc == -1
+
+
 def test_zero_outputs_is_noop(lib):
     # n_out == 0 returns before any device work
     assert lib.spk_reconstruct(FAKE, 4, 4, 10, 1.0, None, 0, None, 1, None) == 0

@@ -301,3 +301,51 @@ def test_tfp(spk, window):
     torch.cuda.synchronize()
     ref = oracle.tfp(s, H, W, T, 1.5, window, t_out)
     np.testing.assert_array_equal(got.cpu().numpy(), ref.astype(np.float32))
+
+
+# --------------------------------------------------------------------------
+# segment encoding and its decoder
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_decode_of_segments_equals_reconstruct(spk, order):
+    """Expanding the segment lists to frames gives exactly what the
+    reconstruction writes from the stream (and so the oracle's values)."""
+    H, W, T = 37, 91, 3001
+    for s, h, w, T_ in ((spkgen.gratings(H, W, T, seed=14), H, W, T),
+                        (spkgen.blocks(40, 64, 1500, seed=15, vx=0.6), 40, 64, 1500),
+                        worked_example_stream()):
+        ds = dev(s)
+        t_out = list(range(0, T_, 3)) + [T_ - 1, 0, 0, 5]
+        cnt = spk.segments(ds, h, w, T_, order=order, cap=0)[3]
+        cap = max(1, int(cnt.max().item()))
+        sf, sl, sn, cnt = spk.segments(ds, h, w, T_, order=order, cap=cap)
+        got = spk.decode(sf, sl, sn, cnt, h, w, T_, 1.0, t_out)
+        ref = spk.reconstruct(ds, h, w, T_, 1.0, t_out, order=order)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
+        np.testing.assert_array_equal(
+            got.cpu().numpy(),
+            oracle.reconstruct(s, h, w, T_, 1.0, t_out, order=order).astype(np.float32))
+
+
+def test_decode_of_cut_lists_is_nan_past_cap(spk):
+    """With lists cut at cap, outputs held by a stored segment decode to the
+    oracle's value and later ones to NaN."""
+    H, W, T = 20, 50, 2000
+    s = spkgen.gratings(H, W, T, seed=16)
+    t_out = list(range(0, T, 11))
+    cap = 5
+    sf, sl, sn, cnt = spk.segments(dev(s), H, W, T, order=2, cap=cap)
+    got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out).cpu().numpy().reshape(len(t_out), -1)
+    torch.cuda.synchronize()
+    ref = oracle.reconstruct(s, H, W, T, 1.0, t_out, order=2).astype(np.float32)
+    ref = ref.reshape(len(t_out), -1)
+    rl = oracle.segments(s, H, W, T, order=2, cap=cap)[1]          # last spike of stored segments
+    rc = oracle.segments(s, H, W, T, order=2, cap=cap)[3]
+    for p in range(H * W):
+        reach = rl[min(cap, rc[p]) - 1, p] if rc[p] > 0 else None
+        for k, t in enumerate(t_out):
+            if rc[p] <= cap or t <= reach:
+                assert got[k, p] == ref[k, p], (p, t)
+            else:
+                assert np.isnan(got[k, p]), (p, t)
