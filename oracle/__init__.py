@@ -17,6 +17,7 @@ import numpy as np
 FSR = 1
 SSR = 2
 TFI = 3
+TSR = 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")

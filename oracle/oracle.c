@@ -21,9 +21,12 @@
  *                                                    (Sec. III-B, Fig. 1 caption)
  *   O-6 output time   the segment holding the interval in progress at t
  *   O-7 intensity     I = theta * N / sum_i T0(i)                 (Eq. 6)
+ *   third order       inside each SSR piece, cut where an S3 stream (gaps of
+ *                     an S2 value inside S2) leaves zero-order stability
+ *                                                    (Sec. III-A, Eq. 5)
  * Baselines the paper compares against (Sec. II): TFI (every interval its
- * own segment, so I = theta / T0) as a third segmentation order, and TFP
- * (spike count over a fixed window).
+ * own segment, so I = theta / T0) as a further order, and TFP (spike count
+ * over a fixed window).
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes of the repository):
@@ -46,7 +49,9 @@
 #define ORACLE_FSR 1
 #define ORACLE_SSR 2
 #define ORACLE_TFI 3
-#define ORACLE_ORDER_OK(o) ((o) == ORACLE_FSR || (o) == ORACLE_SSR || (o) == ORACLE_TFI)
+#define ORACLE_TSR 4
+#define ORACLE_ORDER_OK(o) \
+    ((o) == ORACLE_FSR || (o) == ORACLE_SSR || (o) == ORACLE_TFI || (o) == ORACLE_TSR)
 
 /* ---- O-1: spike frames of pixel p (Eq. 2: P(n) = 1 marks a spike) ------ */
 static int32_t spikes_of_pixel(const uint8_t *stream, size_t fb, int32_t T, int64_t p,
@@ -142,6 +147,85 @@ static int32_t ssr_refine(const int32_t *x, int32_t s, int32_t e, int32_t *start
     return nseg;
 }
 
+/* ---- third order: inside one SSR piece [s, e], the next stage of the
+ * n-order rule (Sec. III-A, Eq. 5 applied once more; Sec. III-B: the
+ * judgement extends to S3 at O(2^(n-1)) streams).  For each interval value
+ * v of the open sub-piece, S2(v) is the list of gaps between its
+ * consecutive occurrences; for each value g of S2(v), S3(v, g) is the list
+ * of gaps between consecutive positions of g in S2(v).  The sub-piece is
+ * cut before the interval whose new S2 element makes some S3(v, g) leave
+ * zero-order stability; the cut opens a sub-piece whose S2 and S3 start
+ * empty.  Appends sub-piece starts to start[], returns the count. */
+typedef struct {
+    int32_t value;   /* an element value g of S2(v) */
+    int32_t last;    /* index in S2(v) of its latest occurrence */
+    int32_t gap_lo, gap_hi, has_gap;
+} s3_track;
+
+typedef struct {
+    int32_t value;   /* interval value v */
+    int32_t last;    /* interval index of its latest occurrence */
+    int32_t n2;      /* elements of S2(v) so far */
+    s3_track t3[2];
+    int32_t nt3;
+} v_track;
+
+static int32_t tsr_refine(const int32_t *x, int32_t s, int32_t e, int32_t *start)
+{
+    int32_t nseg = 0;
+    v_track tr[2];
+    int32_t ntr = 0;
+    start[nseg++] = s;
+    for (int32_t m = s; m <= e; m++) {
+        int32_t v = x[m];
+        int32_t j = -1;
+        for (int32_t k = 0; k < ntr; k++)
+            if (tr[k].value == v) j = k;
+        if (j < 0) {
+            /* an SSR piece holds at most two interval values */
+            if (ntr >= 2) abort();
+            tr[ntr].value = v;
+            tr[ntr].last = m;
+            tr[ntr].n2 = 0;
+            tr[ntr].nt3 = 0;
+            ntr++;
+            continue;
+        }
+        v_track *t = &tr[j];
+        int32_t d = m - t->last;   /* new element of S2(v), at index n2 */
+        int32_t q = -1;
+        for (int32_t k = 0; k < t->nt3; k++)
+            if (t->t3[k].value == d) q = k;
+        if (q >= 0) {
+            s3_track *u = &t->t3[q];
+            int32_t g = t->n2 - u->last;   /* new element of S3(v, d) */
+            int32_t glo = u->has_gap && u->gap_lo < g ? u->gap_lo : g;
+            int32_t ghi = u->has_gap && u->gap_hi > g ? u->gap_hi : g;
+            if (!zero_order_stable(glo, ghi)) {
+                start[nseg++] = m;
+                ntr = 0;
+                tr[ntr].value = v;
+                tr[ntr].last = m;
+                tr[ntr].n2 = 0;
+                tr[ntr].nt3 = 0;
+                ntr++;
+                continue;
+            }
+            u->gap_lo = glo;
+            u->gap_hi = ghi;
+            u->has_gap = 1;
+            u->last = t->n2;
+        } else {
+            /* S2(v) is zero-order stable inside an SSR piece: two values */
+            if (t->nt3 >= 2) abort();
+            t->t3[t->nt3++] = (s3_track){d, t->n2, 0, 0, 0};
+        }
+        t->n2++;
+        t->last = m;
+    }
+    return nseg;
+}
+
 /* Segment S1 (n intervals) by the given order; writes segment starts,
  * returns the number of segments. work[] holds n ints. */
 static int32_t segment_intervals(const int32_t *x, int32_t n, int32_t order, int32_t *start,
@@ -154,13 +238,28 @@ static int32_t segment_intervals(const int32_t *x, int32_t n, int32_t order, int
     }
     int32_t nf = fsr_segments(x, n, order == ORACLE_FSR ? start : work);
     if (order == ORACLE_FSR) return nf;
+    /* third order refines the SSR pieces, which then go to a buffer of
+     * their own */
+    int32_t *ssr = start;
+    if (order == ORACLE_TSR) {
+        ssr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        if (!ssr) abort();
+    }
     int32_t ns = 0;
     for (int32_t i = 0; i < nf; i++) {
         int32_t s = work[i];
         int32_t e = (i + 1 < nf ? work[i + 1] : n) - 1;
-        ns += ssr_refine(x, s, e, start + ns);
+        ns += ssr_refine(x, s, e, ssr + ns);
     }
-    return ns;
+    if (order != ORACLE_TSR) return ns;
+    int32_t nt = 0;
+    for (int32_t i = 0; i < ns; i++) {
+        int32_t s = ssr[i];
+        int32_t e = (i + 1 < ns ? ssr[i + 1] : n) - 1;
+        nt += tsr_refine(x, s, e, start + nt);
+    }
+    free(ssr);
+    return nt;
 }
 
 /* Exported: segment an interval list directly (tests). */

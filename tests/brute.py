@@ -12,7 +12,10 @@ the result rather than as the greedy procedure the oracle runs:
 * SSR (Sec. III-B, Fig. 1 caption): inside each FSR segment, a contiguous
   partition whose parts have a zero-order stable S2 for every interval value
   (S2 of a value = gaps between its consecutive occurrences, Eq. 5), again
-  maximal.
+  maximal;
+* third order (the n-order rule of Sec. III-A once more): inside each SSR
+  piece, parts whose S3 streams (gaps between consecutive positions of each
+  S2 value inside S2) are zero-order stable, again maximal.
 
 Both properties are prefix-closed, so at most one partition satisfies them;
 ``enumerate_partitions`` checks that claim by brute force on small inputs.
@@ -81,6 +84,40 @@ def is_ssr_partition(x, starts, fsr_starts) -> bool:
         if not (zero_order_stable(x[a:b]) and s2_stable(x[a:b])):
             return False
         if b < seg_end and s2_stable(x[a:b + 1]):
+            return False
+    return True
+
+
+def s3_stable(part) -> bool:
+    """Third order (the n-order rule of Sec. III-A applied to S2): for every
+    interval value v and every value g of S2(v), the gaps between
+    consecutive positions of g in S2(v) are zero-order stable."""
+    for gaps in s2_streams(part).values():
+        for s3 in s2_streams(gaps).values():
+            if not zero_order_stable(s3):
+                return False
+    return True
+
+
+def is_tsr_partition(x, starts, ssr_starts) -> bool:
+    """True iff ``starts`` refines the SSR partition and, inside each SSR
+    piece, is the maximal partition into third-order stable parts."""
+    if len(x) == 0:
+        return list(starts) == []
+    if not set(ssr_starts) <= set(starts):
+        return False
+    if not starts or starts[0] != 0 or list(starts) != sorted(set(starts)):
+        return False
+    pb = list(ssr_starts) + [len(x)]
+    sb = list(starts) + [len(x)]
+    for a, b in zip(sb, sb[1:]):
+        piece_end = min(e for e in pb if e > a)
+        if b > piece_end:
+            return False
+        part = x[a:b]
+        if not (zero_order_stable(part) and s2_stable(part) and s3_stable(part)):
+            return False
+        if b < piece_end and s3_stable(x[a:b + 1]):
             return False
     return True
 

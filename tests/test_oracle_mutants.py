@@ -40,6 +40,10 @@ MUTANTS = {
                          "for (int32_t i = 0; i < n; i++) start[i / 2] = i & ~1;\n        return (n + 1) / 2;"),
     "tfp_window_off_by_one": ("int32_t f0 = t - window + 1 < 0 ? 0 : t - window + 1;",
                               "int32_t f0 = t - window < 0 ? 0 : t - window;"),
+    "tsr_no_reset_at_cut": ("                start[nseg++] = m;\n                ntr = 0;\n                tr[ntr].value = v;",
+                            "                start[nseg++] = m;\n                tr[ntr].value = v;"),
+    "tsr_last_not_updated": ("            u->has_gap = 1;\n            u->last = t->n2;",
+                             "            u->has_gap = 1;"),
     "first_segment_start": ("    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0];",
                             "    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0] + 1;"),
 }
@@ -70,6 +74,7 @@ def _battery(lib):
     s = spkgen.pack(bits)
     f = oracle.segments(s, 16, 128, T, order=oracle.FSR, cap=T, lib=lib)
     g = oracle.segments(s, 16, 128, T, order=oracle.SSR, cap=T, lib=lib)
+    h = oracle.segments(s, 16, 128, T, order=oracle.TSR, cap=T, lib=lib)
     ok = True
     for q in range(n):
         tau = np.flatnonzero(bits[:, q]).tolist()
@@ -78,10 +83,12 @@ def _battery(lib):
         try:
             fs = [idx[f[0][k, q]] for k in range(f[3][q])]
             ss = [idx[g[0][k, q]] for k in range(g[3][q])]
+            ts = [idx[h[0][k, q]] for k in range(h[3][q])]
         except KeyError:
             ok = False
             break
-        if not (brute.is_fsr_partition(x, fs) and brute.is_ssr_partition(x, ss, fs)):
+        if not (brute.is_fsr_partition(x, fs) and brute.is_ssr_partition(x, ss, fs)
+                and brute.is_tsr_partition(x, ts, ss)):
             ok = False
             break
     if not ok:

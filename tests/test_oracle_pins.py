@@ -97,10 +97,10 @@ def test_lemma2_s2_gaps_and_theorem1_third_order():
                 assert brute.zero_order_stable(gaps2), (q, th, v, val, val2)
 
 
-@pytest.mark.parametrize("order", [oracle.FSR, oracle.SSR])
+@pytest.mark.parametrize("order", [oracle.FSR, oracle.SSR, oracle.TSR])
 def test_constant_rate_single_segment_and_exact_intensity(order):
-    """Theorem 1: a constant-rate pixel is absolutely stable, so FSR and SSR
-    keep one segment; Eq. 6 over it is theta*(K-1)/(tau_K - tau_1).  When Q
+    """Theorem 1: a constant-rate pixel is absolutely stable, so FSR, SSR
+    and the third order keep one segment; Eq. 6 over it is theta*(K-1)/(tau_K - tau_1).  When Q
     divides theta every interval is theta/Q and the estimate is exactly
     theta*Q/theta_int; otherwise its relative error is below
     1/(N*theta_int/Q - 1) (residuals at both ends are in [0, Q))."""
@@ -168,6 +168,8 @@ def test_fsr_ssr_all_streams_bruteforce(T):
         ss = [idx[s_first[k, p]] for k in range(s_cnt[p])]
         assert brute.is_fsr_partition(x, fs), (p, x, fs)
         assert brute.is_ssr_partition(x, ss, fs), (p, x, ss, fs)
+        ts = oracle.segment_intervals(x, oracle.TSR)
+        assert brute.is_tsr_partition(x, ts, ss), (p, x, ts, ss)
         # windows are consistent: last = first of the next, n counts intervals
         for k in range(f_cnt[p]):
             a = fs[k]
@@ -193,6 +195,9 @@ def test_partition_uniqueness_by_enumeration():
         ssr = brute.enumerate_partitions(x, lambda st: brute.is_ssr_partition(x, st, fsr[0]))
         assert len(ssr) == 1
         assert oracle.segment_intervals(x, oracle.SSR) == ssr[0]
+        tsr = brute.enumerate_partitions(x, lambda st: brute.is_tsr_partition(x, st, ssr[0]))
+        assert len(tsr) == 1
+        assert oracle.segment_intervals(x, oracle.TSR) == tsr[0]
 
 
 def test_random_long_interval_streams_declarative():
@@ -205,8 +210,10 @@ def test_random_long_interval_streams_declarative():
         x = np.maximum(1, np.round(drift + rng.integers(-1, 2, n))).astype(int).tolist()
         fs = oracle.segment_intervals(x, oracle.FSR)
         ss = oracle.segment_intervals(x, oracle.SSR)
+        ts = oracle.segment_intervals(x, oracle.TSR)
         assert brute.is_fsr_partition(x, fs)
         assert brute.is_ssr_partition(x, ss, fs)
+        assert brute.is_tsr_partition(x, ts, ss)
 
 
 def test_break_function_monotone():
@@ -217,7 +224,7 @@ def test_break_function_monotone():
     for _ in range(100):
         n = int(rng.integers(5, 60))
         x = (4 + rng.integers(-1, 2, n) + (rng.random(n) < 0.1) * 3).tolist()
-        for order in (oracle.FSR, oracle.SSR):
+        for order in (oracle.FSR, oracle.SSR, oracle.TSR):
             ends = []
             for s in range(n):
                 st = oracle.segment_intervals(x[s:], order)
@@ -335,7 +342,7 @@ def test_argument_errors():
     with pytest.raises(ValueError):
         oracle.reconstruct(s, 1, 8, 4, 1.0, [4])          # t out of range
     with pytest.raises(ValueError):
-        oracle.reconstruct(s, 1, 8, 4, 1.0, [0], order=4)  # unknown order
+        oracle.reconstruct(s, 1, 8, 4, 1.0, [0], order=5)  # unknown order
     with pytest.raises(ValueError):
         oracle.tfp(s, 1, 8, 4, 1.0, 0, [0])                # empty window
 
@@ -460,3 +467,29 @@ def test_tfp_constant_rate_closed_form(window):
         cnt = C(int(t)) - C(int(t) - L)
         np.testing.assert_array_equal(out[k], 3.0 * cnt / L)
         assert np.all(np.abs(out[k] - 3.0 * Q / th) < 3.0 / L + 1e-12)
+
+
+def test_third_order_cuts_where_s3_breaks():
+    """Worked by hand: S1 = 4 4 4 5 4 5 4 5 4 4.  FSR keeps {4, 5}; S2(4) =
+    gaps of 4 at 0 1 2 4 6 8 9 = 1 1 2 2 2 1 and S2(5) = 2 2 are stable, so
+    SSR keeps one piece.  S3(4, 1) = gaps between the positions 0 1 5 of the
+    value 1 in S2(4) = 1 4: the S2 element that interval 9 adds breaks it,
+    so the third order cuts before interval 9."""
+    x = [4, 4, 4, 5, 4, 5, 4, 5, 4, 4]
+    assert oracle.segment_intervals(x, oracle.FSR) == [0]
+    assert oracle.segment_intervals(x, oracle.SSR) == [0]
+    assert oracle.segment_intervals(x, oracle.TSR) == [0, 9]
+    assert brute.is_tsr_partition(x, [0, 9], [0])
+
+
+def test_third_order_refines_ssr_on_generated_scenes():
+    """The third order never merges what SSR splits, and on noisy scenes it
+    does cut inside SSR pieces (the order adds something)."""
+    H, W, T = 8, 40, 3000
+    s = spkgen.gratings(H, W, T, seed=23)
+    _, sl, _, sc = oracle.segments(s, H, W, T, order=oracle.SSR, cap=T)
+    _, tl, _, tc = oracle.segments(s, H, W, T, order=oracle.TSR, cap=T)
+    assert np.all(tc >= sc)
+    assert tc.sum() > sc.sum()
+    for p in range(H * W):
+        assert set(sl[:sc[p], p].tolist()) <= set(tl[:tc[p], p].tolist())
