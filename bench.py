@@ -378,8 +378,9 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
 
 def run_accuracy(spk, spkgen, torch, np):
     """Synthetic analogue of the paper's quality comparison (Sec. IV):
-    PSNR of FSR, SSR and the TFI / TFP baselines against the scene's true
-    intensity (the generator's per-frame rate), at 16 output frames."""
+    PSNR of FSR, SSR, the third order and the TFI / TFP baselines against
+    the scene's true intensity (the generator's per-frame rate), at 16
+    output frames."""
     H, W, T = 250, 400, 4096
     t_out = np.linspace(128, T - 1, 16).astype(int).tolist()
     scenes = {
@@ -396,6 +397,7 @@ def run_accuracy(spk, spkgen, torch, np):
         truth = truth_fn()
         outs = {"FSR": spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.FSR),
                 "SSR": spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.SSR),
+                "third order": spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.TSR),
                 "TFI": spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.TFI),
                 "TFP-32": spk.tfp(ds, H, W, T, 1.0, 32, t_out),
                 "TFP-64": spk.tfp(ds, H, W, T, 1.0, 64, t_out)}

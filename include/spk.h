@@ -56,12 +56,15 @@ enum {
 
 /*
  * Segmentation orders: SPK_FSR and SPK_SSR are the paper's first- and
- * second-order stable reconstructions (Sec. III-B).  SPK_TFI is the TFI
+ * second-order stable reconstructions (Sec. III-B).  SPK_TSR takes the
+ * n-order rule (Sec. III-A, Eq. 5) one step further: inside each SSR piece
+ * it also cuts where an S3 stream (gaps between consecutive positions of an
+ * S2 value inside S2) leaves zero-order stability.  SPK_TFI is the TFI
  * baseline the paper compares against (Sec. II: the reciprocal of the
  * interval between the two spikes around the output frame), run as the
  * order that keeps every interval on its own (windows have N = 1).
  */
-enum { SPK_FSR = 1, SPK_SSR = 2, SPK_TFI = 3 };
+enum { SPK_FSR = 1, SPK_SSR = 2, SPK_TFI = 3, SPK_TSR = 4 };
 
 /* Bytes per packed frame: ceil(H*W / 128) * 16.  0 if H or W <= 0. */
 size_t spk_frame_bytes(int32_t H, int32_t W);

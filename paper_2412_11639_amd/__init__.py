@@ -20,8 +20,9 @@ from ._lib import SpkError
 FSR = 1
 SSR = 2
 TFI = 3
+TSR = 4
 
-__all__ = ["FSR", "SSR", "TFI", "SpkError", "tfp", "decode", "frame_bytes", "reconstruct", "reconstruct_windows",
+__all__ = ["FSR", "SSR", "TFI", "TSR", "SpkError", "tfp", "decode", "frame_bytes", "reconstruct", "reconstruct_windows",
            "segments", "version", "set_time_chunks", "get_time_chunks", "Plan",
            "PLAN_AUTOTUNE", "PLAN_NO_GRAPH"]
 

@@ -193,7 +193,8 @@ int check_common(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0) return SPK_EINVAL;
     if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
-    if (order != SPK_FSR && order != SPK_SSR && order != SPK_TFI) return SPK_EINVAL;
+    if (order != SPK_FSR && order != SPK_SSR && order != SPK_TFI && order != SPK_TSR)
+        return SPK_EINVAL;
     const size_t fb = spk_frame_bytes(H, W);
     if ((size_t)T > SIZE_MAX / fb) return SPK_EINVAL;
     return SPK_OK;
@@ -233,7 +234,7 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
     p.win_first = wf;
     p.win_last = wl;
     p.win_n = wn;
-    spk::ChunkPlan cp = spk::plan_chunks(p.HW, T, requested_chunks(), requested_warm());
+    spk::ChunkPlan cp = spk::plan_chunks(p.HW, T, order, requested_chunks(), requested_warm());
     rc = get_scratch(dev, st, spk::chunk_record_ints(cp, p.HW), &cp.rec);
     if (rc) return rc;
     return spk::launch_recon(p, order, spk::MODE_RECON, cp, st) == hipSuccess ? SPK_OK : SPK_EHIP;

@@ -198,7 +198,8 @@ hipError_t launch_batch(const spk_plan_s *pl, int grid, int grab, hipStream_t st
     switch (pl->order) {
     case SPK_FSR: SPK_BATCH_LAUNCH(1) break;
     case SPK_SSR: SPK_BATCH_LAUNCH(2) break;
-    default: SPK_BATCH_LAUNCH(3) break;
+    case SPK_TFI: SPK_BATCH_LAUNCH(3) break;
+    default: SPK_BATCH_LAUNCH(4) break;
     }
 #undef SPK_BATCH_LAUNCH
     return hipGetLastError();
@@ -259,8 +260,7 @@ int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32
 {
     if (!plan) return SPK_EINVAL;
     *plan = nullptr;
-    if (!jobs || n_jobs <= 0 || (order != SPK_FSR && order != SPK_SSR && order != SPK_TFI))
-        return SPK_EINVAL;
+    if (!jobs || n_jobs <= 0 || order < SPK_FSR || order > SPK_TSR) return SPK_EINVAL;
     if (flags & ~(SPK_PLAN_AUTOTUNE | SPK_PLAN_NO_GRAPH)) return SPK_EINVAL;
     // validate every job before touching the device
     int64_t items = 0;
@@ -298,7 +298,8 @@ int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32
     size_t off = 0;
     int32_t strip = 0;
     char sig[64];
-    pl->signature = order == SPK_FSR ? "fsr" : (order == SPK_SSR ? "ssr" : "tfi");
+    static const char *const names[] = {"", "fsr", "ssr", "tfi", "tsr"};
+    pl->signature = names[order];
     for (int32_t j = 0; j < n_jobs; j++) {
         const spk_job &J = jobs[j];
         std::vector<int32_t> ord(J.n_out);

@@ -267,9 +267,10 @@ hipError_t launch_pmap(const ReconParams &p, const ChunkPlan &cp, hipStream_t st
 
 }  // namespace
 
-ChunkPlan plan_chunks(int32_t HW, int32_t T, int requested, int warm)
+ChunkPlan plan_chunks(int32_t HW, int32_t T, int order, int requested, int warm)
 {
     ChunkPlan cp;
+    cp.fields = rec_fields_of(order);
     const int nblocks = (HW + 63) / 64;
     const int ntiles = (T + 63) / 64;
     int c = requested;
@@ -296,7 +297,8 @@ hipError_t launch_recon(const ReconParams &p, int order, Mode mode, const ChunkP
         switch (order) {
         case 1: return launch_one<1, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
         case 2: return launch_one<2, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
-        default: return launch_one<3, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
+        case 3: return launch_one<3, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
+        default: return launch_one<4, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
         }
     }
     switch (order) {
@@ -304,8 +306,10 @@ hipError_t launch_recon(const ReconParams &p, int order, Mode mode, const ChunkP
                        : launch_pmap<1, MODE_RECON, false>(p, cp, stream);
     case 2: return win ? launch_pmap<2, MODE_RECON, true>(p, cp, stream)
                        : launch_pmap<2, MODE_RECON, false>(p, cp, stream);
-    default: return win ? launch_pmap<3, MODE_RECON, true>(p, cp, stream)
-                        : launch_pmap<3, MODE_RECON, false>(p, cp, stream);
+    case 3: return win ? launch_pmap<3, MODE_RECON, true>(p, cp, stream)
+                       : launch_pmap<3, MODE_RECON, false>(p, cp, stream);
+    default: return win ? launch_pmap<4, MODE_RECON, true>(p, cp, stream)
+                        : launch_pmap<4, MODE_RECON, false>(p, cp, stream);
     }
 }
 

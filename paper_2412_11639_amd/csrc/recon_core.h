@@ -146,6 +146,14 @@ struct SegState {
     // first occurrence in a piece, hence valid whenever the occurrence is).
     int32_t ii, ps;
     int32_t l0, l1, g0l, g0h, g1l, g1h;
+    // Third order (ORDER 4): the open sub-piece starts at interval p3 (>= ps).
+    // S2 elements of each interval value are numbered by c2* (running), and
+    // b2* is that count at the value's first occurrence in the sub-piece.
+    // Per (value parity, S2-value parity) slot k = 2*odd + dodd: the number
+    // of the latest S2 element with that value (meaningful when >= b2 of the
+    // value) and the extremes of the S3 gaps between such elements.
+    int32_t p3, c20, c21, b20, b21;
+    int32_t m0, m1, m2, m3, hl0, hl1, hl2, hl3, hh0, hh1, hh2, hh3;
 
     __device__ __forceinline__ void reset()
     {
@@ -155,6 +163,10 @@ struct SegState {
         l0 = l1 = -1;
         g0l = g1l = kBig;
         g0h = g1h = -kBig;
+        p3 = c20 = c21 = b20 = b21 = 0;
+        m0 = m1 = m2 = m3 = -1;
+        hl0 = hl1 = hl2 = hl3 = kBig;
+        hh0 = hh1 = hh2 = hh3 = -kBig;
     }
 
     // Whole-word shortcut: if none of the word's intervals -- x0 (from the
@@ -168,8 +180,8 @@ struct SegState {
     template <int ORDER>
     __device__ __forceinline__ bool fast_word(uint64_t w, int32_t x0, int32_t c)
     {
-        if constexpr (ORDER == 3) {
-            return false;  // TFI: every interval is cut
+        if constexpr (ORDER == 3 || ORDER == 4) {
+            return false;  // TFI: every interval is cut; third order: no shortcut
         } else if constexpr (ORDER == 1) {
             const int32_t a = flo;
             if (a < 1 || a > kFastMaxGap || x0 < a || x0 > a + 1) return false;
@@ -357,6 +369,46 @@ struct SegState {
             g1l = odd ? ugl : g1l;
             g1h = odd ? ugh : g1h;
             ps = cut ? ii : ps;
+            if constexpr (ORDER == 4) {
+                // third order: d is the new element of S2(x) if x occurred in
+                // the open sub-piece; its S3 gap is the distance (in S2
+                // elements) back to the latest element of the same value
+                const bool seen3 = l >= p3;
+                const bool dodd = d & 1;
+                const int32_t c2 = odd ? c21 : c20, b2 = odd ? b21 : b20;
+                const int32_t m = odd ? (dodd ? m3 : m2) : (dodd ? m1 : m0);
+                const int32_t hl = odd ? (dodd ? hl3 : hl2) : (dodd ? hl1 : hl0);
+                const int32_t hh = odd ? (dodd ? hh3 : hh2) : (dodd ? hh1 : hh0);
+                const bool mvalid = seen3 && m >= b2;
+                const int32_t e = c2 - m;
+                const int32_t nl3 = min(hl, e), nh3 = max(hh, e);
+                const bool cut3 = cut || (mvalid && nh3 - nl3 > 1);
+                const bool rec = seen3 && !cut3;  // an S2 element inside the sub-piece
+                const int32_t ul = mvalid ? nl3 : kBig, uh = mvalid ? nh3 : -kBig;
+                const bool w0 = rec && !odd && !dodd, w1 = rec && !odd && dodd;
+                const bool w2 = rec && odd && !dodd, w3 = rec && odd && dodd;
+                m0 = w0 ? c2 : m0;
+                m1 = w1 ? c2 : m1;
+                m2 = w2 ? c2 : m2;
+                m3 = w3 ? c2 : m3;
+                hl0 = w0 ? ul : hl0;
+                hl1 = w1 ? ul : hl1;
+                hl2 = w2 ? ul : hl2;
+                hl3 = w3 ? ul : hl3;
+                hh0 = w0 ? uh : hh0;
+                hh1 = w1 ? uh : hh1;
+                hh2 = w2 ? uh : hh2;
+                hh3 = w3 ? uh : hh3;
+                const int32_t nc2 = c2 + (rec ? 1 : 0);
+                const int32_t nb2 = (!seen3 || cut3) ? c2 : b2;
+                c20 = odd ? c20 : nc2;
+                c21 = odd ? nc2 : c21;
+                b20 = odd ? b20 : nb2;
+                b21 = odd ? nb2 : b21;
+                p3 = cut3 ? ii : p3;
+                ii++;
+                return cut3;
+            }
             ii++;
             return cut;
         }
@@ -578,13 +630,21 @@ struct Run {
 
 // Per-chunk record of the running state at the chunk's end, [field][chunk][pixel].
 // FSR and TFI runs keep the fields up to R_NFSR, SSR runs all but the FSR
-// capture.
+// capture up to R_NSSR, third-order runs all but the capture.
 enum RecField {
     R_LASTSPK, R_CNTLAST, R_CUM, R_FIRST, R_FIRSTIDX, R_K0, R_LASTB, R_FB1, R_FN1,
     R_FI1, R_FLO, R_FHI, R_FWLO, R_FWHI, R_NFSR = R_FWHI + 1,
-    R_II = R_FWLO, R_PS, R_L0, R_L1, R_G0L, R_G0H, R_G1L, R_G1H, R_NFIELDS
+    R_II = R_FWLO, R_PS, R_L0, R_L1, R_G0L, R_G0H, R_G1L, R_G1H, R_NSSR,
+    R_P3 = R_NSSR, R_C20, R_C21, R_B20, R_B21, R_M0, R_M1, R_M2, R_M3, R_HL0, R_HL1, R_HL2,
+    R_HL3, R_HH0, R_HH1, R_HH2, R_HH3, R_NFIELDS
 };
 static_assert(R_NFIELDS <= kRecFields, "record layout");
+
+// Fields a run of the given order keeps in its records.
+__host__ __device__ constexpr int rec_fields_of(int order)
+{
+    return order == 2 ? (int)R_NSSR : (order == 4 ? (int)R_NFIELDS : (int)R_NFSR);
+}
 
 // Records of chunk c: the state at the chunk's end (all chunks) and the
 // warmed-up speculative state at its start (chunks > 0), each [field][chunk][HW].
@@ -594,7 +654,7 @@ __device__ __forceinline__ int32_t *rec_end(const ChunkPlan &cp, int c, int64_t 
 }
 __device__ __forceinline__ int32_t *rec_start(const ChunkPlan &cp, int c, int64_t p, int32_t HW)
 {
-    return cp.rec + (int64_t)kRecFields * cp.nchunks * HW + (int64_t)c * HW + p;
+    return cp.rec + (int64_t)cp.fields * cp.nchunks * HW + (int64_t)c * HW + p;
 }
 
 template <int ORDER>
@@ -612,7 +672,15 @@ __device__ __forceinline__ void save_run(int32_t *rec, int64_t stride, const Run
     rec[R_FI1 * stride] = r.fi1;
     rec[R_FLO * stride] = r.st.flo;
     rec[R_FHI * stride] = r.st.fhi;
-    if constexpr (ORDER != 2) {
+    if constexpr (ORDER == 4) {
+        const int32_t v[R_NFIELDS - R_P3] = {r.st.p3, r.st.c20, r.st.c21, r.st.b20, r.st.b21,
+                                             r.st.m0, r.st.m1, r.st.m2, r.st.m3, r.st.hl0,
+                                             r.st.hl1, r.st.hl2, r.st.hl3, r.st.hh0, r.st.hh1,
+                                             r.st.hh2, r.st.hh3};
+#pragma unroll
+        for (int f = 0; f < R_NFIELDS - R_P3; f++) rec[(R_P3 + f) * stride] = v[f];
+    }
+    if constexpr (ORDER != 2 && ORDER != 4) {
         rec[R_FWLO * stride] = r.fwlo;
         rec[R_FWHI * stride] = r.fwhi;
     } else {
@@ -643,7 +711,29 @@ __device__ __forceinline__ void load_run(const int32_t *rec, int64_t stride, Run
     r.fi1 = rec[R_FI1 * stride];
     r.st.flo = rec[R_FLO * stride];
     r.st.fhi = rec[R_FHI * stride];
-    if constexpr (ORDER != 2) {
+    if constexpr (ORDER == 4) {
+        int32_t v[R_NFIELDS - R_P3];
+#pragma unroll
+        for (int f = 0; f < R_NFIELDS - R_P3; f++) v[f] = rec[(R_P3 + f) * stride];
+        r.st.p3 = v[0];
+        r.st.c20 = v[1];
+        r.st.c21 = v[2];
+        r.st.b20 = v[3];
+        r.st.b21 = v[4];
+        r.st.m0 = v[5];
+        r.st.m1 = v[6];
+        r.st.m2 = v[7];
+        r.st.m3 = v[8];
+        r.st.hl0 = v[9];
+        r.st.hl1 = v[10];
+        r.st.hl2 = v[11];
+        r.st.hl3 = v[12];
+        r.st.hh0 = v[13];
+        r.st.hh1 = v[14];
+        r.st.hh2 = v[15];
+        r.st.hh3 = v[16];
+    }
+    if constexpr (ORDER != 2 && ORDER != 4) {
         r.fwlo = rec[R_FWLO * stride];
         r.fwhi = rec[R_FWHI * stride];
     } else {
@@ -676,6 +766,25 @@ __device__ __forceinline__ bool same_decisions(const SegState &a, const SegState
             return false;
         if (a1 && (a.ii - a.l1 != b.ii - b.l1 || a.g1l != b.g1l || a.g1h != b.g1h))
             return false;
+        if constexpr (ORDER == 4) {
+            // third order: the same values seen in the sub-piece and, per
+            // S2-value slot, the same validity, distance back and S3 extremes
+            if ((a.l0 >= a.p3) != (b.l0 >= b.p3) || (a.l1 >= a.p3) != (b.l1 >= b.p3))
+                return false;
+            auto slot = [](int32_t am, int32_t ab, int32_t ac, int32_t ahl, int32_t ahh,
+                           int32_t bm, int32_t bb, int32_t bc, int32_t bhl, int32_t bhh) {
+                const bool av = am >= ab, bv = bm >= bb;
+                return av == bv && (!av || (ac - am == bc - bm && ahl == bhl && ahh == bhh));
+            };
+            if (a.l0 >= a.p3 &&
+                !(slot(a.m0, a.b20, a.c20, a.hl0, a.hh0, b.m0, b.b20, b.c20, b.hl0, b.hh0) &&
+                  slot(a.m1, a.b20, a.c20, a.hl1, a.hh1, b.m1, b.b20, b.c20, b.hl1, b.hh1)))
+                return false;
+            if (a.l1 >= a.p3 &&
+                !(slot(a.m2, a.b21, a.c21, a.hl2, a.hh2, b.m2, b.b21, b.c21, b.hl2, b.hh2) &&
+                  slot(a.m3, a.b21, a.c21, a.hl3, a.hh3, b.m3, b.b21, b.c21, b.hl3, b.hh3)))
+                return false;
+        }
         return true;
     }
 }

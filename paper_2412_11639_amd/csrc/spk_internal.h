@@ -31,25 +31,26 @@ struct ReconParams {
 
 enum Mode { MODE_RECON = 0, MODE_SEGMENTS = 1 };
 
-// Fields of one per-chunk state record.
-constexpr int kRecFields = 20;
+// Fields of one per-chunk state record (the most any order keeps).
+constexpr int kRecFields = 37;
 
 // How a stream is cut into time chunks processed by separate waves.
 struct ChunkPlan {
     int nchunks = 1;
     int chunk_tiles = 1 << 30;  // 64-frame tiles per chunk
     int warm_tiles = 0;         // tiles of speculative warm-up before a chunk
-    int32_t *rec = nullptr;     // device [2][kRecFields][nchunks][HW] int32 when nchunks > 1
+    int fields = kRecFields;    // record fields the order keeps
+    int32_t *rec = nullptr;     // device [2][fields][nchunks][HW] int32 when nchunks > 1
 };
 
-// Number of chunks for a stream (requested <= 0: automatic; warm < 0:
-// automatic warm-up length).
-ChunkPlan plan_chunks(int32_t HW, int32_t T, int requested, int warm = -1);
+// Number of chunks for a stream of the given order (requested <= 0:
+// automatic; warm < 0: automatic warm-up length).
+ChunkPlan plan_chunks(int32_t HW, int32_t T, int order, int requested, int warm = -1);
 
 // Ints of device workspace a plan needs.
 inline size_t chunk_record_ints(const ChunkPlan &cp, int32_t HW)
 {
-    return cp.nchunks > 1 ? (size_t)2 * kRecFields * cp.nchunks * (size_t)HW : 0;
+    return cp.nchunks > 1 ? (size_t)2 * cp.fields * cp.nchunks * (size_t)HW : 0;
 }
 
 // Device tables of one output-time list (cached per device; a table stays

@@ -65,7 +65,7 @@ FAKE = 4096  # a non-null pointer value; validation must fail before any use
     dict(n_out=-1),
     dict(t_out=[5, 10]),          # 10 >= T
     dict(t_out=[-1]),
-    dict(order=0), dict(order=4),
+    dict(order=0), dict(order=5),
     dict(out=0),
     dict(H=65536, W=65536),       # H*W overflows int32
 ])
@@ -154,7 +154,7 @@ def test_plan_create_rejects_bad_arguments(lib):
     h = ctypes.c_void_p()
     assert lib.spk_plan_create(None, arr, 1, 1, 0) == -1
     assert lib.spk_plan_create(ctypes.byref(h), arr, 0, 1, 0) == -1
-    assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 4, 0) == -1
+    assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 5, 0) == -1
     assert lib.spk_plan_create(ctypes.byref(h), arr, 1, 1, 8) == -1
     assert lib.spk_plan_execute(None, None) == -1
     assert lib.spk_plan_destroy(None) == 0

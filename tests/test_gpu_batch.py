@@ -42,7 +42,7 @@ def check_against_oracle(jobs, outs, order):
         np.testing.assert_array_equal(out.cpu().numpy(), ref.astype(np.float32))
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 @pytest.mark.parametrize("unsorted", [False, True])
 def test_plan_matches_oracle(spk, order, unsorted):
     jobs = make_jobs(1, unsorted)

@@ -349,3 +349,30 @@ def test_decode_of_cut_lists_is_nan_past_cap(spk):
                 assert got[k, p] == ref[k, p], (p, t)
             else:
                 assert np.isnan(got[k, p]), (p, t)
+
+
+# --------------------------------------------------------------------------
+# the third order (n-order rule one step past SSR)
+
+@pytest.mark.parametrize("n_chunks", [0, 3, 24])
+def test_third_order(spk, chunks, n_chunks):
+    chunks(n_chunks)
+    H, W, T = 37, 91, 3001
+    s = spkgen.gratings(H, W, T, seed=17)
+    check_recon(spk, s, H, W, T, list(range(0, T, 5)) + [T - 1, 0], spk.TSR)
+    check_segments(spk, s, H, W, T, spk.TSR, cap=T)
+    rng = np.random.default_rng(18)
+    bits = _two_value_streams(rng, 6 * 120, 1500)
+    check_recon(spk, spkgen.pack(bits), 6, 120, 1500, list(range(0, 1500, 7)), spk.TSR)
+    s = spkgen.blocks(48, 80, 2048, seed=19, vx=0.3, vy=0.2)
+    check_recon(spk, s, 48, 80, 2048, list(range(3, 2048, 11)), spk.TSR)
+
+
+def test_third_order_every_stream_of_12_frames(spk):
+    T = 12
+    n = 1 << T
+    p = np.arange(n)
+    bits = ((p[None, :] >> np.arange(T)[:, None]) & 1).astype(np.uint8)
+    s = spkgen.pack(bits)
+    check_segments(spk, s, 32, 128, T, spk.TSR, cap=T)
+    check_recon(spk, s, 32, 128, T, list(range(T)), spk.TSR)
