@@ -134,6 +134,21 @@ int spk_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
             int32_t window, const int32_t *t_out, int32_t n_out, float *out, void *hip_stream);
 
 /*
+ * Static / motion mask (the use of the stability theorem the paper's
+ * conclusion names: stable and unstable spike emission tell static from
+ * moving parts).  mask[k][p] = 1 when the segment of the given order that
+ * holds the interval in progress at t_out[k] begins at a cut less than
+ * `window` frames back (its first spike f > t - window and it is not the
+ * pixel's first segment), else 0; 0 for pixels with fewer than two spikes.
+ * mask: device uint8 [n_out][H][W].  window >= 1, n_out <= 65535; other
+ * arguments and errors as spk_reconstruct.  Uses temporary device memory
+ * from the stream-ordered allocator.
+ */
+int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
+               int32_t window, const int32_t *t_out, int32_t n_out, uint8_t *mask,
+               void *hip_stream);
+
+/*
  * Decoder of the segment encoding (the encoder/decoder split of the
  * paper's hardware design, Sec. III-C): the intensity at each requested
  * frame from segment lists as spk_segments writes them (seg_first,

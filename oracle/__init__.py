@@ -136,6 +136,17 @@ def tfp(stream, H, W, T, theta, window, t_out, lib=None):
     return out
 
 
+def motion(stream, H, W, T, window, t_out, order=SSR, lib=None):
+    """Static / motion mask (uint8 [n_out, H, W]): 1 where the segment that
+    holds the interval in progress at t began at a cut less than ``window``
+    frames back -- its first spike f > t - window and it is not the pixel's
+    first segment (whose start is the first spike, no cut)."""
+    _, wf, _, _ = reconstruct(stream, H, W, T, 1.0, t_out, order=order, windows=True, lib=lib)
+    first = segments(stream, H, W, T, order=order, cap=1, lib=lib)[0][0].reshape(H, W)
+    t = np.asarray(t_out, dtype=np.int64).reshape(-1, 1, 1)
+    return ((wf >= 0) & (wf != first[None]) & (wf > t - window)).astype(np.uint8)
+
+
 def segments(stream, H, W, T, order=FSR, cap=64, nthreads=None, lib=None):
     """All segments per pixel: (first, last, n) each [cap, H*W] int32, and
     the total count per pixel [H*W]."""

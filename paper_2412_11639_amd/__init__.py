@@ -22,7 +22,7 @@ SSR = 2
 TFI = 3
 TSR = 4
 
-__all__ = ["FSR", "SSR", "TFI", "TSR", "SpkError", "tfp", "decode", "frame_bytes", "reconstruct", "reconstruct_windows",
+__all__ = ["FSR", "SSR", "TFI", "TSR", "SpkError", "tfp", "decode", "motion", "frame_bytes", "reconstruct", "reconstruct_windows",
            "segments", "version", "set_time_chunks", "get_time_chunks", "Plan",
            "PLAN_AUTOTUNE", "PLAN_NO_GRAPH"]
 
@@ -122,6 +122,19 @@ def decode(seg_first, seg_last, seg_n, count, H, W, T, theta, t_out, out=None, s
                                 out.data_ptr(), _stream_handle(stream))
     _lib.check("spk_decode", rc)
     return out
+
+
+def motion(stream_t, H, W, T, window, t_out, order=SSR, stream=None):
+    """Static / motion mask, uint8 [n_out, H, W]: 1 where the segment holding
+    t begins at a cut less than ``window`` frames back."""
+    _check_stream_tensor(stream_t, H, W, T)
+    t, tp = _host_times(t_out)
+    n_out = len(t)
+    mask = torch.empty((n_out, H, W), dtype=torch.uint8, device=stream_t.device)
+    rc = _lib.load().spk_motion(stream_t.data_ptr(), H, W, T, order, int(window), tp, n_out,
+                                mask.data_ptr(), _stream_handle(stream))
+    _lib.check("spk_motion", rc)
+    return mask
 
 
 def reconstruct_windows(stream_t, H, W, T, theta, t_out, order=FSR, stream=None):

@@ -49,6 +49,9 @@ def _declare(lib):
     lib.spk_decode.restype = ctypes.c_int
     lib.spk_decode.argtypes = [P_i32, P_i32, P_i32, P_i32, c_i32, c_i32, c_i32, c_i32,
                                ctypes.c_float, P_i32, c_i32, P_f32, ctypes.c_void_p]
+    lib.spk_motion.restype = ctypes.c_int
+    lib.spk_motion.argtypes = [P_u8, c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, c_i32,
+                               ctypes.c_void_p, ctypes.c_void_p]
     lib.spk_segments.restype = ctypes.c_int
     lib.spk_segments.argtypes = [P_u8, c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32,
                                  P_i32, ctypes.c_void_p]

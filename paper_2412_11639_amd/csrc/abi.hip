@@ -263,6 +263,25 @@ int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t strea
 
 }  // namespace spk
 
+namespace {
+
+// Motion mask (see spk.h): the segment holding t started at a cut less than
+// `window` frames back.
+__global__ void motion_kernel(const int32_t *win_first, const int32_t *first_spike, int64_t HW,
+                              int32_t window, const int32_t *t_sorted, const int32_t *plane,
+                              uint8_t *mask)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= HW) return;
+    const int32_t j = blockIdx.y, t = t_sorted[j];
+    const int64_t o = (int64_t)plane[j] * HW + p;
+    const int32_t f = win_first[o];
+    // f < 0: fewer than two spikes; f == the first spike: no cut before it
+    mask[o] = f >= 0 && f != first_spike[p] && f > t - window;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t spk_frame_bytes(int32_t H, int32_t W)
@@ -323,6 +342,55 @@ int spk_reconstruct_windows(const uint8_t *stream, int32_t H, int32_t W, int32_t
 {
     return reconstruct_impl(stream, H, W, T, theta, t_out, n_out, out, win_first, win_last,
                             win_n, order, hip_stream);
+}
+
+int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
+               int32_t window, const int32_t *t_out, int32_t n_out, uint8_t *mask,
+               void *hip_stream)
+{
+    int rc = check_common(stream, H, W, T, order);
+    if (rc) return rc;
+    if (window < 1 || n_out < 0) return SPK_EINVAL;
+    if (n_out == 0) return SPK_OK;
+    if (!t_out || !mask) return SPK_EINVAL;
+    const int64_t HW = (int64_t)H * W;
+    if ((int64_t)n_out * HW > ((int64_t)1 << 60) || n_out > 65535) return SPK_EINVAL;
+    for (int32_t k = 0; k < n_out; k++)
+        if (t_out[k] < 0 || t_out[k] >= T) return SPK_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int32_t *tmp = nullptr;
+    const size_t ints = (size_t)n_out * (size_t)HW + (size_t)HW;
+    if (hipMallocAsync((void **)&tmp, ints * sizeof(int32_t), st) != hipSuccess) return SPK_ENOMEM;
+    int32_t *wf = tmp, *first = tmp + (size_t)n_out * (size_t)HW;
+    // window of the segment holding each t, and each pixel's first spike
+    // (the start of its first segment)
+    rc = reconstruct_impl(stream, H, W, T, 1.0f, t_out, n_out, nullptr, wf, nullptr, nullptr,
+                          order, hip_stream);
+    int32_t *count = nullptr;
+    if (!rc && hipMallocAsync((void **)&count, (size_t)HW * sizeof(int32_t), st) != hipSuccess)
+        rc = SPK_ENOMEM;
+    if (!rc) {
+        int32_t *last = nullptr, *nn = nullptr;
+        if (hipMallocAsync((void **)&last, 2 * (size_t)HW * sizeof(int32_t), st) != hipSuccess) {
+            rc = SPK_ENOMEM;
+        } else {
+            nn = last + HW;
+            rc = spk_segments(stream, H, W, T, order, 1, first, last, nn, count, hip_stream);
+            hipFreeAsync(last, st);
+        }
+    }
+    if (!rc) {
+        spk::OutTables tab;
+        rc = spk::out_tables(T, t_out, n_out, st, &tab);
+        if (!rc) {
+            hipLaunchKernelGGL(motion_kernel, dim3((unsigned)((HW + 255) / 256), n_out), dim3(256),
+                               0, st, wf, first, HW, window, tab.t_sorted, tab.plane, mask);
+            if (hipGetLastError() != hipSuccess) rc = SPK_EHIP;
+        }
+    }
+    if (count) hipFreeAsync(count, st);
+    hipFreeAsync(tmp, st);
+    return rc;
 }
 
 int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,

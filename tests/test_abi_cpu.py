@@ -118,6 +118,21 @@ def test_decode_rejects_bad_arguments(lib, args):
     assert rc == -1
 
 
+@pytest.mark.parametrize("args", [
+    dict(stream=0), dict(H=0), dict(order=0), dict(window=0), dict(n_out=-1),
+    dict(t_out=[10]), dict(mask=0),
+])
+def test_motion_rejects_bad_arguments(lib, args):
+    a = dict(stream=FAKE, H=4, W=4, T=10, order=2, window=5, t_out=[0, 5], n_out=None,
+             mask=FAKE)
+    a.update(args)
+    t = (ctypes.c_int32 * max(1, len(a["t_out"])))(*a["t_out"])
+    n_out = len(a["t_out"]) if a["n_out"] is None else a["n_out"]
+    rc = lib.spk_motion(a["stream"], a["H"], a["W"], a["T"], a["order"], a["window"],
+                        ctypes.addressof(t), n_out, a["mask"], None)
+    assert rc == -1
+
+
 def test_zero_outputs_is_noop(lib):
     # n_out == 0 returns before any device work
     assert lib.spk_reconstruct(FAKE, 4, 4, 10, 1.0, None, 0, None, 1, None) == 0

@@ -376,3 +376,14 @@ def test_third_order_every_stream_of_12_frames(spk):
     s = spkgen.pack(bits)
     check_segments(spk, s, 32, 128, T, spk.TSR, cap=T)
     check_recon(spk, s, 32, 128, T, list(range(T)), spk.TSR)
+
+
+@pytest.mark.parametrize("order", [1, 2, 4])
+def test_motion_mask(spk, order):
+    H, W, T = 37, 91, 2500
+    for s in (spkgen.blocks(H, W, T, seed=24, vx=0.4, vy=-0.2), spkgen.gratings(H, W, T, seed=25)):
+        t_out = list(range(0, T, 9)) + [T - 1, 3, 3]
+        got = spk.motion(dev(s), H, W, T, 48, t_out, order=order)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(),
+                                      oracle.motion(s, H, W, T, 48, t_out, order=order))

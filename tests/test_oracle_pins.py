@@ -493,3 +493,37 @@ def test_third_order_refines_ssr_on_generated_scenes():
     assert tc.sum() > sc.sum()
     for p in range(H * W):
         assert set(sl[:sc[p], p].tolist()) <= set(tl[:tc[p], p].tolist())
+
+
+# --------------------------------------------------------------------------
+# static / motion mask (the theorem's use named in the conclusion)
+
+def test_motion_mask_constant_light_is_static():
+    """Theorem 1: constant light keeps one segment, so no pixel is ever
+    marked as moving, whatever the window."""
+    rng = np.random.default_rng(8)
+    H, W, T = 4, 64, 1500
+    th = 4096
+    s = spkgen.from_increments(rng.integers(1, th + 1, H * W), rng.integers(0, th, H * W), th,
+                               H, W, T=T)
+    for order in (oracle.FSR, oracle.SSR, oracle.TSR):
+        m = oracle.motion(s, H, W, T, 64, list(range(0, T, 13)), order=order)
+        assert m.sum() == 0
+
+
+def test_motion_mask_after_a_step_in_light():
+    """Intervals 4 up to frame ~200, then 9: FSR cuts at the first 9, whose
+    segment starts at the last spike f of the 4-run.  With window L the mask
+    is 1 exactly for t in (f, f + L) and 0 before."""
+    T = 600
+    tau = list(range(2, 203, 4))
+    f = tau[-1]
+    tau += list(range(f + 9, T, 9))
+    bits = np.zeros((T, 1), dtype=np.uint8)
+    bits[tau, 0] = 1
+    s = spkgen.pack(bits)
+    L = 50
+    t_out = list(range(T))
+    m = oracle.motion(s, 1, 1, T, L, t_out, order=oracle.FSR)[:, 0, 0]
+    want = np.array([1 if f < t < f + L else 0 for t in t_out], dtype=np.uint8)
+    np.testing.assert_array_equal(m, want)
