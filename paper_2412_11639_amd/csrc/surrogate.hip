@@ -606,14 +606,25 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
     if (tid < CO * 8 && tid % 8 == 0) out[S::nw + tid / 8] = bsum;
 }
 
-// dst[j] = sum over blocks of partial[blk][j], blocks in order
-__global__ void reduce_kernel(const float *partial, int nblocks, int np, float *dst)
+// dst[j] = sum over blocks of partial[blk][j] in a fixed order: 16 threads
+// per weight each add every 16th block (in block order), then the 16 sums
+// are added in a fixed tree.  A workgroup covers 16 consecutive weights.
+__global__ __launch_bounds__(256) void reduce_kernel(const float *partial, int nblocks, int np,
+                                                     float *dst)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= np) return;
+    __shared__ float red[16][17];
+    const int jl = threadIdx.x & 15, part = threadIdx.x >> 4;
+    const int j = blockIdx.x * 16 + jl;
     float acc = 0.0f;
-    for (int k = 0; k < nblocks; k++) acc += partial[(int64_t)k * np + j];
-    dst[j] = acc;
+    if (j < np)
+        for (int k = part; k < nblocks; k += 16) acc += partial[(int64_t)k * np + j];
+    red[part][jl] = acc;
+    __syncthreads();
+    for (int s = 8; s > 0; s >>= 1) {
+        if (part < s) red[part][jl] += red[part + s][jl];
+        __syncthreads();
+    }
+    if (part == 0 && j < np) dst[j] = red[0][jl];
 }
 
 // The weight-gradient kernels produce dW[co][tap][ci] and db[co] per layer,
@@ -716,8 +727,8 @@ void launch_wgrad(WgArgs a, float *dst, hipStream_t st)
     const int nblk = a.ntiles < kWgMaxBlocks ? a.ntiles : kWgMaxBlocks;
     hipLaunchKernelGGL(wgrad_kernel<K>, dim3(nblk), dim3(256), 0, st, a);
     const int np = WgShape<K>::np;
-    hipLaunchKernelGGL(reduce_kernel, dim3((np + 255) / 256), dim3(256), 0, st, a.partial, nblk,
-                       np, dst);
+    hipLaunchKernelGGL(reduce_kernel, dim3((np + 15) / 16), dim3(256), 0, st, a.partial, nblk, np,
+                       dst);
 }
 
 void forward_all(const float *params, const uint32_t *win, const float *est, int B, int Hc,
