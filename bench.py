@@ -270,7 +270,7 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
         a.record()
         sur.Surrogate.stream_step(ds[t], H, W, 1.0, win, est, st)
         if t >= 31:
-            model.forward(win, est, out=y)
+            model.infer(win, est, out=y)
             sur.Surrogate.mux(y, est, st, out=mx)
         b.record()
         if t in slot:
@@ -284,7 +284,7 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     fwd = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fwd[0].record()
     for _ in range(20):
-        model.forward(win, est, out=y)
+        model.infer(win, est, out=y)
     fwd[1].record()
     torch.cuda.synchronize()
     fwd_ms = fwd[0].elapsed_time(fwd[1]) / 20

@@ -83,10 +83,16 @@ int spk_version(void);
  *                        (the default; the SPK_CHUNKS environment variable
  *                        overrides it at first use).  Values above the
  *                        number of 64-frame tiles are clamped.
+ *   SPK_OPT_SUR_FUSED    0 (default): one kernel per surrogate layer;
+ *                        1: two layers per kernel with the intermediate
+ *                        layer kept in LDS.  Same results bit for bit; the
+ *                        two-layer kernels hold both layers' weights in
+ *                        registers and run at lower occupancy, so they are
+ *                        the slower of the two on gfx950.
  * spk_set_option returns SPK_OK or SPK_EINVAL (unknown option, value < 0);
  * spk_get_option returns the value or SPK_EINVAL.
  */
-enum { SPK_OPT_TIME_CHUNKS = 1 };
+enum { SPK_OPT_TIME_CHUNKS = 1, SPK_OPT_SUR_FUSED = 2 };
 int spk_set_option(int option, int value);
 int spk_get_option(int option);
 
@@ -260,6 +266,12 @@ int spk_sur_stream_step(const uint8_t *frame, int32_t H, int32_t W, float theta,
 /* y = network(win, est), float32 [B][Hc][Wc]. */
 int spk_sur_forward(const float *params, const uint32_t *win, const float *est, int32_t B,
                     int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream);
+
+/* As spk_sur_forward for inference only; y is identical.  With
+ * SPK_OPT_SUR_FUSED = 1 the activations the backward pass reads are not
+ * written (less memory traffic); layer by layer it equals spk_sur_forward. */
+int spk_sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
+                  int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream);
 
 /* Gradient of the mean squared error between y and target over all B*Hc*Wc
  * pixels with respect to the parameters (grad: float32 [SPK_SUR_NPARAMS],

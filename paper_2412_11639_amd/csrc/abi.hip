@@ -244,6 +244,8 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
 
 namespace spk {
 
+int g_sur_fused = 0;
+
 int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
                OutTables *out)
 {
@@ -312,6 +314,10 @@ int spk_set_option(int option, int value)
         if (value < 0) return SPK_EINVAL;
         g_chunks = value;
         return SPK_OK;
+    case SPK_OPT_SUR_FUSED:
+        if (value != 0 && value != 1) return SPK_EINVAL;
+        spk::g_sur_fused = value;
+        return SPK_OK;
     default:
         return SPK_EINVAL;
     }
@@ -322,6 +328,7 @@ int spk_get_option(int option)
     std::lock_guard<std::mutex> lock(g_mu);
     switch (option) {
     case SPK_OPT_TIME_CHUNKS: return requested_chunks();
+    case SPK_OPT_SUR_FUSED: return spk::g_sur_fused;
     default: return SPK_EINVAL;
     }
 }

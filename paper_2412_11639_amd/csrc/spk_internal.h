@@ -65,6 +65,10 @@ struct OutTables {
 int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
                OutTables *out);
 
+// SPK_OPT_SUR_FUSED: surrogate forward layer by layer (0, default) or
+// through the two-layer kernels (1).
+extern int g_sur_fused;
+
 // Enqueue the plain FSR/SSR reconstruction (or segment listing) on stream.
 hipError_t launch_recon(const ReconParams &p, int order, Mode mode, const ChunkPlan &cp,
                         hipStream_t stream);

@@ -170,3 +170,30 @@ def test_training_reduces_loss_and_beats_short_window(sur):
         err_est.append(((est - tgt) ** 2).mean().item())
     print("held-out MSE net %.3g est %.3g" % (np.mean(err_net), np.mean(err_est)))
     assert np.mean(err_net) < np.mean(err_est)
+
+
+@pytest.mark.parametrize("shape", [(2, 16, 16), (3, 19, 37), (1, 70, 45), (1, 1, 5)])
+def test_fused_forward_equals_layer_by_layer(sur, shape):
+    """The two-layer kernels give the layer-by-layer result bit for bit,
+    keep the same activations for the backward pass, and inference equals
+    the training forward."""
+    import paper_2412_11639_amd as spk
+    rng = np.random.default_rng(9)
+    B, Hc, Wc = shape
+    model = sur.Surrogate(sur.init_params(6) + rng.normal(0, 0.05, sur.NPARAMS))
+    win, est = _to_dev(*_rand_batch(rng, B, Hc, Wc))
+    target = torch.rand((B, Hc, Wc), device="cuda")
+    res = {}
+    for fused in (False, True):
+        spk.set_surrogate_fused(fused)
+        try:
+            y = model.forward(win, est)
+            model.backward(win, est, y, target)
+            res[fused] = (y.clone(), model.grad.clone(), model.infer(win, est).clone())
+        finally:
+            spk.set_surrogate_fused(False)
+    torch.cuda.synchronize()
+    assert torch.equal(res[False][0], res[True][0])
+    assert torch.equal(res[False][1], res[True][1])
+    assert torch.equal(res[True][2], res[True][0])
+    assert torch.equal(res[False][2], res[False][0])
