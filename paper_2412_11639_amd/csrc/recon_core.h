@@ -108,32 +108,25 @@ __device__ __forceinline__ int xcd_strip(int b, int nblocks)
     return xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
 }
 
-// OR of (w >> d) for d = 1..k, 0 <= k <= 15: bit j is set when some spike
-// lies within k frames after frame j.
-__device__ __forceinline__ uint64_t smear_down(uint64_t w, int k)
+// True when every gap between consecutive spikes of the nonzero word w (c
+// spikes) is a, or a or a + 1 when plus1; 1 <= a <= 62.  No walk: the c - 1
+// gaps sum to the distance from the first spike to the last.  Give each
+// spike but the last the spike a frames later if there is one, else (plus1)
+// the one a + 1 frames later, and fail if neither exists.  Each chosen gap is
+// at least the true one, so the chosen gaps sum to that distance exactly
+// when every true gap is a or a + 1; the n1 = popc(w & (w >> a)) gaps of a
+// and c - 1 - n1 of a + 1 sum to (c - 1)(a + 1) - n1.
+__device__ __forceinline__ bool gaps_within(uint64_t w, int a, bool plus1, int32_t c)
 {
-    const uint64_t r1 = w >> 1, r2 = r1 | (r1 >> 1), r4 = r2 | (r2 >> 2), r8 = r4 | (r4 >> 4);
-    uint64_t s = (k & 8) ? r8 : 0;
-    int sh = k & 8;
-    s |= ((k & 4) ? r4 : 0) >> sh;
-    sh += k & 4;
-    s |= ((k & 2) ? r2 : 0) >> sh;
-    sh += k & 2;
-    s |= ((k & 1) ? r1 : 0) >> sh;
-    return s;
+    const int hi = 63 - __builtin_clzll(w), lo = __builtin_ctzll(w);
+    const uint64_t rest = w & ~(1ull << hi);
+    const uint64_t s1 = w >> a, s2 = plus1 ? (s1 >> 1) : 0ull;
+    const int32_t n1 = __builtin_popcountll(w & s1);
+    const int32_t sum = plus1 ? (c - 1) * (a + 1) - n1 : (c - 1) * a;
+    return !(rest & ~(s1 | s2)) && sum == hi - lo;
 }
 
-// True when every gap between consecutive spikes of the nonzero word w is a
-// (or a + 1 when plus1), 1 <= a <= 15.
-__device__ __forceinline__ bool gaps_within(uint64_t w, int a, bool plus1)
-{
-    const uint64_t near = smear_down(w, a - 1);  // another spike closer than a
-    const uint64_t within = near | (w >> a) | (plus1 ? (w >> (a + 1)) : 0ull);
-    const uint64_t top = 1ull << (63 - __builtin_clzll(w));
-    return !(w & near) && (w & ~within) == top;
-}
-
-constexpr int kFastMaxGap = 15;  // word-level shortcut for intervals up to this
+constexpr int kFastMaxGap = 62;  // word-level shortcut for intervals up to this
 
 // Segmentation state of one pixel (registers).
 struct SegState {
@@ -185,7 +178,7 @@ struct SegState {
         } else if constexpr (ORDER == 1) {
             const int32_t a = flo;
             if (a < 1 || a > kFastMaxGap || x0 < a || x0 > a + 1) return false;
-            if (!gaps_within(w, a, true)) return false;
+            if (!gaps_within(w, a, true, c)) return false;
             // a gap of a + 1 somewhere (the others are exactly a)
             const bool wide = x0 == a + 1 || popc64(w & (w >> a)) < c - 1;
             fhi = max(fhi, wide ? a + 1 : a);
@@ -198,7 +191,7 @@ struct SegState {
                 // waiting): vote on its cheap preconditions first
                 const int32_t a = flo;
                 const bool pre = a >= 1 && a <= kFastMaxGap && fhi <= a + 1 && x0 <= a + 1 &&
-                                 gaps_within(w, a, true);
+                                 gaps_within(w, a, true, c);
                 if (popc64(__ballot(pre)) * 4 < popc64(__ballot(1)) * 3) return false;
                 return pre && two_values(w, x0, c);
             }
@@ -206,7 +199,7 @@ struct SegState {
             // the word opens with a value below the segment's single value:
             // only words of that one value (all S2 gaps inside are 1)
             if (v > kFastMaxGap) return false;
-            if (c > 1 && !gaps_within(w, v, false)) return false;
+            if (c > 1 && !gaps_within(w, v, false, c)) return false;
             const bool odd = v & 1;
             const int32_t l = odd ? l1 : l0;
             int32_t gl = kBig, gh = -kBig;
@@ -287,38 +280,54 @@ struct SegState {
                 gJl = min(gJl, 1);
                 gJh = max(gJh, 1);
             }
-            if (MJ & (MM << xJ) & (MJ << (xJ + xM))) {
+            if (xJ + xM < 64 && (MJ & (MM << xJ) & (MJ << (xJ + xM)))) {
                 gJl = min(gJl, 2);
                 gJh = max(gJh, 2);
             }
             nlJ = ii + popc64(w & ((1ull << hibit64(MJ)) - 1));
         }
         if (gJh - gJl > 1) return false;
-        // the isolated value: walk its occurrences
+        // the isolated value: a gap of k intervals between two of its
+        // occurrences is k*xJ + (xM - xJ) frames.  Its n occurrences in the
+        // word have n - 1 gaps summing to K (the difference of their interval
+        // numbers); the gaps have span <= 1 only if they lie in {g, g + 1}
+        // with g = floor(K / (n - 1)).  Send each occurrence but the last to
+        // the nearer of the occurrences g and g + 1 intervals later (one must
+        // exist); that gap is at least the true one, and the counts n1, n2 of
+        // each choice give n1*g + n2*(g + 1) >= K, equal exactly when every
+        // true gap is g or g + 1.  No walk over the occurrences is needed.
         if (MM) {
             const uint64_t fM = MM & (~MM + 1);
             const int32_t first = ii + popc64(w & (fM - 1));
+            const int hM = hibit64(MM);
+            const int32_t lastM = ii + popc64(w & ((1ull << hM) - 1));
             if (seenM) {
                 gMl = min(gMl, first - lM);
                 gMh = max(gMh, first - lM);
             }
-            uint64_t m = MM & (MM - 1);
-            int32_t prev = ctz64(MM), dmin = kBig, dmax = -kBig;
-            while (m) {
-                const int32_t q = ctz64(m);
-                m &= m - 1;
-                dmin = min(dmin, q - prev);
-                dmax = max(dmax, q - prev);
-                prev = q;
+            const int32_t n = popc64(MM);
+            if (n >= 2) {
+                const int32_t K = lastM - first;
+                // K / (n - 1) with K <= 63: the fraction is a multiple of
+                // 1/(n - 1) >= 1/31, far above the reciprocal's error
+                const int32_t g = (int32_t)fmaf((float)K, __builtin_amdgcn_rcpf((float)(n - 1)),
+                                                1e-3f);
+                const int32_t D1 = g * xJ + (xM - xJ), D2 = D1 + xJ;
+                const uint64_t s1 = D1 < 64 ? MM >> D1 : 0ull, s2 = D2 < 64 ? MM >> D2 : 0ull;
+                const uint64_t rest = MM & ~(1ull << hM);
+                if (rest & ~(s1 | s2)) return false;
+                const int32_t n1 = popc64(rest & s1), n2 = n - 1 - n1;
+                if (n1 * g + n2 * (g + 1) != K) return false;
+                if (n1) {
+                    gMl = min(gMl, g);
+                    gMh = max(gMh, g);
+                }
+                if (n2) {
+                    gMl = min(gMl, g + 1);
+                    gMh = max(gMh, g + 1);
+                }
             }
-            if (dmax >= 0) {
-                // frame distances -> interval counts (exact multiples)
-                const float r = __builtin_amdgcn_rcpf((float)xJ);
-                const int32_t off = isoB ? -1 : 1;
-                gMl = min(gMl, (int32_t)rintf((float)(dmin + off) * r));
-                gMh = max(gMh, (int32_t)rintf((float)(dmax + off) * r));
-            }
-            nlM = ii + popc64(w & ((1ull << prev) - 1));
+            nlM = lastM;
         }
         if (gMh - gMl > 1) return false;
         fhi = max(fhi, MB ? a + 1 : a);

@@ -107,15 +107,16 @@ def test_gratings_ragged(spk, order):
     check_segments(spk, s, H, W, T, order, cap=400)
 
 
-def _two_value_streams(rng, P, T):
-    """Per pixel an interval sequence over {a, a+1} (a = 1..15): balanced
-    (constant-rate) sequences, balanced ones with two neighbours swapped,
-    i.i.d. ones and long runs -- so the two values' S2 streams are stable
-    over long stretches and then break at all kinds of places."""
+def _two_value_streams(rng, P, T, avals=tuple(range(1, 16)), group=15):
+    """Per pixel an interval sequence over {a, a+1} (a from avals in turn):
+    balanced (constant-rate) sequences, balanced ones with two neighbours
+    swapped, i.i.d. ones and long runs, the kind changing every group
+    pixels -- so the two values' S2 streams are stable over long stretches
+    and then break at all kinds of places."""
     bits = np.zeros((T, P), dtype=np.uint8)
     for p in range(P):
-        a = 1 + p % 15
-        kind = (p // 15) % 4
+        a = avals[p % len(avals)]
+        kind = (p // group) % 4
         n = T // a + 2
         if kind == 0 or kind == 1:
             frac = rng.uniform(0.02, 0.98)
@@ -146,6 +147,22 @@ def test_two_value_words(spk, chunks, order, n_chunks):
     bits = _two_value_streams(rng, H * W, T)
     s = spkgen.pack(bits)
     check_recon(spk, s, H, W, T, list(range(0, T, 7)) + [T - 1], order)
+    check_segments(spk, s, H, W, T, order, cap=T)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("n_chunks", [0, 5])
+def test_two_value_words_wide_gaps(spk, chunks, order, n_chunks):
+    """As above with intervals up to 63 frames (the shortcut takes a <= 62)
+    and one kind per 64-pixel strip, so whole waves take the word-level
+    shortcut (balanced strips) or leave it (i.i.d. and run strips)."""
+    chunks(n_chunks)
+    rng = np.random.default_rng(12)
+    H, W, T = 8, 128, 2500
+    avals = tuple(range(1, 16)) + (16, 17, 21, 31, 32, 33, 40, 47, 60, 61, 62, 63)
+    bits = _two_value_streams(rng, H * W, T, avals=avals, group=64)
+    s = spkgen.pack(bits)
+    check_recon(spk, s, H, W, T, list(range(0, T, 5)) + [T - 1], order)
     check_segments(spk, s, H, W, T, order, cap=T)
 
 
