@@ -17,6 +17,16 @@ constexpr int kWarmTiles = 4;        // speculative warm-up before a chunk
 constexpr int kCaptureTiles = 4;     // tiles after a chunk's start that record the
                                      // first segment's window for the fixup pass
 
+// Global-memory view of a pointer.  Pointers that reach a kernel through a
+// table in device memory (the batched jobs) are generic to the compiler,
+// which then emits flat loads and stores; those count against the LDS wait
+// counter too, so every LDS wait would also wait for the stream prefetch.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // ---- cross-lane moves ----------------------------------------------------
 
 template <int S>
@@ -442,7 +452,7 @@ struct Emitter {
     {
         if constexpr (PMAP == PMAP_IDENT) return k;
         else if constexpr (PMAP == PMAP_LDS) return plane_s[k];
-        else return P.plane[k];
+        else return gp(P.plane)[k];
     }
 
     // A closed segment spanning spike frames [first, last] with n intervals
@@ -454,9 +464,9 @@ struct Emitter {
         if constexpr (MODE == MODE_SEGMENTS) {
             if (segc < P.cap) {
                 const int64_t o = (int64_t)segc * P.HW + p;
-                P.seg_first[o] = first;
-                P.seg_last[o] = last;
-                P.seg_n[o] = n;
+                gp(P.seg_first)[o] = first;
+                gp(P.seg_last)[o] = last;
+                gp(P.seg_n)[o] = n;
             }
             segc++;
         } else {
@@ -466,19 +476,19 @@ struct Emitter {
             const float I = (float)(P.theta * (double)n / (double)(last - first));
             if constexpr (PMAP == PMAP_IDENT && !WIN) {
                 // planes in time order: step a pointer by one plane per output
-                float *q = P.out + p + (uint64_t)(uint32_t)k0 * (uint32_t)P.HW;
+                auto q = gp(P.out) + p + (uint64_t)(uint32_t)k0 * (uint32_t)P.HW;
                 for (int32_t k = k0; k < kend; k++, q += (uint32_t)P.HW) *q = I;
                 return;
             }
             for (int32_t k = k0; k < kend; k++) {
                 const int64_t o = (int64_t)(uint64_t)(uint32_t)plane(k) * (uint32_t)P.HW + p;
                 if constexpr (WIN) {
-                    if (P.out) P.out[o] = I;
-                    if (P.win_first) P.win_first[o] = first;
-                    if (P.win_last) P.win_last[o] = last;
-                    if (P.win_n) P.win_n[o] = n;
+                    if (P.out) gp(P.out)[o] = I;
+                    if (P.win_first) gp(P.win_first)[o] = first;
+                    if (P.win_last) gp(P.win_last)[o] = last;
+                    if (P.win_n) gp(P.win_n)[o] = n;
                 } else {
-                    P.out[o] = I;
+                    gp(P.out)[o] = I;
                 }
             }
         }
@@ -491,12 +501,12 @@ struct Emitter {
         for (int32_t k = 0; k < P.n_out; k++) {
             const int64_t o = (int64_t)plane(k) * P.HW + p;
             if constexpr (WIN) {
-                if (P.out) P.out[o] = 0.0f;
-                if (P.win_first) P.win_first[o] = -1;
-                if (P.win_last) P.win_last[o] = -1;
-                if (P.win_n) P.win_n[o] = 0;
+                if (P.out) gp(P.out)[o] = 0.0f;
+                if (P.win_first) gp(P.win_first)[o] = -1;
+                if (P.win_last) gp(P.win_last)[o] = -1;
+                if (P.win_n) gp(P.win_n)[o] = 0;
             } else {
-                P.out[o] = 0.0f;
+                gp(P.out)[o] = 0.0f;
             }
         }
     }
@@ -667,8 +677,9 @@ __device__ __forceinline__ int32_t *rec_start(const ChunkPlan &cp, int c, int64_
 }
 
 template <int ORDER>
-__device__ __forceinline__ void save_run(int32_t *rec, int64_t stride, const Run &r)
+__device__ __forceinline__ void save_run(int32_t *rec_, int64_t stride, const Run &r)
 {
+    const auto rec = gp(rec_);
     rec[R_LASTSPK * stride] = r.lastspk;
     rec[R_CNTLAST * stride] = r.cnt_last;
     rec[R_CUM * stride] = r.cum;
@@ -705,8 +716,9 @@ __device__ __forceinline__ void save_run(int32_t *rec, int64_t stride, const Run
 }
 
 template <int ORDER>
-__device__ __forceinline__ void load_run(const int32_t *rec, int64_t stride, Run &r)
+__device__ __forceinline__ void load_run(const int32_t *rec_, int64_t stride, Run &r)
 {
+    const auto rec = gp(rec_);
     r.reset(0);
     r.lastspk = rec[R_LASTSPK * stride];
     r.cnt_last = rec[R_CNTLAST * stride];
@@ -819,10 +831,10 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
             rlo[i] = rhi[i] = 0;
             rc[i] = 0;
             if (tg + i < tile1 && tr < P.T) {
-                const uint2 v = *(const uint2 *)(base + (int64_t)tr * P.fb);
-                rlo[i] = v.x;
-                rhi[i] = v.y;
-                if (P.cnt_le) rc[i] = P.cnt_le[tr];
+                const uint64_t v = *gp((const uint64_t *)(base + (int64_t)tr * P.fb));
+                rlo[i] = (uint32_t)v;
+                rhi[i] = (uint32_t)(v >> 32);
+                if (P.cnt_le) rc[i] = gp(P.cnt_le)[tr];
             }
         }
     };
