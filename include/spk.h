@@ -89,10 +89,14 @@ int spk_version(void);
  *                        two-layer kernels hold both layers' weights in
  *                        registers and run at lower occupancy, so they are
  *                        the slower of the two on gfx950.
+ *   SPK_OPT_SUR_CONV_WG  at most this many workgroups per layer-by-layer
+ *                        surrogate convolution, each walking a contiguous
+ *                        range of 16 x 16 pixel blocks; 0 (default): as many
+ *                        as fit on the device at once.
  * spk_set_option returns SPK_OK or SPK_EINVAL (unknown option, value < 0);
  * spk_get_option returns the value or SPK_EINVAL.
  */
-enum { SPK_OPT_TIME_CHUNKS = 1, SPK_OPT_SUR_FUSED = 2 };
+enum { SPK_OPT_TIME_CHUNKS = 1, SPK_OPT_SUR_FUSED = 2, SPK_OPT_SUR_CONV_WG = 3 };
 int spk_set_option(int option, int value);
 int spk_get_option(int option);
 

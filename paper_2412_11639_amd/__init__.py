@@ -61,6 +61,15 @@ def set_surrogate_fused(on: bool) -> None:
     _lib.check("spk_set_option", _lib.load().spk_set_option(OPT_SUR_FUSED, int(bool(on))))
 
 
+OPT_SUR_CONV_WG = 3
+
+
+def set_surrogate_conv_workgroups(n: int) -> None:
+    """Cap the workgroups of each layer-by-layer surrogate convolution (0:
+    as many as fit on the device).  Results are identical."""
+    _lib.check("spk_set_option", _lib.load().spk_set_option(OPT_SUR_CONV_WG, int(n)))
+
+
 def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()

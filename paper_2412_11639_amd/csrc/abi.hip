@@ -245,6 +245,7 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
 namespace spk {
 
 int g_sur_fused = 0;
+int g_sur_conv_wg = 0;
 
 int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
                OutTables *out)
@@ -318,6 +319,10 @@ int spk_set_option(int option, int value)
         if (value != 0 && value != 1) return SPK_EINVAL;
         spk::g_sur_fused = value;
         return SPK_OK;
+    case SPK_OPT_SUR_CONV_WG:
+        if (value < 0) return SPK_EINVAL;
+        spk::g_sur_conv_wg = value;
+        return SPK_OK;
     default:
         return SPK_EINVAL;
     }
@@ -329,6 +334,7 @@ int spk_get_option(int option)
     switch (option) {
     case SPK_OPT_TIME_CHUNKS: return requested_chunks();
     case SPK_OPT_SUR_FUSED: return spk::g_sur_fused;
+    case SPK_OPT_SUR_CONV_WG: return spk::g_sur_conv_wg;
     default: return SPK_EINVAL;
     }
 }

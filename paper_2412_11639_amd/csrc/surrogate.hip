@@ -268,21 +268,35 @@ __device__ __forceinline__ bf16x8 bits_to_bf16(uint32_t bits)
     return v;
 }
 
-// A workgroup computes a 16 x 16 block of output pixels, all 32 output
+// A workgroup computes 16 x 16 blocks of output pixels, all 32 output
 // channels; wave w takes block rows 4w .. 4w+3.  The 18 x 18 input halo is
-// staged once in LDS (NHWC bfloat16, 64 bytes per pixel, so every A
-// fragment -- 16 pixels x 8 channels -- is one aligned 16-byte read per
-// lane); a scalar input channel (estimate, or dL/dy for the last layer's
-// input gradient) is staged beside it as float.
+// staged in LDS (NHWC bfloat16, 64 bytes per pixel, so every A fragment --
+// 16 pixels x 8 channels -- is one aligned 16-byte read per lane); a scalar
+// input channel (estimate, or dL/dy for the last layer's input gradient) is
+// staged beside it as float.  A workgroup walks a contiguous range of
+// blocks and loads the next block's halo into registers while it computes
+// the current one, so the loads' latency hides behind the MFMA work.
 template <int KIND>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
 {
     using S = ConvShape<KIND>;
     constexpr bool VEC_IN = KIND != CK_DGRAD_LAST;              // 32-channel input
     constexpr bool SCALAR_IN = KIND == CK_FIRST || KIND == CK_DGRAD_LAST;
-    __shared__ __attribute__((aligned(16))) __bf16 tin[VEC_IN ? 18 * 18 * C : 8];
-    __shared__ float tsc[SCALAR_IN ? 18 * 18 : 1];
-    __shared__ __attribute__((aligned(16))) __bf16 stage[4][16 * C];
+    constexpr bool BITS_IN = KIND == CK_FIRST;                  // window words
+    constexpr int kHalo = 18 * 18;
+    // staging items per thread: 16-byte pieces of the 32-channel halo (the
+    // window word of a pixel for the first layer) and scalar pixels
+    constexpr int kVecItems = BITS_IN ? kHalo : kHalo * 4;
+    constexpr int kVecPer = VEC_IN ? (kVecItems + 255) / 256 : 1;
+    constexpr int kScPer = SCALAR_IN ? (kHalo + 255) / 256 : 1;
+    constexpr int CP = C;  // pixel stride in the halo tile
+    // pixel stride of the output staging rows: 40 bfloat16 puts the four
+    // lane groups of one 2-byte store on two bank sets instead of one
+    constexpr int SP = 40;
+    __shared__ __attribute__((aligned(16))) __bf16 tin[VEC_IN ? kHalo * CP : 8];
+    __shared__ float tsc[SCALAR_IN ? kHalo : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 stage[4][KIND == CK_LAST ? 8 : 16 * SP];
+    __shared__ float stagef[4][KIND == CK_LAST ? 64 : 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, g = lane >> 4;
     // this layer's weights, resident in registers
@@ -299,35 +313,92 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
         if constexpr (KIND == CK_FIRST || KIND == CK_MID) bias[n] = A.bias[n * 16 + i];
         if constexpr (KIND == CK_LAST) bias[n] = A.bias[0];
     }
-    for (int blk = blockIdx.x; blk < A.nblocks; blk += gridDim.x) {
+    // the halo of the next block, in flight in registers
+    uint32_t pw[BITS_IN ? kVecPer : 1];
+    bf16x8 pv[VEC_IN && !BITS_IN ? kVecPer : 1];
+    float ps[kScPer];
+    auto load = [&](int blk) {
         const int b = blk / (A.bx * A.by);
         const int y0 = ((blk / A.bx) % A.by) * 16, x0 = (blk % A.bx) * 16;
-        // stage the halo: rows y0-1 .. y0+16, columns x0-1 .. x0+16
         if constexpr (VEC_IN) {
-            for (int it = tid; it < 18 * 18 * 4; it += 256) {
-                const int q = it >> 2, part = it & 3;
-                const int y = y0 - 1 + q / 18, x = x0 - 1 + q % 18;
-                bf16x8 v;
 #pragma unroll
-                for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
-                if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc) {
-                    const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                    if constexpr (KIND == CK_FIRST) v = bits_to_bf16((A.win[pix] >> (8 * part)) & 0xFFu);
-                    else v = *(const bf16x8 *)(A.act + pix * C + part * 8);
+            for (int u = 0; u < kVecPer; u++) {
+                const int it = tid + 256 * u;
+                const int q = BITS_IN ? it : it >> 2, part = it & 3;
+                const int y = y0 - 1 + q / 18, x = x0 - 1 + q % 18;
+                const bool in =
+                    it < kVecItems && y >= 0 && y < A.Hc && x >= 0 && x < A.Wc;
+                const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+                if constexpr (BITS_IN) {
+                    pw[u] = in ? A.win[pix] : 0u;
+                } else {
+                    bf16x8 v;
+#pragma unroll
+                    for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
+                    if (in) v = *(const bf16x8 *)(A.act + pix * C + part * 8);
+                    pv[u] = v;
                 }
-                *(bf16x8 *)(&tin[q * C + part * 8]) = v;
             }
         }
         if constexpr (SCALAR_IN) {
-            for (int q = tid; q < 18 * 18; q += 256) {
+#pragma unroll
+            for (int u = 0; u < kScPer; u++) {
+                const int q = tid + 256 * u;
                 const int y = y0 - 1 + q / 18, x = x0 - 1 + q % 18;
-                float v = 0.0f;
-                if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc)
-                    v = A.scalar[((int64_t)b * A.Hc + y) * A.Wc + x];
-                tsc[q] = v;
+                const bool in = q < kHalo && y >= 0 && y < A.Hc && x >= 0 && x < A.Wc;
+                ps[u] = in ? A.scalar[((int64_t)b * A.Hc + y) * A.Wc + x] : 0.0f;
             }
         }
-        __syncthreads();
+    };
+    auto store = [&]() {
+        if constexpr (VEC_IN) {
+#pragma unroll
+            for (int u = 0; u < kVecPer; u++) {
+                const int it = tid + 256 * u;
+                if (it < kVecItems) {
+                    if constexpr (BITS_IN) {
+#pragma unroll
+                        for (int part = 0; part < 4; part++)
+                            *(bf16x8 *)(&tin[it * CP + part * 8]) =
+                                bits_to_bf16((pw[u] >> (8 * part)) & 0xFFu);
+                    } else {
+                        *(bf16x8 *)(&tin[(it >> 2) * CP + (it & 3) * 8]) = pv[u];
+                    }
+                }
+            }
+        }
+        if constexpr (SCALAR_IN) {
+#pragma unroll
+            for (int u = 0; u < kScPer; u++) {
+                const int q = tid + 256 * u;
+                if (q < kHalo) tsc[q] = ps[u];
+            }
+        }
+    };
+    const int per = (A.nblocks + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int blk0 = (int)blockIdx.x * per, blk1 = min(A.nblocks, blk0 + per);
+    if (blk0 >= blk1) return;
+    load(blk0);
+    store();
+    __syncthreads();
+    // output staging rows: pixel lane/4, channels 8 (lane%4) .. +7
+    const int px = lane >> 2, part = lane & 3;
+    for (int blk = blk0; blk < blk1; blk++) {
+        const int b = blk / (A.bx * A.by);
+        const int y0 = ((blk / A.bx) % A.by) * 16, x0 = (blk % A.bx) * 16;
+        // the halo of this block (rows y0-1 .. y0+16, columns x0-1 .. x0+16)
+        // is in LDS; fetch the next one while computing
+        const bool more = blk + 1 < blk1;
+        if (more) load(blk + 1);
+        // the last layer's residual: the estimate at this lane's pixel of
+        // the wave's rows (row 4w + lane/16, column lane%16)
+        float est_l = 0.0f;
+        const int ly = y0 + 4 * wave + (lane >> 4), lx = x0 + (lane & 15);
+        const bool lin = ly < A.Hc && lx < A.Wc;
+        const int64_t lpix = ((int64_t)b * A.Hc + ly) * A.Wc + lx;
+        if constexpr (KIND == CK_LAST) {
+            if (lin) est_l = A.scalar[lpix];
+        }
         f32x4 acc[4][S::nb];
 #pragma unroll
         for (int r = 0; r < 4; r++)
@@ -348,61 +419,88 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
                         a[e] = k < 9 ? (__bf16)tsc[(oy + k / 3) * 18 + i + k % 3] : (__bf16)0.0f;
                     }
                 } else {
-                    a = *(const bf16x8 *)(&tin[((oy + s / 3) * 18 + i + s % 3) * C + 8 * g]);
+                    a = *(const bf16x8 *)(&tin[((oy + s / 3) * 18 + i + s % 3) * CP + 8 * g]);
                 }
 #pragma unroll
                 for (int n = 0; n < S::nb; n++)
                     acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[s][n], acc[r][n], 0, 0, 0);
             }
         }
-        // lane holds D[pixel 4g + e][channel 16n + i] of each block row
+        // Epilogue, first half: the results into registers in store layout
+        // (lane holds D[pixel 4g + e][channel 16n + i] of each block row).
+        // Global stores wait until the next halo is in LDS: its loads are
+        // then the only memory operations outstanding.
+        bf16x8 ov[KIND == CK_LAST ? 1 : 4];
+        bf16x8 om[KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST ? 4 : 1];
+        float of = 0.0f;
+        if constexpr (KIND == CK_LAST) {
+            if (i == 0) {
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int y = y0 + 4 * wave + r;
-            if constexpr (KIND == CK_LAST) {
-                // residual on the plain short-window estimate
-                if (i == 0 && y < A.Hc) {
+                for (int r = 0; r < 4; r++)
 #pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const int x = x0 + 4 * g + e;
-                        if (x < A.Wc) {
-                            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                            A.out_f32[pix] = A.scalar[pix] + (acc[r][0][e] + bias[0]);
-                        }
-                    }
+                    for (int e = 0; e < 4; e++)
+                        stagef[wave][r * 16 + 4 * g + e] = acc[r][0][e] + bias[0];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            of = stagef[wave][lane];
+        } else {
+            if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
+                // the ReLU masks of this block's output rows
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int y = y0 + 4 * wave + r, x = x0 + px;
+#pragma unroll
+                    for (int e = 0; e < 8; e++) om[r][e] = (__bf16)0.0f;
+                    if (x < A.Wc && y < A.Hc)
+                        om[r] = *(const bf16x8 *)(A.mask + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
+                                                  part * 8);
                 }
-            } else {
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
 #pragma unroll
                 for (int n = 0; n < S::nb; n++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
                         float v = acc[r][n][e] + bias[n];
                         if constexpr (KIND == CK_FIRST || KIND == CK_MID) v = fmaxf(v, 0.0f);
-                        stage[wave][(4 * g + e) * C + 16 * n + i] = to_bf16(v);
+                        stage[wave][(4 * g + e) * SP + 16 * n + i] = to_bf16(v);
                     }
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // each lane writes 8 channels of one pixel: pixel lane/4, part lane%4
-                const int px = lane >> 2, part = lane & 3;
-                const int x = x0 + px;
-                bf16x8 v = *(const bf16x8 *)(&stage[wave][px * C + part * 8]);
-                if (x < A.Wc && y < A.Hc) {
-                    const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                    if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
-                        const bf16x8 m = *(const bf16x8 *)(A.mask + pix * C + part * 8);
-#pragma unroll
-                        for (int e = 0; e < 8; e++)
-                            if (!((float)m[e] > 0.0f)) v[e] = (__bf16)0.0f;
-                    }
-                    *(bf16x8 *)(A.out + pix * C + part * 8) = v;
-                }
+                ov[r] = *(const bf16x8 *)(&stage[wave][px * SP + part * 8]);
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
-        __syncthreads();
+        // (more is the same for the whole workgroup, so the barriers are too)
+        if (more) {
+            __syncthreads();  // every wave is done with this halo
+            store();
+        }
+        // second half: global stores
+        if constexpr (KIND == CK_LAST) {
+            if (lin) A.out_f32[lpix] = est_l + of;
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int y = y0 + 4 * wave + r, x = x0 + px;
+                if (x < A.Wc && y < A.Hc) {
+                    bf16x8 v = ov[r];
+                    if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
+#pragma unroll
+                        for (int e = 0; e < 8; e++)
+                            if (!((float)om[r][e] > 0.0f)) v[e] = (__bf16)0.0f;
+                    }
+                    *(bf16x8 *)(A.out + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8) = v;
+                }
+            }
+        }
+        if (more) __syncthreads();  // the next halo is in LDS
     }
 }
 
@@ -918,11 +1016,34 @@ ConvArgs conv_args(int B, int Hc, int Wc)
 }
 
 constexpr int kConvMaxBlocks = 2048;
+constexpr int kMaxDevices = 64;
+
+// Workgroups of conv_kernel<KIND> resident on the whole current device at
+// once (they walk the blocks in contiguous ranges, prefetching).
+template <int KIND>
+int conv_resident()
+{
+    static int cache[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return kConvMaxBlocks;
+    if (cache[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv_kernel<KIND>, 256, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            per_cu <= 0 || cus <= 0)
+            return kConvMaxBlocks;
+        cache[dev] = per_cu * cus;
+    }
+    return cache[dev];
+}
 
 template <int KIND>
 void launch_conv(const ConvArgs &a, hipStream_t st)
 {
-    const int blocks = a.nblocks < kConvMaxBlocks ? a.nblocks : kConvMaxBlocks;
+    int cap = conv_resident<KIND>();
+    if (spk::g_sur_conv_wg > 0 && spk::g_sur_conv_wg < cap) cap = spk::g_sur_conv_wg;
+    const int blocks = a.nblocks < cap ? a.nblocks : cap;
     hipLaunchKernelGGL(conv_kernel<KIND>, dim3(blocks), dim3(256), 0, st, a);
 }
 

@@ -179,3 +179,8 @@ def test_options(lib):
     assert lib.spk_set_option(99, 1) == -1
     assert lib.spk_set_option(1, -1) == -1
     assert lib.spk_get_option(99) == -1
+    # surrogate options: two-layer kernels on/off, convolution workgroup cap
+    assert lib.spk_set_option(2, 2) == -1
+    assert lib.spk_set_option(3, -1) == -1
+    assert lib.spk_set_option(3, 5) == 0 and lib.spk_get_option(3) == 5
+    assert lib.spk_set_option(3, 0) == 0 and lib.spk_get_option(3) == 0

@@ -197,3 +197,32 @@ def test_fused_forward_equals_layer_by_layer(sur, shape):
     assert torch.equal(res[False][1], res[True][1])
     assert torch.equal(res[True][2], res[True][0])
     assert torch.equal(res[False][2], res[False][0])
+
+
+@pytest.mark.parametrize("shape", [(1, 70, 45), (2, 40, 100)])
+def test_conv_block_walk_is_bit_identical(sur, shape):
+    """Each convolution workgroup walks a contiguous range of 16x16 blocks,
+    loading the next block's halo while it computes the current one.
+    Capping the workgroups (one walks every block; several walk ranges
+    that cross image boundaries; some get no block) leaves the forward
+    output, inference and the gradient bit-identical to one block per
+    workgroup."""
+    import paper_2412_11639_amd as spk
+    rng = np.random.default_rng(10)
+    B, Hc, Wc = shape
+    model = sur.Surrogate(sur.init_params(7) + rng.normal(0, 0.05, sur.NPARAMS))
+    win, est = _to_dev(*_rand_batch(rng, B, Hc, Wc))
+    target = torch.rand((B, Hc, Wc), device="cuda")
+    res = {}
+    for cap in (0, 1, 3, 7):
+        spk.set_surrogate_conv_workgroups(cap)
+        try:
+            y = model.forward(win, est)
+            model.backward(win, est, y, target)
+            res[cap] = (y.clone(), model.grad.clone(), model.infer(win, est).clone())
+        finally:
+            spk.set_surrogate_conv_workgroups(0)
+    torch.cuda.synchronize()
+    for cap in (1, 3, 7):
+        for k in range(3):
+            assert torch.equal(res[cap][k], res[0][k]), (cap, k)
