@@ -290,6 +290,30 @@ int spk_sur_backward(const float *params, const uint32_t *win, const float *est,
 int spk_sur_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
                  float beta1, float beta2, float eps, void *hip_stream);
 
+/* Training loop replayed from a HIP graph, for callers whose step is bound
+ * by host launch overhead.  Each step is spk_sur_input (with targets),
+ * spk_sur_forward, spk_sur_backward and spk_sur_adam, with results
+ * identical bit for bit to those calls.  samples: host array of steps * B
+ * crop records, step k's at [k * B, k * B + B); lr: host, steps learning
+ * rates (> 0); both are copied to the device.  Adam's step number of the
+ * plan's first step is step0 (>= 1); beta1, beta2, eps as spk_sur_adam.
+ * params, m, v: the caller's device buffers, updated in place by every
+ * step.  loss_partial (device, may be NULL): row k (ceil(B*Hc*Wc/256)
+ * partial sums of squared errors) is written by step k.  The sample
+ * streams and targets must stay valid while steps run.  The plan belongs
+ * to the current device and owns its buffers and graph.
+ * Errors: SPK_EINVAL (arguments, any record), SPK_ENOMEM, SPK_EHIP. */
+typedef struct spk_sur_train_s *spk_sur_train_t;
+int spk_sur_train_create(spk_sur_train_t *plan, float *params, float *m, float *v,
+                         const spk_sur_sample *samples, const float *lr, int32_t steps,
+                         int32_t B, int32_t Hc, int32_t Wc, float theta, float beta1, float beta2,
+                         float eps, int32_t step0, float *loss_partial);
+/* Enqueue the plan's next n steps on hip_stream (SPK_EINVAL if fewer than
+ * n remain, or from another device). */
+int spk_sur_train_run(spk_sur_train_t plan, int32_t n, void *hip_stream);
+/* Waits for the device, then frees the plan (NULL: no-op). */
+int spk_sur_train_destroy(spk_sur_train_t plan);
+
 /* Fallback: out = stable ? y : est, over n values. */
 int spk_sur_mux(const float *y, const float *est, const uint8_t *stable, int64_t n, float *out,
                 void *hip_stream);

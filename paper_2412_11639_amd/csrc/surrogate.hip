@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <vector>
 
 #include "spk.h"
 #include "spk_internal.h"
@@ -175,16 +176,16 @@ __device__ __forceinline__ void window_estimate(uint32_t win, double theta, floa
     stable = nseg == 1;
 }
 
-__global__ __launch_bounds__(64) void input_kernel(SampleTab tab, int Hc, int Wc, int xtiles,
-                                                   double theta, uint32_t *win, float *est,
-                                                   uint8_t *stable, float *target)
+// One 64-pixel row tile of crop b (sample S): window, estimate, flag and
+// optionally the target.
+__device__ __forceinline__ void input_tile(const spk_sur_sample &S, int b, int Hc, int Wc,
+                                           int xtiles, double theta, uint32_t *win, float *est,
+                                           uint8_t *stable, float *target)
 {
     const int lane = threadIdx.x;
     const int tile = blockIdx.x;
-    const int b = tile / (Hc * xtiles);
     const int y = (tile / xtiles) % Hc;
     const int x0 = (tile % xtiles) * 64;
-    const spk_sur_sample &S = tab.s[b];
     const int64_t fb = (int64_t)(((int64_t)S.H * S.W + 127) / 128) * 16;
     // frame row of 64 consecutive stream pixels starting at q0 (not aligned)
     const int64_t q0 = (int64_t)(S.oy + y) * S.W + S.ox + x0;
@@ -209,6 +210,27 @@ __global__ __launch_bounds__(64) void input_kernel(SampleTab tab, int Hc, int Wc
     est[o] = e;
     stable[o] = st;
     if (target && S.target) target[o] = S.target[(int64_t)(S.oy + y) * S.W + S.ox + x];
+}
+
+__global__ __launch_bounds__(64) void input_kernel(SampleTab tab, int Hc, int Wc, int xtiles,
+                                                   double theta, uint32_t *win, float *est,
+                                                   uint8_t *stable, float *target)
+{
+    const int b = blockIdx.x / (Hc * xtiles);
+    input_tile(tab.s[b], b, Hc, Wc, xtiles, theta, win, est, stable, target);
+}
+
+// As input_kernel with the crops of training step *kstep taken from a
+// device table of B records per step.
+__global__ __launch_bounds__(64) void input_step_kernel(const spk_sur_sample *samples,
+                                                        const int32_t *kstep, int B, int Hc,
+                                                        int Wc, int xtiles, double theta,
+                                                        uint32_t *win, float *est,
+                                                        uint8_t *stable, float *target)
+{
+    const int b = blockIdx.x / (Hc * xtiles);
+    const spk_sur_sample S = samples[(int64_t)*kstep * B + b];
+    input_tile(S, b, Hc, Wc, xtiles, theta, win, est, stable, target);
 }
 
 // Streaming window update for a full frame: win = (win >> 1) | bit(t) << 31,
@@ -714,8 +736,11 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs A)
 // loss: dL/dy = 2 (y - target) / N, rounded to bfloat16 like every gradient
 // the GEMMs consume; per-block partial sums of the squared error
 
+// partial: one sum per block; with kstep, step *kstep's row of a table
+// [step][gridDim.x].
 __global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *tgt, int64_t n,
-                                                   float *dy, float *partial)
+                                                   float *dy, float *partial,
+                                                   const int32_t *kstep)
 {
     __shared__ float red[256];
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -731,7 +756,8 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0)
+        partial[(kstep ? (int64_t)*kstep * gridDim.x : 0) + blockIdx.x] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -936,17 +962,41 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float *partial, int n
 
 // ---------------------------------------------------------------------------
 
-__global__ void adam_kernel(float *p, float *m, float *v, const float *g, int n, float lr,
-                            float b1, float b2, float eps, float c1, float c2)
+// Adam update of parameter j (c1, c2: the bias corrections 1 - beta^t).
+__device__ __forceinline__ void adam_update(int j, float *p, float *m, float *v, const float *g,
+                                            float lr, float b1, float b2, float eps, float c1,
+                                            float c2)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
     const float gj = g[j];
     const float mj = b1 * m[j] + (1.0f - b1) * gj;
     const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
     m[j] = mj;
     v[j] = vj;
     p[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
+
+__global__ void adam_kernel(float *p, float *m, float *v, const float *g, int n, float lr,
+                            float b1, float b2, float eps, float c1, float c2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) adam_update(j, p, m, v, g, lr, b1, b2, eps, c1, c2);
+}
+
+// Adam for training step k = *kstep: learning rate and bias corrections
+// from per-step tables (the host computes them exactly as spk_sur_adam).
+__global__ void adam_step_kernel(float *p, float *m, float *v, const float *g, int n,
+                                 const float *lr, const float *c1, const float *c2,
+                                 const int32_t *kstep, float b1, float b2, float eps)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int k = *kstep;
+    adam_update(j, p, m, v, g, lr[k], b1, b2, eps, c1[k], c2[k]);
+}
+
+__global__ void advance_kernel(int32_t *kstep)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *kstep += 1;
 }
 
 __global__ void mux_kernel(const float *y, const float *est, const uint8_t *stable, int64_t n,
@@ -1047,6 +1097,17 @@ void launch_conv(const ConvArgs &a, hipStream_t st)
     hipLaunchKernelGGL(conv_kernel<KIND>, dim3(blocks), dim3(256), 0, st, a);
 }
 
+// Fill the per-device launch-shape caches (no device work), so that a
+// later stream capture makes no occupancy queries.
+void warm_launch_caches()
+{
+    conv_resident<CK_FIRST>();
+    conv_resident<CK_MID>();
+    conv_resident<CK_LAST>();
+    conv_resident<CK_DGRAD_MID>();
+    conv_resident<CK_DGRAD_LAST>();
+}
+
 template <int K>
 void launch_wgrad(WgArgs a, float *dst, hipStream_t st)
 {
@@ -1126,97 +1187,28 @@ void forward_all(const float *params, const uint32_t *win, const float *est, int
     launch_conv<CK_LAST>(a, st);
 }
 
-}  // namespace
-}  // namespace sur
-}  // namespace spk
-
-using namespace spk::sur;
-
-extern "C" {
-
-size_t spk_sur_workspace_bytes(int32_t B, int32_t Hc, int32_t Wc)
+// Forward for training (the activations the backward pass reads are kept).
+void forward_train(const float *params, const uint32_t *win, const float *est, int B, int Hc,
+                   int Wc, float *y, const Workspace &w, hipStream_t st)
 {
-    if (B <= 0 || Hc <= 0 || Wc <= 0) return 0;
-    return (size_t)workspace_bytes(B, Hc, Wc);
-}
-
-static int check_batch(int32_t B, int32_t Hc, int32_t Wc)
-{
-    if (B <= 0 || Hc <= 0 || Wc <= 0) return SPK_EINVAL;
-    if ((int64_t)B * Hc * Wc > ((int64_t)1 << 31) / C) return SPK_EINVAL;
-    return SPK_OK;
-}
-
-int spk_sur_input(const spk_sur_sample *samples, int32_t B, int32_t Hc, int32_t Wc, float theta,
-                  uint32_t *win, float *est, uint8_t *stable, float *target, void *hip_stream)
-{
-    if (!samples || !win || !est || !stable || B > SPK_SUR_MAX_SAMPLES) return SPK_EINVAL;
-    if (check_batch(B, Hc, Wc) || !std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
-    SampleTab tab{};
-    for (int b = 0; b < B; b++) {
-        const spk_sur_sample &S = samples[b];
-        if (!S.stream || S.H <= 0 || S.W <= 0 || S.T < 32 || S.t < 31 || S.t >= S.T ||
-            S.oy < 0 || S.ox < 0 || S.oy + Hc > S.H || S.ox + Wc > S.W)
-            return SPK_EINVAL;
-        if ((int64_t)S.H * S.W > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
-        if (target && !S.target) return SPK_EINVAL;
-        tab.s[b] = S;
-    }
-    const int xtiles = (Wc + 63) / 64;
-    hipLaunchKernelGGL(input_kernel, dim3(B * Hc * xtiles), dim3(64), 0, (hipStream_t)hip_stream,
-                       tab, Hc, Wc, xtiles, (double)theta, win, est, stable, target);
-    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
-}
-
-int spk_sur_stream_step(const uint8_t *frame, int32_t H, int32_t W, float theta, uint32_t *win,
-                        float *est, uint8_t *stable, void *hip_stream)
-{
-    if (!frame || !win || !est || !stable || H <= 0 || W <= 0) return SPK_EINVAL;
-    if (!std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
-    const int64_t HW = (int64_t)H * W;
-    if (HW > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
-    hipLaunchKernelGGL(stream_kernel, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)hip_stream, frame, HW, (double)theta, win, est, stable);
-    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
-}
-
-int spk_sur_forward(const float *params, const uint32_t *win, const float *est, int32_t B,
-                    int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream)
-{
-    if (!params || !win || !est || !y || !workspace || check_batch(B, Hc, Wc)) return SPK_EINVAL;
-    const Workspace w = carve(workspace, B, Hc, Wc);
     if (spk::g_sur_fused)
-        forward_fused(params, win, est, B, Hc, Wc, y, w, true, (hipStream_t)hip_stream);
+        forward_fused(params, win, est, B, Hc, Wc, y, w, true, st);
     else
-        forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream);
-    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+        forward_all(params, win, est, B, Hc, Wc, y, w, st);
 }
 
-int spk_sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
-                  int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream)
+// MSE gradient: loss (dL/dy and the loss partial sums, into a per-step row
+// of loss_partial when kstep is given), then per layer from the top the
+// weight gradient and the input gradient through the ReLU mask.
+void backward_all(const float *params, const uint32_t *win, const float *est, int B, int Hc,
+                  int Wc, const float *y, const float *target, float *grad, float *loss_partial,
+                  const int32_t *kstep, const Workspace &w, hipStream_t st)
 {
-    if (!params || !win || !est || !y || !workspace || check_batch(B, Hc, Wc)) return SPK_EINVAL;
-    const Workspace w = carve(workspace, B, Hc, Wc);
-    if (spk::g_sur_fused)
-        forward_fused(params, win, est, B, Hc, Wc, y, w, false, (hipStream_t)hip_stream);
-    else
-        forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream);
-    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
-}
-
-int spk_sur_backward(const float *params, const uint32_t *win, const float *est, int32_t B,
-                     int32_t Hc, int32_t Wc, const float *y, const float *target, float *grad,
-                     float *loss_partial_out, void *workspace, void *hip_stream)
-{
-    if (!params || !win || !est || !y || !target || !grad || !workspace ||
-        check_batch(B, Hc, Wc))
-        return SPK_EINVAL;
-    hipStream_t st = (hipStream_t)hip_stream;
-    const Workspace w = carve(workspace, B, Hc, Wc);
     const int64_t P = (int64_t)B * Hc * Wc;
     const int lblocks = (int)((P + 255) / 256);
     hipLaunchKernelGGL(loss_kernel, dim3(lblocks), dim3(256), 0, st, y, target, P, w.dy,
-                       loss_partial_out ? loss_partial_out : w.loss_partial);
+                       loss_partial ? loss_partial : w.loss_partial,
+                       loss_partial ? kstep : nullptr);
     ConvArgs a = conv_args(B, Hc, Wc);
     // layer 4: weights from dL/dy and a3; gradient into a3's pre-activation
     WgArgs g{};
@@ -1257,16 +1249,129 @@ int spk_sur_backward(const float *params, const uint32_t *win, const float *est,
     g.win = win;
     g.est = est;
     launch_wgrad<WG_FIRST>(g, grad + OFF_W1, st);
+}
+
+}  // namespace
+}  // namespace sur
+}  // namespace spk
+
+using namespace spk::sur;
+
+// A training loop captured once in a HIP graph.  Device buffer (one
+// allocation): workspace, the batch (win, est, stable, target, y), the
+// gradient, the per-step tables (crops, learning rate, bias corrections)
+// and the step counter.
+struct spk_sur_train_s {
+    int dev = -1;
+    int32_t steps = 0, done = 0, B = 0, Hc = 0, Wc = 0;
+    void *buf = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+size_t spk_sur_workspace_bytes(int32_t B, int32_t Hc, int32_t Wc)
+{
+    if (B <= 0 || Hc <= 0 || Wc <= 0) return 0;
+    return (size_t)workspace_bytes(B, Hc, Wc);
+}
+
+static int check_batch(int32_t B, int32_t Hc, int32_t Wc)
+{
+    if (B <= 0 || Hc <= 0 || Wc <= 0) return SPK_EINVAL;
+    if ((int64_t)B * Hc * Wc > ((int64_t)1 << 31) / C) return SPK_EINVAL;
+    return SPK_OK;
+}
+
+// A crop record is usable for Hc x Wc crops (and has a target if one is
+// wanted).
+static bool sample_ok(const spk_sur_sample &S, int32_t Hc, int32_t Wc, bool need_target)
+{
+    if (!S.stream || S.H <= 0 || S.W <= 0 || S.T < 32 || S.t < 31 || S.t >= S.T || S.oy < 0 ||
+        S.ox < 0 || S.oy + Hc > S.H || S.ox + Wc > S.W)
+        return false;
+    if ((int64_t)S.H * S.W > (int64_t)INT32_MAX - 128) return false;
+    return !need_target || S.target;
+}
+
+int spk_sur_input(const spk_sur_sample *samples, int32_t B, int32_t Hc, int32_t Wc, float theta,
+                  uint32_t *win, float *est, uint8_t *stable, float *target, void *hip_stream)
+{
+    if (!samples || !win || !est || !stable || B > SPK_SUR_MAX_SAMPLES) return SPK_EINVAL;
+    if (check_batch(B, Hc, Wc) || !std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
+    SampleTab tab{};
+    for (int b = 0; b < B; b++) {
+        if (!sample_ok(samples[b], Hc, Wc, target != nullptr)) return SPK_EINVAL;
+        tab.s[b] = samples[b];
+    }
+    const int xtiles = (Wc + 63) / 64;
+    hipLaunchKernelGGL(input_kernel, dim3(B * Hc * xtiles), dim3(64), 0, (hipStream_t)hip_stream,
+                       tab, Hc, Wc, xtiles, (double)theta, win, est, stable, target);
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
 }
+
+int spk_sur_stream_step(const uint8_t *frame, int32_t H, int32_t W, float theta, uint32_t *win,
+                        float *est, uint8_t *stable, void *hip_stream)
+{
+    if (!frame || !win || !est || !stable || H <= 0 || W <= 0) return SPK_EINVAL;
+    if (!std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
+    const int64_t HW = (int64_t)H * W;
+    if (HW > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
+    hipLaunchKernelGGL(stream_kernel, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)hip_stream, frame, HW, (double)theta, win, est, stable);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_forward(const float *params, const uint32_t *win, const float *est, int32_t B,
+                    int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream)
+{
+    if (!params || !win || !est || !y || !workspace || check_batch(B, Hc, Wc)) return SPK_EINVAL;
+    const Workspace w = carve(workspace, B, Hc, Wc);
+    forward_train(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
+                  int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream)
+{
+    if (!params || !win || !est || !y || !workspace || check_batch(B, Hc, Wc)) return SPK_EINVAL;
+    const Workspace w = carve(workspace, B, Hc, Wc);
+    if (spk::g_sur_fused)
+        forward_fused(params, win, est, B, Hc, Wc, y, w, false, (hipStream_t)hip_stream);
+    else
+        forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_backward(const float *params, const uint32_t *win, const float *est, int32_t B,
+                     int32_t Hc, int32_t Wc, const float *y, const float *target, float *grad,
+                     float *loss_partial_out, void *workspace, void *hip_stream)
+{
+    if (!params || !win || !est || !y || !target || !grad || !workspace ||
+        check_batch(B, Hc, Wc))
+        return SPK_EINVAL;
+    const Workspace w = carve(workspace, B, Hc, Wc);
+    backward_all(params, win, est, B, Hc, Wc, y, target, grad, loss_partial_out, nullptr, w,
+                 (hipStream_t)hip_stream);
+    return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+static bool adam_ok(float beta1, float beta2, float eps)
+{
+    return beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f;
+}
+
+// Adam's bias corrections 1 - beta^t (the same expression for the eager
+// step and the per-step tables of a training plan).
+static float bias_correction(float beta, int32_t t) { return 1.0f - std::pow(beta, (float)t); }
 
 int spk_sur_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
                  float beta1, float beta2, float eps, void *hip_stream)
 {
-    if (!params || !m || !v || !grad || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f) ||
-        !(beta1 < 1.0f) || !(beta2 >= 0.0f) || !(beta2 < 1.0f) || !(eps > 0.0f))
+    if (!params || !m || !v || !grad || step < 1 || !(lr > 0.0f) || !adam_ok(beta1, beta2, eps))
         return SPK_EINVAL;
-    const float c1 = 1.0f - std::pow(beta1, (float)step), c2 = 1.0f - std::pow(beta2, (float)step);
+    const float c1 = bias_correction(beta1, step), c2 = bias_correction(beta2, step);
     hipLaunchKernelGGL(adam_kernel, dim3((NPARAMS + 255) / 256), dim3(256), 0,
                        (hipStream_t)hip_stream, params, m, v, grad, NPARAMS, lr, beta1, beta2, eps,
                        c1, c2);
@@ -1281,6 +1386,128 @@ int spk_sur_mux(const float *y, const float *est, const uint8_t *stable, int64_t
     hipLaunchKernelGGL(mux_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        (hipStream_t)hip_stream, y, est, stable, n, out);
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+static void train_free(spk_sur_train_s *pl)
+{
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->buf) (void)hipFree(pl->buf);
+    delete pl;
+}
+
+int spk_sur_train_create(spk_sur_train_t *plan, float *params, float *m, float *v,
+                         const spk_sur_sample *samples, const float *lr, int32_t steps,
+                         int32_t B, int32_t Hc, int32_t Wc, float theta, float beta1, float beta2,
+                         float eps, int32_t step0, float *loss_partial)
+{
+    if (!plan) return SPK_EINVAL;
+    *plan = nullptr;
+    if (!params || !m || !v || !samples || !lr || steps <= 0 || step0 < 1 ||
+        B > SPK_SUR_MAX_SAMPLES || check_batch(B, Hc, Wc) || !std::isfinite(theta) ||
+        !(theta > 0.0f) || !adam_ok(beta1, beta2, eps))
+        return SPK_EINVAL;
+    if ((int64_t)step0 + steps > INT32_MAX || (int64_t)steps * B > INT32_MAX) return SPK_EINVAL;
+    for (int64_t k = 0; k < (int64_t)steps * B; k++)
+        if (!sample_ok(samples[k], Hc, Wc, true)) return SPK_EINVAL;
+    for (int32_t k = 0; k < steps; k++)
+        if (!(lr[k] > 0.0f) || !std::isfinite(lr[k])) return SPK_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SPK_EHIP;
+    // host tables: learning rate and bias corrections per step
+    std::vector<float> tab((size_t)steps * 3);
+    for (int32_t k = 0; k < steps; k++) {
+        tab[k] = lr[k];
+        tab[(size_t)steps + k] = bias_correction(beta1, step0 + k);
+        tab[(size_t)steps * 2 + k] = bias_correction(beta2, step0 + k);
+    }
+    const int64_t P = (int64_t)B * Hc * Wc;
+    const int64_t ws = workspace_bytes(B, Hc, Wc);
+    const int64_t o_win = align256(ws), o_est = o_win + align256(P * 4),
+                  o_stable = o_est + align256(P * 4), o_target = o_stable + align256(P),
+                  o_y = o_target + align256(P * 4), o_grad = o_y + align256(P * 4),
+                  o_samples = o_grad + align256((int64_t)NPARAMS * 4),
+                  o_tab = o_samples + align256((int64_t)steps * B * sizeof(spk_sur_sample)),
+                  o_k = o_tab + align256((int64_t)steps * 3 * 4), total = o_k + 256;
+    auto *pl = new spk_sur_train_s;
+    pl->dev = dev;
+    pl->steps = steps;
+    pl->B = B;
+    pl->Hc = Hc;
+    pl->Wc = Wc;
+    if (hipMalloc(&pl->buf, (size_t)total) != hipSuccess) {
+        (void)hipGetLastError();
+        train_free(pl);
+        return SPK_ENOMEM;
+    }
+    char *c = (char *)pl->buf;
+    uint32_t *win = (uint32_t *)(c + o_win);
+    float *est = (float *)(c + o_est), *target = (float *)(c + o_target), *y = (float *)(c + o_y);
+    float *grad = (float *)(c + o_grad), *dtab = (float *)(c + o_tab);
+    uint8_t *stable = (uint8_t *)(c + o_stable);
+    spk_sur_sample *dsamples = (spk_sur_sample *)(c + o_samples);
+    int32_t *kstep = (int32_t *)(c + o_k);
+    const int32_t zero = 0;
+    if (hipMemcpy(dsamples, samples, (size_t)steps * B * sizeof(spk_sur_sample),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(kstep, &zero, 4, hipMemcpyHostToDevice) != hipSuccess) {
+        train_free(pl);
+        return SPK_EHIP;
+    }
+    // capture one step on a private stream
+    warm_launch_caches();
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        train_free(pl);
+        return SPK_EHIP;
+    }
+    const Workspace w = carve(pl->buf, B, Hc, Wc);
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const int xtiles = (Wc + 63) / 64;
+        hipLaunchKernelGGL(input_step_kernel, dim3(B * Hc * xtiles), dim3(64), 0, cs, dsamples,
+                           kstep, B, Hc, Wc, xtiles, (double)theta, win, est, stable, target);
+        forward_train(params, win, est, B, Hc, Wc, y, w, cs);
+        backward_all(params, win, est, B, Hc, Wc, y, target, grad, loss_partial, kstep, w, cs);
+        hipLaunchKernelGGL(adam_step_kernel, dim3((NPARAMS + 255) / 256), dim3(256), 0, cs,
+                           params, m, v, grad, NPARAMS, dtab, dtab + steps, dtab + 2 * steps,
+                           kstep, beta1, beta2, eps);
+        hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, cs, kstep);
+        ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess && pl->graph;
+    }
+    ok = ok && hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipStreamDestroy(cs);
+    if (!ok) {
+        (void)hipGetLastError();
+        train_free(pl);
+        return SPK_EHIP;
+    }
+    *plan = pl;
+    return SPK_OK;
+}
+
+int spk_sur_train_run(spk_sur_train_t plan, int32_t n, void *hip_stream)
+{
+    if (!plan || n < 0 || n > plan->steps - plan->done) return SPK_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->dev) return SPK_EINVAL;
+    for (int32_t i = 0; i < n; i++)
+        if (hipGraphLaunch(plan->exec, (hipStream_t)hip_stream) != hipSuccess) return SPK_EHIP;
+    plan->done += n;
+    return SPK_OK;
+}
+
+int spk_sur_train_destroy(spk_sur_train_t plan)
+{
+    if (!plan) return SPK_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(plan->dev);
+    (void)hipDeviceSynchronize();
+    train_free(plan);
+    (void)hipSetDevice(cur);
+    return SPK_OK;
 }
 
 }  // extern "C"

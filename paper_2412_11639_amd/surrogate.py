@@ -44,6 +44,11 @@ _lib.EXTRA_DECLS.update({
     "spk_sur_adam": [_P, _P, _P, _P, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                      ctypes.c_float, _P],
     "spk_sur_mux": [_P, _P, _P, ctypes.c_int64, _P, _P],
+    "spk_sur_train_create": [ctypes.POINTER(_P), _P, _P, _P, ctypes.POINTER(SurSample), _P, _i32,
+                             _i32, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_float, _i32, _P],
+    "spk_sur_train_run": [_P, _i32, _P],
+    "spk_sur_train_destroy": [_P],
 })
 
 
@@ -252,3 +257,87 @@ def train(model: Surrogate, scenes: SceneSet, steps: int, B: int = 16, Hc: int =
         losses.append(float(torch.stack([p.sum() for p in parts]).cpu().sum())
                       / (n * len(parts)))
     return losses
+
+
+class TrainPlan:
+    """``spk_sur_train_*``: the training loop of ``model`` over fixed crops
+    (per step a list of B sample dicts, as for ``Surrogate.input``) and
+    learning rates, replayed step by step from one captured HIP graph.
+    ``run(n)`` enqueues n steps; ``losses()`` gives the mean squared error
+    of every step run so far."""
+
+    def __init__(self, model: "Surrogate", steps_samples, lrs, Hc, Wc, theta=1.0,
+                 beta1=0.9, beta2=0.999, eps=1e-8):
+        steps = len(steps_samples)
+        B = len(steps_samples[0])
+        assert steps > 0 and 0 < B <= MAX_SAMPLES and len(lrs) == steps
+        self.model, self.steps, self.B, self.Hc, self.Wc = model, steps, B, Hc, Wc
+        arr = (SurSample * (steps * B))()
+        for k, samples in enumerate(steps_samples):
+            assert len(samples) == B
+            for i, smp in enumerate(samples):
+                _check_stream_tensor(smp["stream"], smp["H"], smp["W"], smp["T"])
+                arr[k * B + i] = SurSample(smp["stream"].data_ptr(), smp["H"], smp["W"],
+                                           smp["T"], smp["oy"], smp["ox"], smp["t"],
+                                           smp["target"].data_ptr())
+        self._keep = [smp["stream"] for smps in steps_samples for smp in smps] + \
+            [smp["target"] for smps in steps_samples for smp in smps]
+        lr = np.ascontiguousarray(lrs, dtype=np.float32)
+        self.nparts = (B * Hc * Wc + 255) // 256
+        self.loss_partial = torch.empty((steps, self.nparts), dtype=torch.float32,
+                                        device=model.params.device)
+        h = _P()
+        rc = _lib_sur().spk_sur_train_create(
+            ctypes.byref(h), model.params.data_ptr(), model.m.data_ptr(), model.v.data_ptr(),
+            arr, lr.ctypes.data, steps, B, Hc, Wc, float(theta), beta1, beta2, eps,
+            model.step_count + 1, self.loss_partial.data_ptr())
+        _lib.check("spk_sur_train_create", rc)
+        self._h = h
+        self.done = 0
+
+    def run(self, n: int, stream=None):
+        rc = _lib_sur().spk_sur_train_run(self._h, int(n), _stream_handle(stream))
+        _lib.check("spk_sur_train_run", rc)
+        self.done += int(n)
+        self.model.step_count += int(n)
+
+    def losses(self) -> np.ndarray:
+        n = self.B * self.Hc * self.Wc
+        return (self.loss_partial[:self.done].sum(dim=1) / n).cpu().numpy()
+
+    def close(self):
+        if self._h:
+            _lib_sur().spk_sur_train_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def train_graph(model: Surrogate, scenes: SceneSet, steps: int, B: int = 16, Hc: int = 64,
+                Wc: int = 64, lr: float = 2e-3, seed: int = 0, log_every: int = 0):
+    """``train`` with the same crops and learning rates (same seed), run
+    through a ``TrainPlan``: identical parameters, without per-step host
+    work.  Returns the losses averaged as ``train`` does."""
+    rng = np.random.default_rng(seed)
+    samples = [scenes.samples(rng, B, Hc, Wc) for _ in range(steps)]
+    lrs = [lr * 0.5 * (1 + math.cos(math.pi * k / max(1, steps))) for k in range(steps)]
+    plan = TrainPlan(model, samples, lrs, Hc, Wc, scenes.theta)
+    try:
+        every = log_every if log_every else steps
+        losses = []
+        while plan.done < steps:
+            n = min(every, steps - plan.done)
+            plan.run(n)
+            if log_every:
+                l = float(plan.losses()[-n:].mean())
+                print("step %d loss %.6g" % (plan.done, l), flush=True)
+                losses.append(l)
+        if not log_every:
+            losses.append(float(plan.losses().mean()))
+        return losses
+    finally:
+        plan.close()

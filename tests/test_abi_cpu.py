@@ -184,3 +184,35 @@ def test_options(lib):
     assert lib.spk_set_option(3, -1) == -1
     assert lib.spk_set_option(3, 5) == 0 and lib.spk_get_option(3) == 5
     assert lib.spk_set_option(3, 0) == 0 and lib.spk_get_option(3) == 0
+
+
+def test_sur_train_plan_rejects_bad_arguments():
+    """The graph-replayed training plan validates everything on the host."""
+    import paper_2412_11639_amd.surrogate as sur
+    lib = sur._lib_sur()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: rejected before use
+    good = sur.SurSample(0x2000, 250, 400, 4096, 0, 0, 100, 0x3000)
+    lr = (ctypes.c_float * 2)(1e-3, 1e-3)
+
+    def create(samples, steps=2, B=1, Hc=64, Wc=64, theta=1.0, b1=0.9, b2=0.999, eps=1e-8,
+               step0=1, lrs=lr, plan=True):
+        h = ctypes.c_void_p()
+        arr = (sur.SurSample * len(samples))(*samples)
+        return lib.spk_sur_train_create(ctypes.byref(h) if plan else None, fake, fake, fake, arr,
+                                        ctypes.cast(lrs, ctypes.c_void_p), steps, B, Hc, Wc, theta,
+                                        b1, b2, eps, step0, None)
+
+    assert create([good, good], plan=False) == -1
+    assert create([good, good], steps=0) == -1
+    assert create([good] * 65, steps=1, B=65) == -1
+    assert create([good, good], step0=0) == -1
+    assert create([good, good], theta=0.0) == -1
+    assert create([good, good], b1=1.0) == -1
+    assert create([good, good], eps=0.0) == -1
+    assert create([good, good], lrs=(ctypes.c_float * 2)(1e-3, 0.0)) == -1
+    assert create([good, sur.SurSample(None, 250, 400, 4096, 0, 0, 100, 0x3000)]) == -1
+    assert create([good, sur.SurSample(0x2000, 250, 400, 4096, 0, 0, 100, None)]) == -1
+    assert create([good, sur.SurSample(0x2000, 250, 400, 4096, 200, 0, 100, 0x3000)]) == -1
+    assert create([good, sur.SurSample(0x2000, 250, 400, 4096, 0, 0, 30, 0x3000)]) == -1
+    assert lib.spk_sur_train_run(None, 1, None) == -1
+    assert lib.spk_sur_train_destroy(None) == 0

@@ -9,6 +9,8 @@ accumulation and, rarely, by one bfloat16 step where a float32 sum lands on
 the other side of a rounding boundary than its float64 value.  The bounds
 below allow a few such steps (bfloat16 has 8 significant bits, 2^-8 = 0.4%).
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -226,3 +228,33 @@ def test_conv_block_walk_is_bit_identical(sur, shape):
     for cap in (1, 3, 7):
         for k in range(3):
             assert torch.equal(res[cap][k], res[0][k]), (cap, k)
+
+
+def test_train_plan_equals_eager_training(sur):
+    """The graph-replayed training plan gives the eager loop's parameters and
+    Adam moments bit for bit (same crops, learning rates and step numbers),
+    including when its steps are run in several batches, and records each
+    step's loss."""
+    scenes = sur.SceneSet([10000, 10001], H=128, W=160, T=512, target_times=(31, 255, 511))
+    B, Hc, Wc, steps = 4, 32, 48, 9
+    eager = sur.Surrogate(seed=3)
+    losses_e = sur.train(eager, scenes, steps=steps, B=B, Hc=Hc, Wc=Wc, lr=2e-3, seed=5,
+                         log_every=1)
+    graph = sur.Surrogate(seed=3)
+    rng = np.random.default_rng(5)
+    lrs = [2e-3 * 0.5 * (1 + math.cos(math.pi * k / steps)) for k in range(steps)]
+    plan = sur.TrainPlan(graph, [scenes.samples(rng, B, Hc, Wc) for _ in range(steps)], lrs,
+                         Hc, Wc)
+    plan.run(2)
+    plan.run(0)
+    plan.run(steps - 2)
+    with pytest.raises(Exception):
+        plan.run(1)  # no steps left
+    torch.cuda.synchronize()
+    losses_g = plan.losses()
+    plan.close()
+    assert graph.step_count == eager.step_count == steps
+    assert torch.equal(graph.params, eager.params)
+    assert torch.equal(graph.m, eager.m)
+    assert torch.equal(graph.v, eager.v)
+    np.testing.assert_allclose(losses_g, losses_e, rtol=1e-5)
