@@ -936,18 +936,41 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
     if (tid < CO * 8 && tid % 8 == 0) out[S::nw + tid / 8] = bsum;
 }
 
+// The weight-gradient partials of every layer, reduced by one launch:
+// segment s sums partial[blk][j] (nblocks rows of np) into dst[j]; its
+// weights start at reduce workgroup blk0.
+struct RedSeg {
+    const float *partial;
+    float *dst;
+    int np, blk0;
+};
+struct RedArgs {
+    RedSeg seg[4];
+    int nseg, nblocks;
+};
+
 // dst[j] = sum over blocks of partial[blk][j] in a fixed order: 16 threads
 // per weight each add every 16th block (in block order), then the 16 sums
-// are added in a fixed tree.  A workgroup covers 16 consecutive weights.
-__global__ __launch_bounds__(256) void reduce_kernel(const float *partial, int nblocks, int np,
-                                                     float *dst)
+// are added in a fixed tree.  A workgroup covers 16 consecutive weights of
+// one segment.
+__global__ __launch_bounds__(256) void reduce_kernel(RedArgs R)
 {
     __shared__ float red[16][17];
+    int si = 0;
+    for (int q = 1; q < R.nseg; q++)
+        if ((int)blockIdx.x >= R.seg[q].blk0) si = q;
+    const RedSeg S = R.seg[si];
+    const int np = S.np, nblocks = R.nblocks;
+    const float *partial = S.partial;
+    float *dst = S.dst;
     const int jl = threadIdx.x & 15, part = threadIdx.x >> 4;
-    const int j = blockIdx.x * 16 + jl;
+    const int j = ((int)blockIdx.x - S.blk0) * 16 + jl;
     float acc = 0.0f;
-    if (j < np)
+    // one accumulator, rows in order; the unrolled loads overlap
+    if (j < np) {
+#pragma unroll 8
         for (int k = part; k < nblocks; k += 16) acc += partial[(int64_t)k * np + j];
+    }
     red[part][jl] = acc;
     __syncthreads();
     for (int s = 8; s > 0; s >>= 1) {
@@ -1022,13 +1045,18 @@ __host__ __device__ inline int64_t align256(int64_t x) { return (x + 255) & ~(in
 
 inline int wg_blocks(int B, int Hc, int Wc) { return B * ((Hc + 15) / 16) * ((Wc + 15) / 16); }
 
+// weight-gradient partial columns of all four layers (each layer has its
+// own rows, so that one launch reduces them all)
+constexpr int kPartialCols =
+    WgShape<WG_FIRST>::np + 2 * WgShape<WG_MID>::np + WgShape<WG_LAST>::np;
+
 inline int64_t workspace_bytes(int B, int Hc, int Wc)
 {
     const int64_t P = (int64_t)B * Hc * Wc;
     int64_t s = align256((int64_t)PACK_TOTAL * 2);
     s += 5 * align256(P * C * 2);
     s += align256(P * 4);
-    s += align256((int64_t)wg_blocks(B, Hc, Wc) * WgShape<WG_FIRST>::np * 4);
+    s += align256((int64_t)wg_blocks(B, Hc, Wc) * kPartialCols * 4);
     s += align256(((P + 255) / 256) * 4);
     return s;
 }
@@ -1048,7 +1076,7 @@ inline Workspace carve(void *ws, int B, int Hc, int Wc)
     w.dy = (float *)c;
     c += align256(P * 4);
     w.partial = (float *)c;
-    c += align256((int64_t)wg_blocks(B, Hc, Wc) * WgShape<WG_FIRST>::np * 4);
+    c += align256((int64_t)wg_blocks(B, Hc, Wc) * kPartialCols * 4);
     w.loss_partial = (float *)c;
     return w;
 }
@@ -1108,15 +1136,27 @@ void warm_launch_caches()
     conv_resident<CK_DGRAD_LAST>();
 }
 
+// Weight-gradient partials of layer kind K into a.partial (one row per
+// workgroup); the reduction into dst is queued as a segment of R.
 template <int K>
-void launch_wgrad(WgArgs a, float *dst, hipStream_t st)
+void launch_wgrad(WgArgs a, float *dst, RedArgs &R, hipStream_t st)
 {
     a.ntiles = a.B * a.tx * a.ty;
     const int nblk = a.ntiles < kWgMaxBlocks ? a.ntiles : kWgMaxBlocks;
     hipLaunchKernelGGL(wgrad_kernel<K>, dim3(nblk), dim3(256), 0, st, a);
     const int np = WgShape<K>::np;
-    hipLaunchKernelGGL(reduce_kernel, dim3((np + 15) / 16), dim3(256), 0, st, a.partial, nblk, np,
-                       dst);
+    RedSeg &S = R.seg[R.nseg++];
+    S.partial = a.partial;
+    S.dst = dst;
+    S.np = np;
+    S.blk0 = R.nseg > 1 ? R.seg[R.nseg - 2].blk0 + (R.seg[R.nseg - 2].np + 15) / 16 : 0;
+    R.nblocks = nblk;
+}
+
+void launch_reduce(const RedArgs &R, hipStream_t st)
+{
+    const RedSeg &L = R.seg[R.nseg - 1];
+    hipLaunchKernelGGL(reduce_kernel, dim3(L.blk0 + (L.np + 15) / 16), dim3(256), 0, st, R);
 }
 
 // Forward through the two fused kernels; with save, the activations of
@@ -1217,10 +1257,16 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     g.Wc = Wc;
     g.tx = (Wc + 15) / 16;
     g.ty = (Hc + 15) / 16;
-    g.partial = w.partial;
+    // each layer's partial rows in a region of its own; one reduction at
+    // the end
+    const int64_t rows = wg_blocks(B, Hc, Wc);
+    float *part = w.partial;
+    RedArgs R{};
+    g.partial = part;
+    part += rows * WgShape<WG_LAST>::np;
     g.gy = w.dy;
     g.a = w.a3;
-    launch_wgrad<WG_LAST>(g, grad + OFF_W4, st);
+    launch_wgrad<WG_LAST>(g, grad + OFF_W4, R, st);
     a.scalar = w.dy;
     a.packed = w.packed + pack_offset(PK_DG4);
     a.mask = w.a3;
@@ -1229,7 +1275,9 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     // layer 3
     g.g = w.g1;
     g.a = w.a2;
-    launch_wgrad<WG_MID>(g, grad + OFF_W3, st);
+    g.partial = part;
+    part += rows * WgShape<WG_MID>::np;
+    launch_wgrad<WG_MID>(g, grad + OFF_W3, R, st);
     a.act = w.g1;
     a.packed = w.packed + pack_offset(PK_DG3);
     a.mask = w.a2;
@@ -1238,7 +1286,9 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     // layer 2
     g.g = w.g2;
     g.a = w.a1;
-    launch_wgrad<WG_MID>(g, grad + OFF_W2, st);
+    g.partial = part;
+    part += rows * WgShape<WG_MID>::np;
+    launch_wgrad<WG_MID>(g, grad + OFF_W2, R, st);
     a.act = w.g2;
     a.packed = w.packed + pack_offset(PK_DG2);
     a.mask = w.a1;
@@ -1248,7 +1298,9 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     g.g = w.g1;
     g.win = win;
     g.est = est;
-    launch_wgrad<WG_FIRST>(g, grad + OFF_W1, st);
+    g.partial = part;
+    launch_wgrad<WG_FIRST>(g, grad + OFF_W1, R, st);
+    launch_reduce(R, st);
 }
 
 }  // namespace
