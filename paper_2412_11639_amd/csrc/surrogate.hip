@@ -8,7 +8,8 @@
 //                 the plain estimate on that window (FSR on the window as a
 //                 stream of its own, Eq. 6; fixed-window rate below two
 //                 spikes) and whether FSR keeps the window as one segment.
-//   conv (MFMA)   implicit GEMM per 16-pixel row tile: M = 16 pixels,
+//   conv (MFMA)   implicit GEMM per 16-pixel row tile (a workgroup walks
+//                 16x16 blocks, prefetching the next halo): M = 16 pixels,
 //                 N = 16 output channels per v_mfma_f32_16x16x32_bf16,
 //                 K = 32 input channels of one tap per step, 9 taps (plus a
 //                 step for the estimate channel in layer 1).  The weights of
@@ -19,10 +20,14 @@
 //                 writes 16-byte rows through LDS.  The input gradient of a
 //                 layer is the same GEMM with the taps mirrored and the
 //                 channel roles swapped.
-//   wgrad         per 16x16 pixel block, each thread accumulates its share
-//                 of dW in float32 from LDS tiles; blocks write partial sums
-//                 that a second kernel adds in a fixed order (deterministic).
+//   wgrad (MFMA)  per tap a GEMM with M = output channels, N = input
+//                 channels, K = the pixels of a 16x16 tile (both operands
+//                 staged channel-major in LDS); workgroups write partial
+//                 sums that one more kernel adds in a fixed order
+//                 (deterministic).
 //   loss, adam, mux  elementwise.
+//   training plan  one step (crops from a per-step table, forward, backward,
+//                 Adam) captured in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
