@@ -11,7 +11,8 @@ namespace {
 constexpr int kBig = 1 << 29;
 constexpr int kGroup = 8;          // tiles per prefetch group
 constexpr int kMaxLdsPlanes = 8192;  // plane map staged in LDS up to this size
-constexpr int kTargetWaves = 12288;  // chunk a stream until this many waves run
+constexpr int kTargetWaves = 12288;  // chunk a stream until this many waves run (no occupancy)
+constexpr int kMaxAutoChunks = 64;   // largest automatic chunk count
 constexpr int kMinChunkTiles = 16;   // shortest chunk worth a separate wave
 constexpr int kWarmTiles = 4;        // speculative warm-up before a chunk
 constexpr int kCaptureTiles = 4;     // tiles after a chunk's start that record the
