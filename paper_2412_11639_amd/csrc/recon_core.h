@@ -3,6 +3,8 @@
 // FSR/SSR state machine, the segment writer and the per-word walk.
 #pragma once
 
+#include <type_traits>
+
 #include "spk_internal.h"
 
 namespace spk {
@@ -566,7 +568,8 @@ struct Run {
 
     // Process the 64-frame word w starting at frame t0; cnt_row[j] is the
     // number of sorted outputs at or before frame t0 + j.
-    template <int ORDER, bool CAPTURE, class EM>
+    // FB1: keep fb1/fn1/fi1 (chunked runs only).
+    template <int ORDER, bool CAPTURE, bool FB1, class EM>
     __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em)
     {
         if (lastspk >= 0) {
@@ -615,32 +618,44 @@ struct Run {
             h = nh;
         }
         // close the segments that ended in this word
-        uint64_t B = ((uint64_t)Bhi << 32) | Blo;
-        while (B) {
-            const int cpos = ctz64(B);
-            B &= B - 1;
-            const uint64_t below = wfull & ((1ull << cpos) - 1);
-            int32_t last, kend;
-            if (below) {
-                const int bp = hibit64(below);
-                last = t0 + bp;
-                kend = cnt_row[bp];
-            } else {
-                last = lastspk0;
-                kend = cnt_last0;
+        const uint64_t B0 = ((uint64_t)Bhi << 32) | Blo;
+        // chunked runs keep the first segment closed at or after the chunk's
+        // start (for the fixup pass); once every lane that closes a segment
+        // in this word has it, the loop runs without that bookkeeping
+        auto closes = [&](auto fb1_pending) {
+            uint64_t B = B0;
+            while (B) {
+                const int cpos = ctz64(B);
+                B &= B - 1;
+                const uint64_t below = wfull & ((1ull << cpos) - 1);
+                int32_t last, kend;
+                if (below) {
+                    const int bp = hibit64(below);
+                    last = t0 + bp;
+                    kend = cnt_row[bp];
+                } else {
+                    last = lastspk0;
+                    kend = cnt_last0;
+                }
+                const int32_t last_idx = cum0 + popc64(below) - 1;
+                em.close(first, last, last_idx - first_idx, k0, kend);
+                if constexpr (decltype(fb1_pending)::value) {
+                    if (fb1 < 0 && last >= cs) {
+                        fb1 = last;
+                        fn1 = last_idx - first_idx;
+                        fi1 = last_idx;
+                    }
+                }
+                first = last;
+                first_idx = last_idx;
+                k0 = kend;
+                lastb = last;
             }
-            const int32_t last_idx = cum0 + popc64(below) - 1;
-            em.close(first, last, last_idx - first_idx, k0, kend);
-            if (fb1 < 0 && last >= cs) {
-                fb1 = last;
-                fn1 = last_idx - first_idx;
-                fi1 = last_idx;
-            }
-            first = last;
-            first_idx = last_idx;
-            k0 = kend;
-            lastb = last;
-        }
+        };
+        if (FB1 && __ballot(fb1 < 0 && B0 != 0))
+            closes(std::true_type{});
+        else
+            closes(std::false_type{});
         cum = cum0 + popc64(wfull);
         const int hp = hibit64(wfull);
         lastspk = t0 + hp;
@@ -862,11 +877,11 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
                 }
                 // the first tiles of a later chunk keep what the fixup needs
                 if (ORDER == 1 && rec_start && t >= tile0 && t < tile0 + kCaptureTiles) {
-                    if (w) run.template word<ORDER, true>(t * 64, w, cnt_s[i], em);
+                    if (w) run.template word<ORDER, true, CHUNKED>(t * 64, w, cnt_s[i], em);
                     continue;
                 }
             }
-            if (w) run.template word<ORDER, false>(t * 64, w, cnt_s[i], em);
+            if (w) run.template word<ORDER, false, CHUNKED>(t * 64, w, cnt_s[i], em);
         }
         __syncthreads();
     }
