@@ -437,6 +437,27 @@ struct SegState {
     }
 };
 
+// Eq. 6 value theta * n / d, computed in double and rounded once to float.
+// The quotient takes the steps of the compiler's IEEE double division --
+// reciprocal, two Newton-Raphson refinements, the quotient, its residual by
+// fma and one correction (Markstein) -- without the exponent scaling and the
+// special-case fix-up around them, which only act on operands near the
+// exponent limits or non-finite ones.  Here 0 < theta * n < 2^160 and
+// 1 <= d < 2^31, so the value is theta * n / d exactly as that division
+// gives it (the correctly rounded quotient).
+__device__ __forceinline__ float intensity(double theta, int32_t n, int32_t d)
+{
+    const double x = theta * (double)n, dd = (double)d;
+    double y = __builtin_amdgcn_rcp(dd);
+    double e = __builtin_fma(-dd, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-dd, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double q = x * y;
+    const double r = __builtin_fma(-dd, q, x);
+    return (float)__builtin_fma(r, y, q);
+}
+
 // How output k (in time order) maps to its plane: identity, through an LDS
 // copy of the map, or through the map in global memory (very large maps).
 enum PlaneMap { PMAP_IDENT = 0, PMAP_LDS = 1, PMAP_GLOBAL = 2 };
@@ -476,7 +497,7 @@ struct Emitter {
             k0 = max(k0, kmin);
             if (k0 >= kend) return;
             // Eq. 6: theta / ((1/N) sum T0(i)); the N intervals sum to last - first
-            const float I = (float)(P.theta * (double)n / (double)(last - first));
+            const float I = intensity(P.theta, n, last - first);
             if constexpr (PMAP == PMAP_IDENT && !WIN) {
                 // planes in time order: step a pointer by one plane per output
                 auto q = gp(P.out) + p + (uint64_t)(uint32_t)k0 * (uint32_t)P.HW;
@@ -649,13 +670,13 @@ struct Run {
                 first = last;
                 first_idx = last_idx;
                 k0 = kend;
-                lastb = last;
             }
         };
         if (FB1 && __ballot(fb1 < 0 && B0 != 0))
             closes(std::true_type{});
         else
             closes(std::false_type{});
+        if (B0) lastb = first;  // the last closed segment's last spike
         cum = cum0 + popc64(wfull);
         const int hp = hibit64(wfull);
         lastspk = t0 + hp;

@@ -107,6 +107,24 @@ def test_gratings_ragged(spk, order):
     check_segments(spk, s, H, W, T, order, cap=400)
 
 
+@pytest.mark.parametrize("theta", [1e-44, 1.1754944e-38, 1e-30, 0.3, 255.0, 1e20, 3.4e38])
+def test_intensity_extreme_theta(spk, theta):
+    """Eq. 6 over the whole float range of theta (a subnormal, the smallest
+    normal, the largest finite): the double quotient the kernels form,
+    rounded once to float, is bit-identical to the oracle's division."""
+    H, W, T = 19, 45, 1500
+    s = spkgen.gratings(H, W, T, seed=17)
+    th = float(np.float32(theta))
+    for order, t_out in ((2, list(range(0, T, 23)) + [T - 1]), (1, list(range(5, T, 41)))):
+        print("theta %g order %d" % (th, order), flush=True)
+        out = spk.reconstruct(dev(s), H, W, T, th, t_out, order=order)
+        torch.cuda.synchronize()
+        ref = oracle.reconstruct(s, H, W, T, th, t_out, order=order)
+        # bit for bit (results below the float normal range are subnormal,
+        # so a relative bound does not apply to them)
+        np.testing.assert_array_equal(out.cpu().numpy(), ref.astype(np.float32))
+
+
 def _two_value_streams(rng, P, T, avals=tuple(range(1, 16)), group=15):
     """Per pixel an interval sequence over {a, a+1} (a from avals in turn):
     balanced (constant-rate) sequences, balanced ones with two neighbours
