@@ -32,19 +32,22 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p)
 
 // ---- cross-lane moves ----------------------------------------------------
 
+// Each DPP move below reads a valid source lane for every lane, so no old
+// value is needed (a DPP update with an old value costs an extra move).
 template <int S>
 __device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane)
 {
     if constexpr (S == 1) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // quad [1,0,3,2]
     } else if constexpr (S == 2) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
-    } else if constexpr (S == 4 || S == 8) {
-        // within a row of 16 lanes: lanes with bit S clear read lane + S
-        // (row_shl), the others lane - S (row_shr)
-        const int up = __builtin_amdgcn_update_dpp(0, (int)v, 0x100 + S, 0xF, 0xF, false);
-        const int dn = __builtin_amdgcn_update_dpp(0, (int)v, 0x110 + S, 0xF, 0xF, false);
-        return (uint32_t)((lane & S) ? dn : up);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // quad [2,3,0,1]
+    } else if constexpr (S == 4) {
+        // mirror within 8 lanes (i ^ 7), then within 4 (i ^ 3): i ^ 4
+        const int m = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);
+        return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, true);
+    } else if constexpr (S == 8) {
+        // rotate a row of 16 lanes by 8: i ^ 8
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);
     } else {
         static_assert(S == 16, "lane_xor");
         // swap rows 1<->0 and 3<->2 of 16 lanes
@@ -81,7 +84,8 @@ __device__ __forceinline__ uint32_t xstage(uint32_t v, const Xpose &X, int lane)
     // rotate the partner's word so its swapped block lands in place; bits
     // wrapped around by the rotation fall outside the taken mask
     const uint32_t t = __builtin_amdgcn_alignbit(y, y, X.rot[I]);
-    return (v & X.keep[I]) | (t & ~X.keep[I]);
+    // keep ? v : t, bit by bit, in one instruction (table index 4v + 2t + keep)
+    return __builtin_amdgcn_bitop3_b32(v, t, X.keep[I], 0xE4);
 }
 
 // 64x64 bit-matrix transpose across a wave: on entry lane j holds row j as
