@@ -661,6 +661,24 @@ def main():
         wall = time.perf_counter() - w0
         return e0.elapsed_time(e1) / args.steps, wall
 
+    def copy_bandwidth():
+        # a 1 GiB device-to-device copy: bytes read + written per second
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            b.copy_(a)
+        c1.record()
+        torch.cuda.synchronize()
+        ms_copy = c0.elapsed_time(c1) / 5
+        del a, b
+        torch.cuda.empty_cache()
+        return 2.0 * COPY_BYTES / (ms_copy * 1e-3) / 1e9
+
     print("timing %d steps" % args.steps, file=sys.stderr, flush=True)
     other = spk.FSR if order == spk.SSR else spk.SSR
     ms_other, _ = timed(other)
@@ -671,6 +689,7 @@ def main():
     value = px_frames / (ms * 1e-3) / 1e6
     alg = algorithmic_bytes(H, W, T, n_out)
     achieved = alg / (ms * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth()
     counters = load_counters(args.order.upper())
     traffic = counters.get("hbm_bytes_per_launch")
     traffic = None if traffic is None else round(traffic)
@@ -696,6 +715,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
+        "hbm_copy": {"GBs": round(copy_gbs, 1),
+                     "what": "1 GiB device-to-device copy, bytes read + written per second",
+                     "achieved_frac_of_copy": round(achieved / copy_gbs, 4)},
         "valu": None if valu is None else {
             "note": "the kernel is bound by integer VALU issue, not HBM",
             "instr_per_step": round(valu), "issue_per_s": round(valu / (ms * 1e-3)),
