@@ -386,8 +386,8 @@ struct SegState {
             const int32_t ngl = min(odd ? g1l : g0l, d), ngh = max(odd ? g1h : g0h, d);
             const bool seen = l >= ps;  // x already occurred in the open piece
             const bool cut = fcut || (seen && ngh - ngl > 1);
-            const bool fresh = cut || !seen;
-            const int32_t ugl = fresh ? kBig : ngl, ugh = fresh ? -kBig : ngh;
+            const bool keep = seen && !cut;  // the value's gaps continue
+            const int32_t ugl = keep ? ngl : kBig, ugh = keep ? ngh : -kBig;
             l0 = odd ? l0 : ii;
             l1 = odd ? ii : l1;
             g0l = odd ? g0l : ugl;
