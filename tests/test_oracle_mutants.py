@@ -50,7 +50,7 @@ MUTANTS = {
 
 
 def _battery(lib):
-    """Returns the list of pin names that fail for this build."""
+    """Returns the list of pin names that fail for the oracle library lib."""
     failed = []
     # hand-worked example
     s, H, W, T = worked_example_stream()
