@@ -37,7 +37,13 @@ namespace {
 // a fresh state at its first spike (speculation), and each wave records its
 // state at its chunk's end for the fixup pass, which makes the result exact.
 template <int ORDER, int MODE, bool WIN, int PMAP>
-__global__ __launch_bounds__(64) void recon_kernel(ReconParams P, int nblocks, ChunkPlan cp)
+// Four waves per SIMD (at most 128 VGPRs) for FSR, SSR and TFI: the SSR
+// state machine alone would take 140 and run three, and the walk is bound
+// by VALU issue, which the fourth wave keeps fuller (a few bytes of the
+// per-group state go to scratch, outside the per-spike loops).  The third
+// order's larger state keeps its natural allocation.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ORDER == 4 ? 1 : 4)))
+void recon_kernel(ReconParams P, int nblocks, ChunkPlan cp)
 {
     __shared__ uint64_t word_s[kGroup][64];
     __shared__ int32_t cnt_s[kGroup][64];
