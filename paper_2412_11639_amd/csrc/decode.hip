@@ -3,14 +3,15 @@
 // spk_segments writes it, without the stream.  This is the encoder/decoder
 // split of the paper's hardware design (Sec. III-C): the segmentation pass
 // emits one record per segment, and a second pass expands the records to
-// frames.  One lane per pixel walks the requested frames in time order with
-// a cursor on its segment list; every store of a frame plane is coalesced
-// across the wave.
+// frames.  One lane per pixel; the requested frames are taken in time order,
+// 32 at a time, and every store of a frame plane is coalesced across the
+// wave.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 #include "spk.h"
 #include "spk_internal.h"
@@ -18,67 +19,107 @@
 namespace spk {
 namespace {
 
-constexpr int kDecFrames = 32;  // output frames per LDS tile
+constexpr int kDecFrames = 32;  // output frames per tile
 
-// One wave per 64 pixels (lane = pixel).  The requested frames are taken in
-// time order, kDecFrames at a time: each lane first advances its cursor
-// and writes its values into an LDS tile (its segment loads are prefetched
-// one segment ahead, and no global store is pending while it waits for
-// them), then the wave stores the tile plane by plane, 256 contiguous
-// bytes per plane.
+// One wave per 64 pixels (lane = pixel).  Segment s of a pixel covers the
+// requested frames (in time order) from index B(s-1) up to B(s), where
+// B(s) = number of requested times <= its last spike (the last stored
+// segment of a complete list covers every later frame).  Per tile of 32
+// frames a lane only visits the segment boundaries that fall inside the
+// tile: it writes the value of each piece to its own column of an LDS
+// table and sets bit (B - j0) of a mask.  The frames are then expanded with
+// one bit extract and one add each (the piece index is the number of mask
+// bits at or below the frame) and stored plane by plane, 256 contiguous
+// bytes per plane.  A cursor advance -- its gathers and its division -- is
+// paid once per boundary instead of in every frame the wave visits.
+template <bool IDENT>
 __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
                                                     const int32_t *seg_last,
                                                     const int32_t *seg_n, const int32_t *count,
-                                                    int32_t cap, int64_t HW, double theta,
-                                                    const int32_t *t_sorted,
+                                                    int32_t cap, int64_t HW, int32_t T,
+                                                    double theta, const int32_t *cnt_le,
                                                     const int32_t *plane, int32_t n_out,
                                                     float *out)
 {
-    __shared__ float tile[kDecFrames][64];
+    // piece k of the current tile for lane l at vals[k][l]: at most one
+    // piece per frame
+    __shared__ float vals[kDecFrames][64];
     const int lane = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
-    const bool valid = p < HW;
-    const int32_t S = valid ? count[p] : 0;
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const bool valid = p0 + lane < HW;
+    const int32_t S = valid ? count[p0 + lane] : 0;
     const int32_t stored = S < cap ? S : cap;
-    // current segment: index, last spike, value; the next one prefetched
-    int32_t s = 0, last = INT_MAX, nf = 0, nl = 0, nn = 0;
-    float I = 0.0f;  // S == 0: fewer than two spikes, every output is 0
+    // current segment s: value I, first frame index past it B; the record
+    // of segment s + 1 prefetched in nf, nl, nn
+    int32_t s = -1, nf = 0, nl = 0, nn = 0;
+    float I = 0.0f;      // S == 0: fewer than two spikes, every output is 0
+    int32_t B = INT_MAX;
     auto fetch = [&](int32_t k) {
-        const int64_t o = (int64_t)k * HW + p;
+        const int64_t o = (int64_t)k * HW + p0 + lane;
         nf = seg_first[o];
         nl = seg_last[o];
         nn = seg_n[o];
     };
-    auto take = [&]() {
+    auto advance = [&]() {
+        s++;
         if (s < stored) {
-            last = nl;
             // Eq. 6 as in the reconstruction pass
             I = (float)(theta * (double)nn / (double)(nl - nf));
+            // requested times <= the segment's last spike (the last
+            // segment of the list takes every later time)
+            const int32_t c = cnt_le[min(max(nl, 0), T - 1)];
+            B = s + 1 >= S ? INT_MAX : (nl < 0 ? 0 : (nl >= T ? n_out : c));
+            if (s + 1 < stored) fetch(s + 1);
         } else {
             // not stored (the list was cut at cap): unknown from here on
-            last = INT_MAX;
             I = __builtin_nanf("");
+            B = INT_MAX;
         }
-        if (s + 1 < stored) fetch(s + 1);
     };
     if (S > 0) {
         if (stored > 0) fetch(0);
-        take();
+        advance();
     }
+    const uint32_t ulane = (uint32_t)lane;
     for (int32_t j0 = 0; j0 < n_out; j0 += kDecFrames) {
-        const int32_t nj = min(kDecFrames, n_out - j0);
-        for (int32_t jj = 0; jj < nj; jj++) {
-            const int32_t t = t_sorted[j0 + jj];
-            // the segment holding the interval in progress at t: advance
-            // while the current one ends before t (the last takes later t)
-            while (last < t && s + 1 < S) {
-                s++;
-                take();
-            }
-            tile[jj][lane] = I;
+        const int32_t j1 = min(n_out, j0 + kDecFrames);
+        // the segment in progress at the tile's first frame
+        while (B <= j0) advance();
+        uint32_t mask = 0;
+        int k = 0;
+        vals[0][lane] = I;
+        while (B < j1) {
+            const int32_t b = B;   // j0 < b < j0 + 32
+            mask |= 1u << (b - j0);
+            do advance();
+            while (B <= b);        // segments that hold no requested frame
+            vals[++k][lane] = I;
         }
-        for (int32_t jj = 0; jj < nj; jj++)
-            if (valid) out[(int64_t)plane[j0 + jj] * HW + p] = tile[jj][lane];
+        // each lane reads back only its own column
+        float v[kDecFrames];
+        int idx = 0;
+#pragma unroll
+        for (int jj = 0; jj < kDecFrames; jj++) {
+            idx += (mask >> jj) & 1u;
+            v[jj] = vals[idx][lane];
+        }
+        auto put = [&](auto full) {
+            float *row = out + (int64_t)j0 * HW + p0;  // plane j0 (in time order)
+#pragma unroll
+            for (int jj = 0; jj < kDecFrames; jj++) {
+                if (decltype(full)::value || j0 + jj < j1) {
+                    if constexpr (!IDENT) row = out + (int64_t)plane[j0 + jj] * HW + p0;
+                    row[ulane] = v[jj];
+                    if constexpr (IDENT) row += HW;
+                }
+            }
+        };
+        if (valid) {
+            if (j1 - j0 == kDecFrames)
+                put(std::true_type{});
+            else
+                put(std::false_type{});
+        }
     }
 }
 
@@ -105,8 +146,14 @@ extern "C" int spk_decode(const int32_t *seg_first, const int32_t *seg_last, con
     spk::OutTables tab;
     const int rc = spk::out_tables(T, t_out, n_out, st, &tab);
     if (rc) return rc;
-    hipLaunchKernelGGL(spk::decode_kernel, dim3((unsigned)((HW + 63) / 64)), dim3(64), 0, st,
-                       seg_first, seg_last, seg_n, count, cap, HW, (double)theta, tab.t_sorted,
-                       tab.plane, n_out, out);
+    const dim3 grid((unsigned)((HW + 63) / 64)), block(64);
+    if (tab.identity)
+        hipLaunchKernelGGL(spk::decode_kernel<true>, grid, block, 0, st, seg_first, seg_last,
+                           seg_n, count, cap, HW, T, (double)theta, tab.cnt_le, tab.plane,
+                           n_out, out);
+    else
+        hipLaunchKernelGGL(spk::decode_kernel<false>, grid, block, 0, st, seg_first, seg_last,
+                           seg_n, count, cap, HW, T, (double)theta, tab.cnt_le, tab.plane,
+                           n_out, out);
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
 }

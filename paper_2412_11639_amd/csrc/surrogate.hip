@@ -322,6 +322,9 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
     constexpr int SP = 40;
     __shared__ __attribute__((aligned(16))) __bf16 tin[VEC_IN ? kHalo * CP : 8];
     __shared__ float tsc[SCALAR_IN ? kHalo : 1];
+    // the scalar channel's 9 taps per output pixel as bfloat16 (then 7
+    // zeros): the A fragment of its K step is one 16-byte read
+    __shared__ __attribute__((aligned(16))) __bf16 tcol[SCALAR_IN ? 256 * 16 : 8];
     __shared__ __attribute__((aligned(16))) __bf16 stage[4][KIND == CK_LAST ? 8 : 16 * SP];
     __shared__ float stagef[4][KIND == CK_LAST ? 64 : 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -384,10 +387,14 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
                 const int it = tid + 256 * u;
                 if (it < kVecItems) {
                     if constexpr (BITS_IN) {
+                        // neighbouring threads start on different 16-byte
+                        // parts of their pixels (fewer LDS bank conflicts)
 #pragma unroll
-                        for (int part = 0; part < 4; part++)
+                        for (int k = 0; k < 4; k++) {
+                            const int part = (k + it) & 3;
                             *(bf16x8 *)(&tin[it * CP + part * 8]) =
                                 bits_to_bf16((pw[u] >> (8 * part)) & 0xFFu);
+                        }
                     } else {
                         *(bf16x8 *)(&tin[(it >> 2) * CP + (it & 3) * 8]) = pv[u];
                     }
@@ -405,9 +412,27 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
     const int per = (A.nblocks + (int)gridDim.x - 1) / (int)gridDim.x;
     const int blk0 = (int)blockIdx.x * per, blk1 = min(A.nblocks, blk0 + per);
     if (blk0 >= blk1) return;
+    auto build_col = [&]() {
+        if constexpr (SCALAR_IN) {
+            const int oy = tid >> 4, ox = tid & 15;
+            bf16x8 lo, hi;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                lo[e] = (__bf16)tsc[(oy + e / 3) * 18 + ox + e % 3];
+                hi[e] = (__bf16)0.0f;
+            }
+            hi[0] = (__bf16)tsc[(oy + 2) * 18 + ox + 2];
+            *(bf16x8 *)(&tcol[tid * 16]) = lo;
+            *(bf16x8 *)(&tcol[tid * 16 + 8]) = hi;
+        }
+    };
     load(blk0);
     store();
     __syncthreads();
+    if constexpr (SCALAR_IN) {
+        build_col();
+        __syncthreads();
+    }
     // output staging rows: pixel lane/4, channels 8 (lane%4) .. +7
     const int px = lane >> 2, part = lane & 3;
     for (int blk = blk0; blk < blk1; blk++) {
@@ -440,10 +465,11 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
                 const bool scalar_step = KIND == CK_DGRAD_LAST || (KIND == CK_FIRST && s == 9);
                 if (scalar_step) {
                     // row k of the K block = tap k of the scalar channel
+                    if (g < 2) {
+                        a = *(const bf16x8 *)(&tcol[(oy * 16 + i) * 16 + 8 * g]);
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 8; e++) {
-                        const int k = g * 8 + e;
-                        a[e] = k < 9 ? (__bf16)tsc[(oy + k / 3) * 18 + i + k % 3] : (__bf16)0.0f;
+                        for (int e = 0; e < 8; e++) a[e] = (__bf16)0.0f;
                     }
                 } else {
                     a = *(const bf16x8 *)(&tin[((oy + s / 3) * 18 + i + s % 3) * CP + 8 * g]);
@@ -508,6 +534,12 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
         if (more) {
             __syncthreads();  // every wave is done with this halo
             store();
+        }
+        if constexpr (SCALAR_IN) {
+            if (more) {
+                __syncthreads();  // the next halo's scalar channel is in LDS
+                build_col();
+            }
         }
         // second half: global stores
         if constexpr (KIND == CK_LAST) {

@@ -386,6 +386,57 @@ def test_decode_of_cut_lists_is_nan_past_cap(spk):
                 assert np.isnan(got[k, p]), (p, t)
 
 
+@pytest.mark.parametrize("order_name", ["FSR", "SSR", "TSR"])
+def test_decode_every_frame_short_segments(spk, order_name):
+    """Outputs at every frame over pixels whose segments last from one frame
+    to hundreds (up to 31 segment boundaries inside one 32-frame tile of
+    outputs), in time order and shuffled, a ragged last wave of pixels and a
+    ragged last tile: decode equals reconstruct and the oracle."""
+    order = getattr(spk, order_name)
+    rng = np.random.default_rng(41)
+    H, W, T = 3, 69, 701
+    P = H * W
+    # four kinds of pixel: i.i.d. spikes (probability from dense to sparse),
+    # a fixed rate with occasional jumps, intervals alternating 1, 3 (a
+    # segment boundary at every spike: 16 in a 32-frame tile) and intervals
+    # i.i.d. over {a, a+1}, a = 2..4
+    prob = rng.uniform(0.03, 0.95, size=P)
+    bits = np.zeros((T, P), dtype=np.uint8)
+    for p in range(P):
+        if p % 4 == 0:
+            bits[:, p] = rng.random(T) < prob[p]
+            continue
+        if p % 4 == 1:
+            step = max(1, int(round(1 / prob[p])))
+            gaps = step + np.where(rng.random(T) < 0.2, rng.integers(-1, 2, size=T), 0)
+        else:
+            if p % 4 == 2:
+                gaps = 1 + 2 * ((np.arange(T) + p // 4) % 2)
+            else:
+                gaps = int(rng.integers(2, 5)) + (rng.random(T) < 0.5)
+        t = int(rng.integers(0, 3))
+        for g in gaps:
+            if t >= T:
+                break
+            bits[t, p] = 1
+            t += max(1, int(g))
+    s = spkgen.pack(bits)
+    ds = dev(s)
+    cnt = spk.segments(ds, H, W, T, order=order, cap=0)[3]
+    cap = max(1, int(cnt.max().item()))
+    sf, sl, sn, cnt = spk.segments(ds, H, W, T, order=order, cap=cap)
+    every = list(range(T))
+    shuffled = [int(t) for t in rng.permutation(T)] + [0, T - 1, 17]
+    ref_all = oracle.reconstruct(s, H, W, T, 1.0, every, order=order).astype(np.float32)
+    for t_out in (every, every[5:-3], shuffled):
+        got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out)
+        ref = spk.reconstruct(ds, H, W, T, 1.0, t_out, order=order)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
+        np.testing.assert_array_equal(got.cpu().numpy().reshape(len(t_out), -1),
+                                      ref_all.reshape(T, -1)[t_out])
+
+
 # --------------------------------------------------------------------------
 # the third order (n-order rule one step past SSR)
 
