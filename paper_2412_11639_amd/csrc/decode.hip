@@ -24,7 +24,11 @@ constexpr int kDecFrames = 32;  // output frames per tile
 // One wave per 64 pixels (lane = pixel).  Segment s of a pixel covers the
 // requested frames (in time order) from index B(s-1) up to B(s), where
 // B(s) = number of requested times <= its last spike (the last stored
-// segment of a complete list covers every later frame).  Per tile of 32
+// segment of a complete list covers every later frame).  B comes from the
+// cumulative count table, or, when the requested times are evenly spaced
+// (AP: t0, t0 + dt, ...), from one division, so that a cursor advance
+// needs no gather that depends on the record it reads.  The record of the
+// next segment is prefetched.  Per tile of 32
 // frames a lane only visits the segment boundaries that fall inside the
 // tile: it writes the value of each piece to its own column of an LDS
 // table and sets bit (B - j0) of a mask.  The frames are then expanded with
@@ -32,12 +36,13 @@ constexpr int kDecFrames = 32;  // output frames per tile
 // bits at or below the frame) and stored plane by plane, 256 contiguous
 // bytes per plane.  A cursor advance -- its gathers and its division -- is
 // paid once per boundary instead of in every frame the wave visits.
-template <bool IDENT>
+template <bool IDENT, bool AP>
 __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
                                                     const int32_t *seg_last,
                                                     const int32_t *seg_n, const int32_t *count,
                                                     int32_t cap, int64_t HW, int32_t T,
                                                     double theta, const int32_t *cnt_le,
+                                                    int32_t t0, int32_t dt,
                                                     const int32_t *plane, int32_t n_out,
                                                     float *out)
 {
@@ -65,10 +70,18 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
         if (s < stored) {
             // Eq. 6 as in the reconstruction pass
             I = (float)(theta * (double)nn / (double)(nl - nf));
-            // requested times <= the segment's last spike (the last
-            // segment of the list takes every later time)
-            const int32_t c = cnt_le[min(max(nl, 0), T - 1)];
-            B = s + 1 >= S ? INT_MAX : (nl < 0 ? 0 : (nl >= T ? n_out : c));
+            // requested times <= the segment's last spike: from the
+            // cumulative count table, or by one division for t0, t0 + dt, ...
+            // (the last segment of the list takes every later time)
+            int32_t le;
+            if constexpr (AP) {
+                const uint32_t q = (uint32_t)(nl - t0) / (uint32_t)dt + 1u;
+                le = nl < t0 ? 0 : (q < (uint32_t)n_out ? (int32_t)q : n_out);
+            } else {
+                const int32_t c = cnt_le[min(max(nl, 0), T - 1)];
+                le = nl < 0 ? 0 : (nl >= T ? n_out : c);
+            }
+            B = s + 1 >= S ? INT_MAX : le;
             if (s + 1 < stored) fetch(s + 1);
         } else {
             // not stored (the list was cut at cap): unknown from here on
@@ -109,7 +122,9 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
             for (int jj = 0; jj < kDecFrames; jj++) {
                 if (decltype(full)::value || j0 + jj < j1) {
                     if constexpr (!IDENT) row = out + (int64_t)plane[j0 + jj] * HW + p0;
-                    row[ulane] = v[jj];
+                    // streamed past the caches: the frames are not read
+                    // back, and the segment records keep the L2
+                    __builtin_nontemporal_store(v[jj], &row[ulane]);
                     if constexpr (IDENT) row += HW;
                 }
             }
@@ -146,14 +161,33 @@ extern "C" int spk_decode(const int32_t *seg_first, const int32_t *seg_last, con
     spk::OutTables tab;
     const int rc = spk::out_tables(T, t_out, n_out, st, &tab);
     if (rc) return rc;
+    // evenly spaced requested times (ascending or descending, no repeats):
+    // the count of times <= x is one division
+    int32_t t0 = 0, dt = 1;
+    bool ap = n_out == 1;
+    if (n_out >= 2) {
+        const int32_t d = t_out[1] - t_out[0];
+        ap = d != 0;
+        for (int32_t k = 2; ap && k < n_out; k++) ap = t_out[k] - t_out[k - 1] == d;
+        if (ap) {
+            dt = d > 0 ? d : -d;
+            t0 = d > 0 ? t_out[0] : t_out[n_out - 1];
+        }
+    } else {
+        t0 = t_out[0];
+    }
     const dim3 grid((unsigned)((HW + 63) / 64)), block(64);
-    if (tab.identity)
-        hipLaunchKernelGGL(spk::decode_kernel<true>, grid, block, 0, st, seg_first, seg_last,
-                           seg_n, count, cap, HW, T, (double)theta, tab.cnt_le, tab.plane,
-                           n_out, out);
+#define SPK_DECODE_LAUNCH(I, A)                                                                \
+    hipLaunchKernelGGL((spk::decode_kernel<I, A>), grid, block, 0, st, seg_first, seg_last, seg_n, \
+                       count, cap, HW, T, (double)theta, tab.cnt_le, t0, dt, tab.plane, n_out, out)
+    if (tab.identity && ap)
+        SPK_DECODE_LAUNCH(true, true);
+    else if (tab.identity)
+        SPK_DECODE_LAUNCH(true, false);
+    else if (ap)
+        SPK_DECODE_LAUNCH(false, true);
     else
-        hipLaunchKernelGGL(spk::decode_kernel<false>, grid, block, 0, st, seg_first, seg_last,
-                           seg_n, count, cap, HW, T, (double)theta, tab.cnt_le, tab.plane,
-                           n_out, out);
+        SPK_DECODE_LAUNCH(false, false);
+#undef SPK_DECODE_LAUNCH
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
 }

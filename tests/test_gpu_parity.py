@@ -389,9 +389,11 @@ def test_decode_of_cut_lists_is_nan_past_cap(spk):
 @pytest.mark.parametrize("order_name", ["FSR", "SSR", "TSR"])
 def test_decode_every_frame_short_segments(spk, order_name):
     """Outputs at every frame over pixels whose segments last from one frame
-    to hundreds (up to 31 segment boundaries inside one 32-frame tile of
-    outputs), in time order and shuffled, a ragged last wave of pixels and a
-    ragged last tile: decode equals reconstruct and the oracle."""
+    to hundreds (up to 16 segment boundaries inside one 32-frame tile of
+    outputs); evenly spaced output times in both directions and at a stride,
+    a single time, and shuffled times with repeats; a ragged last wave of
+    pixels and a ragged last tile: decode equals reconstruct and the
+    oracle."""
     order = getattr(spk, order_name)
     rng = np.random.default_rng(41)
     H, W, T = 3, 69, 701
@@ -428,7 +430,8 @@ def test_decode_every_frame_short_segments(spk, order_name):
     every = list(range(T))
     shuffled = [int(t) for t in rng.permutation(T)] + [0, T - 1, 17]
     ref_all = oracle.reconstruct(s, H, W, T, 1.0, every, order=order).astype(np.float32)
-    for t_out in (every, every[5:-3], shuffled):
+    # evenly spaced (ascending, descending, stride 7, one time) and not
+    for t_out in (every, every[5:-3], every[::-1], every[2::7], [T // 2], shuffled):
         got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out)
         ref = spk.reconstruct(ds, H, W, T, 1.0, t_out, order=order)
         torch.cuda.synchronize()
