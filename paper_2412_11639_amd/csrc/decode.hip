@@ -26,15 +26,16 @@ constexpr int kDecFrames = 32;  // output frames per tile
 // B(s) = number of requested times <= its last spike (the last stored
 // segment of a complete list covers every later frame).  B comes from the
 // cumulative count table, or, when the requested times are evenly spaced
-// (AP: t0, t0 + dt, ...), from one division, so that a cursor advance
-// needs no gather that depends on the record it reads.  The record of the
-// next segment is prefetched.  Per tile of 32
-// frames a lane only visits the segment boundaries that fall inside the
-// tile: it writes the value of each piece to its own column of an LDS
+// (AP: t0, t0 + dt, ...), from one division, so that a cursor advance needs
+// no gather that depends on the record it reads.  The record of the next
+// segment is prefetched.
+//
+// Per tile of 32 frames a lane visits only the segment boundaries inside
+// the tile: it writes the value of each piece to its own column of an LDS
 // table and sets bit (B - j0) of a mask.  The frames are then expanded with
 // one bit extract and one add each (the piece index is the number of mask
 // bits at or below the frame) and stored plane by plane, 256 contiguous
-// bytes per plane.  A cursor advance -- its gathers and its division -- is
+// bytes per plane.  A cursor advance -- its loads and its division -- is
 // paid once per boundary instead of in every frame the wave visits.
 template <bool IDENT, bool AP>
 __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
@@ -69,13 +70,13 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
         s++;
         if (s < stored) {
             // Eq. 6 as in the reconstruction pass
-            I = (float)(theta * (double)nn / (double)(nl - nf));
+            I = (float)(theta * (double)nn / (double)((int64_t)nl - nf));
             // requested times <= the segment's last spike: from the
             // cumulative count table, or by one division for t0, t0 + dt, ...
             // (the last segment of the list takes every later time)
             int32_t le;
             if constexpr (AP) {
-                const uint32_t q = (uint32_t)(nl - t0) / (uint32_t)dt + 1u;
+                const uint32_t q = ((uint32_t)nl - (uint32_t)t0) / (uint32_t)dt + 1u;
                 le = nl < t0 ? 0 : (q < (uint32_t)n_out ? (int32_t)q : n_out);
             } else {
                 const int32_t c = cnt_le[min(max(nl, 0), T - 1)];
