@@ -247,6 +247,92 @@ def run_surrogate(args, spk, spkgen, torch, np):
     return out, checks
 
 
+def _streaming_scene(spkgen, np, H, W, T):
+    """The streaming workload: blocks translating at one velocity,
+    |v| in (0, 2] px/frame, direction and speed from seed 5."""
+    speed = 2.0 * (1.0 - spkgen.rng_u64(5, 7, 0) / 2.0 ** 64)    # (0, 2]
+    ang = 2.0 * np.pi * (spkgen.rng_u64(5, 7, 1) / 2.0 ** 64)
+    vx, vy = speed * np.cos(ang), speed * np.sin(ang)
+    print("streaming: generating %dx%dx%d" % (H, W, T), file=sys.stderr, flush=True)
+    return spkgen.blocks(H, W, T, 5, vx=vx, vy=vy), speed, vx, vy
+
+
+def _encoded_leg(spk, torch, ds, H, W, T, frames, out, ref_idx, ref_kept):
+    """The plain method through the segment encoding (FSR): spk_segments
+    writes each pixel's segment list, spk_decode expands it to every frame
+    in ``frames`` (into ``out``).  Times both on the second of two runs;
+    ``ref_kept`` (planes ``ref_idx`` of the single-pass output) checks the
+    decoded frames.  The decoder's roofline is HBM: algorithmic bytes are
+    the lists it reads (12 B per segment plus the counts) and the frames it
+    writes."""
+    cnt = spk.segments(ds, H, W, T, order=spk.FSR, cap=0)[3]
+    cap = max(1, int(cnt.max().item()))
+    seg = [torch.empty((cap, H * W), dtype=torch.int32, device="cuda") for _ in range(3)]
+    lib = spk._lib.load()
+    tp = (ctypes.c_int32 * len(frames))(*frames)
+    e0, e_mid, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+
+    def encoded():
+        rc = lib.spk_segments(ds.data_ptr(), H, W, T, spk.FSR, cap, seg[0].data_ptr(),
+                              seg[1].data_ptr(), seg[2].data_ptr(), cnt.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+        e_mid.record()
+        rc |= lib.spk_decode(seg[0].data_ptr(), seg[1].data_ptr(), seg[2].data_ptr(),
+                             cnt.data_ptr(), cap, H, W, T, 1.0, tp, len(frames),
+                             out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        assert rc == 0
+
+    encoded()
+    torch.cuda.synchronize()
+    e0.record()
+    encoded()
+    e1.record()
+    torch.cuda.synchronize()
+    enc_ms, dec_ms = e0.elapsed_time(e_mid), e_mid.elapsed_time(e1)
+    same = bool(torch.equal(out[ref_idx].cpu(), torch.from_numpy(ref_kept)))
+    seg_bytes = int(cnt.sum().item()) * 12
+    dec_bytes = seg_bytes + H * W * 4 + len(frames) * H * W * 4
+    achieved = dec_bytes / (dec_ms * 1e-3) / 1e9
+    del seg
+    return {"mpx_frames_per_s": round(H * W * T / ((enc_ms + dec_ms) * 1e-3) / 1e6, 1),
+            "segments_ms": round(enc_ms, 3), "decode_ms": round(dec_ms, 3),
+            "segment_bytes": seg_bytes, "cap": cap, "equals_single_pass": same,
+            "decode_roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                "algorithmic_bytes": dec_bytes}}
+
+
+def run_encoded(args, spk, spkgen, torch, np):
+    """The streaming scene's plain single pass (every frame from 31 on)
+    and the same through segment lists + decode, nothing else."""
+    H = W = 1000
+    T = args.stream_frames
+    s, speed, _, _ = _streaming_scene(spkgen, np, H, W, T)
+    ds = torch.from_numpy(s).cuda()
+    frames = list(range(31, T))
+    out = torch.empty((len(frames), H, W), dtype=torch.float32, device="cuda")
+    spk.reconstruct(ds, H, W, T, 1.0, frames, order=spk.FSR, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    spk.reconstruct(ds, H, W, T, 1.0, frames, order=spk.FSR, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    idx = np.linspace(0, len(frames) - 1, 64).astype(int).tolist()
+    kept = out[idx].cpu().numpy()
+    res = {"workload": "blocks_1000x1000 translating |v|=%.3f px/frame (seed 5), %d frames"
+                       % (speed, T),
+           "plain_single_pass": {"mpx_frames_per_s": round(H * W * T / (plain_ms * 1e-3) / 1e6, 1),
+                                 "ms": round(plain_ms, 3),
+                                 "outputs": "every frame 31..%d" % (T - 1)},
+           "plain_encoded": _encoded_leg(spk, torch, ds, H, W, T, frames, out, idx, kept)}
+    del ds, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_streaming(args, spk, spkgen, torch, np, model, sur):
     """1000x1000 blocks translating at one velocity, |v| in (0, 2] px/frame
     (seed 5).  Per frame: advance the 32-frame window, run the surrogate and
@@ -256,11 +342,7 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     frames for each output frame."""
     H = W = 1000
     T = args.stream_frames
-    speed = 2.0 * (1.0 - spkgen.rng_u64(5, 7, 0) / 2.0 ** 64)    # (0, 2]
-    ang = 2.0 * np.pi * (spkgen.rng_u64(5, 7, 1) / 2.0 ** 64)
-    vx, vy = speed * np.cos(ang), speed * np.sin(ang)
-    print("streaming: generating 1000x1000x%d" % T, file=sys.stderr, flush=True)
-    s = spkgen.blocks(H, W, T, 5, vx=vx, vy=vy)
+    s, speed, vx, vy = _streaming_scene(spkgen, np, H, W, T)
     ds = torch.from_numpy(s).cuda()
     win = torch.zeros((1, H, W), dtype=torch.int32, device="cuda")
     est = torch.zeros((1, H, W), dtype=torch.float32, device="cuda")
@@ -314,34 +396,9 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     plain_kept = plain_out[[t - 31 for t in check_t]].cpu().numpy()
     # the same through the segment encoding: one pass writes each pixel's
     # segment list, a second expands it to every frame
-    cnt = spk.segments(ds, H, W, T, order=spk.FSR, cap=0)[3]
-    cap = max(1, int(cnt.max().item()))
-    seg = [torch.empty((cap, H * W), dtype=torch.int32, device="cuda") for _ in range(3)]
-    lib = spk._lib.load()
-    tp = (ctypes.c_int32 * len(frames))(*frames)
-
-    def encoded():
-        rc = lib.spk_segments(ds.data_ptr(), H, W, T, spk.FSR, cap, seg[0].data_ptr(),
-                              seg[1].data_ptr(), seg[2].data_ptr(), cnt.data_ptr(),
-                              torch.cuda.current_stream().cuda_stream)
-        e_mid.record()
-        rc |= lib.spk_decode(seg[0].data_ptr(), seg[1].data_ptr(), seg[2].data_ptr(),
-                             cnt.data_ptr(), cap, H, W, T, 1.0, tp, len(frames),
-                             plain_out.data_ptr(), torch.cuda.current_stream().cuda_stream)
-        assert rc == 0
-
-    e_mid = torch.cuda.Event(enable_timing=True)
-    encoded()
-    torch.cuda.synchronize()
-    e0.record()
-    encoded()
-    e1.record()
-    torch.cuda.synchronize()
-    enc_ms, dec_ms = e0.elapsed_time(e_mid), e_mid.elapsed_time(e1)
-    enc_same = bool(torch.equal(plain_out[[t - 31 for t in check_t]].cpu(),
-                                torch.from_numpy(plain_kept)))
-    seg_bytes = int(cnt.sum().item()) * 12
-    del plain_out, seg
+    enc = _encoded_leg(spk, torch, ds, H, W, T, frames, plain_out,
+                       [t - 31 for t in check_t], plain_kept)
+    del plain_out
     # plain, latency-bound: re-scan the last Wn frames for one output frame
     Wn = min(4096, T)
     one = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
@@ -367,10 +424,7 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
            "plain_single_pass": {"mpx_frames_per_s": round(H * W * T / (plain_ms * 1e-3) / 1e6, 1),
                                  "ms": round(plain_ms, 3),
                                  "outputs": "every frame 31..%d" % (T - 1)},
-           "plain_encoded": {"mpx_frames_per_s": round(H * W * T / ((enc_ms + dec_ms) * 1e-3) / 1e6, 1),
-                             "segments_ms": round(enc_ms, 3), "decode_ms": round(dec_ms, 3),
-                             "segment_bytes": seg_bytes, "cap": cap,
-                             "equals_single_pass": enc_same},
+           "plain_encoded": enc,
            "plain_rescan_%d" % Wn: {"mpx_frames_per_s": round(H * W / (rs_ms * 1e-3) / 1e6, 1),
                                     "latency_ms": round(rs_ms, 4)},
            "wall_s": round(wall, 2)}
@@ -585,6 +639,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip surrogate training/evaluation and the streaming run")
     ap.add_argument("--only-surrogate", action="store_true")
+    ap.add_argument("--only-encoded", action="store_true",
+                    help="only the streaming scene's single pass and segment lists + decode")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FSR/SSR/TFI/TFP quality comparison")
     ap.add_argument("--sur-steps", type=int, default=3000)
@@ -616,9 +672,17 @@ def main():
     import paper_2412_11639_amd as spk
     import spkgen
 
-    if args.only_batched or args.only_surrogate:
+    if args.only_batched or args.only_surrogate or args.only_encoded:
         args.no_cpu_baseline = True
         out = {}
+        if args.copy_calibration:
+            a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+            b = torch.empty_like(a)
+            b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
+        if args.only_encoded:
+            out["encoded"] = run_encoded(args, spk, spkgen, torch, np)
         if args.only_batched:
             out["batched"] = run_batched(args, spk, spkgen, torch, np)[0]
         if args.only_surrogate:
