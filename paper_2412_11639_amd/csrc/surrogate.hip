@@ -986,13 +986,15 @@ struct RedArgs {
     int nseg, nblocks;
 };
 
-// dst[j] = sum over blocks of partial[blk][j] in a fixed order: 16 threads
-// per weight each add every 16th block (in block order), then the 16 sums
-// are added in a fixed tree.  A workgroup covers 16 consecutive weights of
-// one segment.
+// dst[j] = sum over blocks of partial[blk][j] in a fixed order: 4 threads
+// per weight each add every 4th block (in block order), then the 4 sums
+// are added in a fixed tree.  A workgroup covers kRedCols consecutive
+// weights of one segment, so each wave reads 256 contiguous bytes per
+// block.
+constexpr int kRedCols = 64, kRedParts = 256 / kRedCols;
 __global__ __launch_bounds__(256) void reduce_kernel(RedArgs R)
 {
-    __shared__ float red[16][17];
+    __shared__ float red[kRedParts][kRedCols + 1];
     int si = 0;
     for (int q = 1; q < R.nseg; q++)
         if ((int)blockIdx.x >= R.seg[q].blk0) si = q;
@@ -1000,17 +1002,17 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs R)
     const int np = S.np, nblocks = R.nblocks;
     const float *partial = S.partial;
     float *dst = S.dst;
-    const int jl = threadIdx.x & 15, part = threadIdx.x >> 4;
-    const int j = ((int)blockIdx.x - S.blk0) * 16 + jl;
+    const int jl = threadIdx.x % kRedCols, part = threadIdx.x / kRedCols;
+    const int j = ((int)blockIdx.x - S.blk0) * kRedCols + jl;
     float acc = 0.0f;
     // one accumulator, rows in order; the unrolled loads overlap
     if (j < np) {
 #pragma unroll 8
-        for (int k = part; k < nblocks; k += 16) acc += partial[(int64_t)k * np + j];
+        for (int k = part; k < nblocks; k += kRedParts) acc += partial[(int64_t)k * np + j];
     }
     red[part][jl] = acc;
     __syncthreads();
-    for (int s = 8; s > 0; s >>= 1) {
+    for (int s = kRedParts / 2; s > 0; s >>= 1) {
         if (part < s) red[part][jl] += red[part + s][jl];
         __syncthreads();
     }
@@ -1186,14 +1188,16 @@ void launch_wgrad(WgArgs a, float *dst, RedArgs &R, hipStream_t st)
     S.partial = a.partial;
     S.dst = dst;
     S.np = np;
-    S.blk0 = R.nseg > 1 ? R.seg[R.nseg - 2].blk0 + (R.seg[R.nseg - 2].np + 15) / 16 : 0;
+    S.blk0 = R.nseg > 1 ? R.seg[R.nseg - 2].blk0 + (R.seg[R.nseg - 2].np + kRedCols - 1) / kRedCols
+                        : 0;
     R.nblocks = nblk;
 }
 
 void launch_reduce(const RedArgs &R, hipStream_t st)
 {
     const RedSeg &L = R.seg[R.nseg - 1];
-    hipLaunchKernelGGL(reduce_kernel, dim3(L.blk0 + (L.np + 15) / 16), dim3(256), 0, st, R);
+    hipLaunchKernelGGL(reduce_kernel, dim3(L.blk0 + (L.np + kRedCols - 1) / kRedCols), dim3(256), 0,
+                       st, R);
 }
 
 // Forward through the two fused kernels; with save, the activations of
