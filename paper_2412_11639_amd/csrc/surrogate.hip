@@ -802,11 +802,12 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *
 // a[p + off(tap)][ci] is a GEMM with M = output channels, N = input
 // channels and K = pixels.  A workgroup walks 16x16-pixel tiles (grid
 // stride) and stages per tile, channel-major in LDS:
-//   gT[co][px]            the tile's gradients (K contiguous for A);
-//   aT[dx][ci][row][col]  the 18x18 activation halo, once per horizontal
-//                         tap offset dx, so that every B fragment (8
-//                         consecutive pixels of one channel) is an aligned
-//                         16-byte LDS read.
+//   gT[co][px]              the tile's gradients (K contiguous for A);
+//   aT[dx][ci][row*16+col]  the 18x18 activation halo, once per horizontal
+//                           tap offset dx, so that every B fragment (8
+//                           consecutive pixels of one channel) is an
+//                           aligned 16-byte LDS read.
+// Both pad each channel row by 16 bytes against bank conflicts.
 // Wave w owns output-channel block w>>1 and input-channel block w&1 for all
 // 9 taps (accumulators stay in registers across tiles).  Layer 1 adds a
 // third input block whose column 0 is the estimate channel; layer 4 (one
@@ -843,8 +844,11 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
     using S = WgShape<K>;
     constexpr int CO = S::cout;                   // staged gradient channels
     constexpr int NE = K == WG_FIRST ? 1 : 0;     // estimate channel planes
-    __shared__ __attribute__((aligned(16))) __bf16 gT[CO][256];
-    __shared__ __attribute__((aligned(16))) __bf16 aT[3][32 + NE][18][16];
+    // rows padded by 16 bytes: the 16 lanes of one fragment read sit on
+    // distinct banks (unpadded, the 512- and 576-byte strides put every
+    // fourth lane, or all of them, on the same banks)
+    __shared__ __attribute__((aligned(16))) __bf16 gT[CO][256 + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 aT[3][32 + NE][18 * 16 + 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, gq = lane >> 4;
     // this wave's blocks
@@ -881,6 +885,43 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
         }
         // activation halo, rows ty0-1 .. ty0+16, columns tx0-1 .. tx0+16,
         // written once per horizontal tap offset
+        if constexpr (K != WG_FIRST) {
+            // item (dx, part, r, seg): 8 pixels x 8 channels, loaded as 8
+            // channel vectors, transposed in registers and written as 8
+            // channel rows of 16 bytes (pixels cc0 .. cc0 + 7 of copy dx)
+            for (int it = tid; it < 3 * 4 * 18 * 2; it += 256) {
+                const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
+                const int part = rest & 3, dx = rest >> 2, cc0 = 8 * seg;
+                const int y = ty0 - 1 + r;
+                uint32_t m[8][4];  // pixel j: channels part*8 .. +7 in pairs
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const int x = tx0 - 1 + cc0 + dx + j;
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc)
+                        v = *(const uint4 *)(A.a + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
+                                             part * 8);
+                    m[j][0] = v.x;
+                    m[j][1] = v.y;
+                    m[j][2] = v.z;
+                    m[j][3] = v.w;
+                }
+#pragma unroll
+                for (int e2 = 0; e2 < 4; e2++) {
+                    uint4 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 7
+                    lo.x = (m[0][e2] & 0xFFFFu) | (m[1][e2] << 16);
+                    lo.y = (m[2][e2] & 0xFFFFu) | (m[3][e2] << 16);
+                    lo.z = (m[4][e2] & 0xFFFFu) | (m[5][e2] << 16);
+                    lo.w = (m[6][e2] & 0xFFFFu) | (m[7][e2] << 16);
+                    hi.x = (m[0][e2] >> 16) | (m[1][e2] & 0xFFFF0000u);
+                    hi.y = (m[2][e2] >> 16) | (m[3][e2] & 0xFFFF0000u);
+                    hi.z = (m[4][e2] >> 16) | (m[5][e2] & 0xFFFF0000u);
+                    hi.w = (m[6][e2] >> 16) | (m[7][e2] & 0xFFFF0000u);
+                    *(uint4 *)(&aT[dx][part * 8 + 2 * e2][r * 16 + cc0]) = lo;
+                    *(uint4 *)(&aT[dx][part * 8 + 2 * e2 + 1][r * 16 + cc0]) = hi;
+                }
+            }
+        } else
         for (int it = tid; it < 18 * 18 * (4 + NE); it += 256) {
             const int q = it / (4 + NE), part = it % (4 + NE);
             const int r = q / 18, c = q % 18;
@@ -900,14 +941,14 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
                     const int cc = c - dx;
                     if (cc >= 0 && cc < 16)
 #pragma unroll
-                        for (int e = 0; e < 8; e++) aT[dx][part * 8 + e][r][cc] = v[e];
+                        for (int e = 0; e < 8; e++) aT[dx][part * 8 + e][r * 16 + cc] = v[e];
                 }
             } else if constexpr (NE) {
                 const __bf16 v = in ? to_bf16(A.est[pix]) : (__bf16)0.0f;
 #pragma unroll
                 for (int dx = 0; dx < 3; dx++) {
                     const int cc = c - dx;
-                    if (cc >= 0 && cc < 16) aT[dx][32][r][cc] = v;
+                    if (cc >= 0 && cc < 16) aT[dx][32][r * 16 + cc] = v;
                 }
             }
         }
@@ -932,7 +973,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
             for (int s = 0; s < 8; s++) {
                 // pixels 32s + 8gq .. +7: tile row 2s + gq/2, columns 8(gq&1) ..
                 const int row = 2 * s + (gq >> 1) + dy, col = 8 * (gq & 1);
-                const bf16x8 Bf = *(const bf16x8 *)(&aT[dx][jb * 16 + i][row][col]);
+                const bf16x8 Bf = *(const bf16x8 *)(&aT[dx][jb * 16 + i][row * 16 + col]);
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[s], Bf, acc[t], 0, 0, 0);
                 if constexpr (NE) {
                     if (jb == 0) {
@@ -940,7 +981,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
                         bf16x8 Be;
 #pragma unroll
                         for (int e = 0; e < 8; e++) Be[e] = (__bf16)0.0f;
-                        if (i == 0) Be = *(const bf16x8 *)(&aT[dx][32][row][col]);
+                        if (i == 0) Be = *(const bf16x8 *)(&aT[dx][32][row * 16 + col]);
                         acce[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[s], Be, acce[t], 0, 0, 0);
                     }
                 }
