@@ -495,6 +495,9 @@ def run_accuracy(spk, spkgen, torch, np):
                         "against the generator's true intensity", "psnr_db": res}
 
 
+CPU_RUNS = 9  # timed oracle runs for the cpu_baseline figure (about 10 s on 16 threads)
+
+
 def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
     """Every use of the oracle in this benchmark.  Times the oracle on a
     sample of the plain workload (the cpu_baseline figure) and checks the
@@ -509,14 +512,14 @@ def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
     sub = s if rows == H else spkgen.pack(spkgen.unpack(s, H, W)[:, :rows, :])
     oracle.reconstruct(sub[:256], rows, W, 256, 1.0, [0], order=order, nthreads=n)  # warm
     runs = []
-    for _ in range(3):
+    for _ in range(CPU_RUNS):
         t0 = time.perf_counter()
         ref = oracle.reconstruct(sub, rows, W, T, 1.0, t_out, order=order, nthreads=n)
         runs.append(time.perf_counter() - t0)
     dt = float(np.median(runs))
     ok = bool(np.array_equal(gpu_out[:, :rows, :], ref.astype(np.float32)))
     del ref
-    r1 = min(4, rows)
+    r1 = min(16, rows)
     sub1 = spkgen.pack(spkgen.unpack(s, H, W)[:, :r1, :])
     t0 = time.perf_counter()
     oracle.reconstruct(sub1, r1, W, T, 1.0, t_out, order=order, nthreads=1)
@@ -524,9 +527,9 @@ def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
     res["cpu_baseline"] = {
         "value": round(rows * W * T / dt / 1e6, 1), "unit": "Mpixel-frames/s", "cores": n,
         "kind": "oracle",
-        "sample": "%d of %d rows, all %d frames and %d outputs (%s); median of 3 runs "
+        "sample": "%d of %d rows, all %d frames and %d outputs (%s); median of %d runs "
                   "(%.2f s each) after a warm-up; GPU output on the same rows bit-exact: %s"
-                  % (rows, H, T, len(t_out), "SSR" if order == 2 else "FSR", dt, ok),
+                  % (rows, H, T, len(t_out), "SSR" if order == 2 else "FSR", CPU_RUNS, dt, ok),
         "single_thread_value": round(r1 * W * T / dt1 / 1e6, 2)}
     failures = [] if ok else ["plain"]
     if batched is not None:
