@@ -440,6 +440,29 @@ def test_decode_every_frame_short_segments(spk, order_name):
                                       ref_all.reshape(T, -1)[t_out])
 
 
+def test_decode_with_no_stored_segments(spk):
+    """Lists taken with cap 0 (no records at all): a pixel that has segments
+    decodes to NaN at every requested frame, one with fewer than two spikes
+    to 0, as the oracle gives for it."""
+    H, W, T = 9, 37, 600
+    bits = spkgen.unpack(spkgen.gratings(H, W, T, seed=21), H, W).reshape(T, H * W).copy()
+    bits[:, :5] = 0                    # dark pixels
+    bits[:, 5:8] = 0
+    bits[T // 2, 5:8] = 1              # one spike each
+    s = spkgen.pack(bits)
+    ds = dev(s)
+    t_out = list(range(0, T, 7)) + [T - 1, 3]
+    for order in (spk.FSR, spk.SSR, spk.TSR):
+        sf, sl, sn, cnt = spk.segments(ds, H, W, T, order=order, cap=0)
+        got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out).cpu().numpy().reshape(len(t_out), -1)
+        c = cnt.cpu().numpy().reshape(-1)
+        assert (c[:8] == 0).all() and (c[8:] > 0).all()
+        assert (got[:, :8] == 0).all()
+        assert np.isnan(got[:, 8:]).all()
+        ref = oracle.reconstruct(s, H, W, T, 1.0, t_out, order=order).reshape(len(t_out), -1)
+        assert (ref[:, :8] == 0).all()
+
+
 # --------------------------------------------------------------------------
 # the third order (n-order rule one step past SSR)
 
