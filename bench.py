@@ -303,6 +303,41 @@ def _encoded_leg(spk, torch, ds, H, W, T, frames, out, ref_idx, ref_kept):
                                 "algorithmic_bytes": dec_bytes}}
 
 
+def run_forward(args, spk, spkgen, torch, np):
+    """The surrogate forward alone at 1000x1000: the window and estimate of
+    the streaming scene after 64 frames, 50 timed inferences (random-init
+    weights, seed 0: the cost does not depend on them)."""
+    import paper_2412_11639_amd.surrogate as sur
+    H = W = 1000
+    s, _, _, _ = _streaming_scene(spkgen, np, H, W, 64)
+    ds = torch.from_numpy(s).cuda()
+    win = torch.zeros((1, H, W), dtype=torch.int32, device="cuda")
+    est = torch.zeros((1, H, W), dtype=torch.float32, device="cuda")
+    st = torch.zeros((1, H, W), dtype=torch.uint8, device="cuda")
+    for t in range(64):
+        sur.Surrogate.stream_step(ds[t], H, W, 1.0, win, est, st)
+    model = sur.Surrogate(seed=0)
+    y = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        model.infer(win, est, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        model.infer(win, est, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 50
+    return {"workload": "surrogate forward 1000x1000 (window and estimate of the streaming "
+                        "scene after 64 frames)",
+            "ms": round(ms, 4),
+            "mfma_frac": round(SUR_FLOP_PER_PX * H * W / (ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
+                               4),
+            "algorithmic_bytes_per_layer": {
+                "first": H * W * (4 + 4) + H * W * 64, "hidden": 2 * H * W * 64,
+                "output": H * W * (64 + 4 + 4)}}
+
+
 def run_encoded(args, spk, spkgen, torch, np):
     """The streaming scene's plain single pass (every frame from 31 on)
     and the same through segment lists + decode, nothing else."""
@@ -642,6 +677,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip surrogate training/evaluation and the streaming run")
     ap.add_argument("--only-surrogate", action="store_true")
+    ap.add_argument("--only-forward", action="store_true",
+                    help="only the surrogate forward at 1000x1000")
     ap.add_argument("--only-encoded", action="store_true",
                     help="only the streaming scene's single pass and segment lists + decode")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -675,7 +712,7 @@ def main():
     import paper_2412_11639_amd as spk
     import spkgen
 
-    if args.only_batched or args.only_surrogate or args.only_encoded:
+    if args.only_batched or args.only_surrogate or args.only_encoded or args.only_forward:
         args.no_cpu_baseline = True
         out = {}
         if args.copy_calibration:
@@ -686,6 +723,8 @@ def main():
             del a, b
         if args.only_encoded:
             out["encoded"] = run_encoded(args, spk, spkgen, torch, np)
+        if args.only_forward:
+            out["forward"] = run_forward(args, spk, spkgen, torch, np)
         if args.only_batched:
             out["batched"] = run_batched(args, spk, spkgen, torch, np)[0]
         if args.only_surrogate:
