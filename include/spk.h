@@ -277,6 +277,17 @@ int spk_sur_forward(const float *params, const uint32_t *win, const float *est, 
 int spk_sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
                   int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream);
 
+/* As spk_sur_infer without re-packing the weights: the convolutions take
+ * them in the MFMA operand layout that the last spk_sur_forward or
+ * spk_sur_infer call on this workspace left at its start (it must have had
+ * the same params; the packed block does not depend on B, Hc, Wc, so a
+ * workspace sized for the largest batch serves them all).  params is
+ * still read for the biases.  For serving loops that run one model on
+ * every frame; y is identical to spk_sur_infer's. */
+int spk_sur_infer_prepacked(const float *params, const uint32_t *win, const float *est,
+                            int32_t B, int32_t Hc, int32_t Wc, float *y, void *workspace,
+                            void *hip_stream);
+
 /* Gradient of the mean squared error between y and target over all B*Hc*Wc
  * pixels with respect to the parameters (grad: float32 [SPK_SUR_NPARAMS],
  * overwritten).  loss_partial (may be NULL): ceil(B*Hc*Wc / 256) partial

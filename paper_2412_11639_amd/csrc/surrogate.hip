@@ -1244,10 +1244,12 @@ void launch_reduce(const RedArgs &R, hipStream_t st)
 // Forward through the two fused kernels; with save, the activations of
 // layers 1 and 3 are kept for the backward pass (layer 2's always are).
 void forward_fused(const float *params, const uint32_t *win, const float *est, int B, int Hc,
-                   int Wc, float *y, const Workspace &w, bool save, hipStream_t st)
+                   int Wc, float *y, const Workspace &w, bool save, hipStream_t st,
+                   bool pack = true)
 {
-    hipLaunchKernelGGL(pack_kernel, dim3((PACK_TOTAL + 255) / 256), dim3(256), 0, st, params,
-                       w.packed);
+    if (pack)
+        hipLaunchKernelGGL(pack_kernel, dim3((PACK_TOTAL + 255) / 256), dim3(256), 0, st,
+                           params, w.packed);
     const ConvArgs c = conv_args(B, Hc, Wc);
     FusedArgs f{};
     f.B = B;
@@ -1278,11 +1280,13 @@ void forward_fused(const float *params, const uint32_t *win, const float *est, i
 }
 
 // Layer by layer (SPK_OPT_SUR_FUSED = 0).
+// (pack = false: the packed weights are already in the workspace)
 void forward_all(const float *params, const uint32_t *win, const float *est, int B, int Hc,
-                 int Wc, float *y, const Workspace &w, hipStream_t st)
+                 int Wc, float *y, const Workspace &w, hipStream_t st, bool pack = true)
 {
-    hipLaunchKernelGGL(pack_kernel, dim3((PACK_TOTAL + 255) / 256), dim3(256), 0, st, params,
-                       w.packed);
+    if (pack)
+        hipLaunchKernelGGL(pack_kernel, dim3((PACK_TOTAL + 255) / 256), dim3(256), 0, st,
+                           params, w.packed);
     ConvArgs a = conv_args(B, Hc, Wc);
     a.win = win;
     a.scalar = est;
@@ -1466,16 +1470,30 @@ int spk_sur_forward(const float *params, const uint32_t *win, const float *est, 
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
 }
 
-int spk_sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
-                  int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream)
+static int sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
+                     int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream,
+                     bool pack)
 {
     if (!params || !win || !est || !y || !workspace || check_batch(B, Hc, Wc)) return SPK_EINVAL;
     const Workspace w = carve(workspace, B, Hc, Wc);
     if (spk::g_sur_fused)
-        forward_fused(params, win, est, B, Hc, Wc, y, w, false, (hipStream_t)hip_stream);
+        forward_fused(params, win, est, B, Hc, Wc, y, w, false, (hipStream_t)hip_stream, pack);
     else
-        forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream);
+        forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream, pack);
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+int spk_sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
+                  int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream)
+{
+    return sur_infer(params, win, est, B, Hc, Wc, y, workspace, hip_stream, true);
+}
+
+int spk_sur_infer_prepacked(const float *params, const uint32_t *win, const float *est,
+                            int32_t B, int32_t Hc, int32_t Wc, float *y, void *workspace,
+                            void *hip_stream)
+{
+    return sur_infer(params, win, est, B, Hc, Wc, y, workspace, hip_stream, false);
 }
 
 int spk_sur_backward(const float *params, const uint32_t *win, const float *est, int32_t B,

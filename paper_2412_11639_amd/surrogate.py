@@ -40,6 +40,7 @@ _lib.EXTRA_DECLS.update({
     "spk_sur_stream_step": [_P, _i32, _i32, ctypes.c_float, _P, _P, _P, _P],
     "spk_sur_forward": [_P, _P, _P, _i32, _i32, _i32, _P, _P, _P],
     "spk_sur_infer": [_P, _P, _P, _i32, _i32, _i32, _P, _P, _P],
+    "spk_sur_infer_prepacked": [_P, _P, _P, _i32, _i32, _i32, _P, _P, _P],
     "spk_sur_backward": [_P, _P, _P, _i32, _i32, _i32, _P, _P, _P, _P, _P, _P],
     "spk_sur_adam": [_P, _P, _P, _P, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                      ctypes.c_float, _P],
@@ -150,16 +151,20 @@ class Surrogate:
         _lib.check("spk_sur_forward", rc)
         return y
 
-    def infer(self, win, est, out=None, stream=None):
-        """Forward for inference only (no activations kept for backward)."""
+    def infer(self, win, est, out=None, stream=None, prepacked=False):
+        """Forward for inference only (no activations kept for backward).
+        prepacked: reuse the packed weights the last infer or forward of this
+        batch shape left in its workspace (spk_sur_infer_prepacked); the
+        parameters must not have changed since."""
         B, Hc, Wc = win.shape
         y = out if out is not None else torch.empty((B, Hc, Wc), dtype=torch.float32,
                                                     device=win.device)
-        rc = _lib_sur().spk_sur_infer(self.params.data_ptr(), win.data_ptr(), est.data_ptr(),
-                                      B, Hc, Wc, y.data_ptr(),
-                                      self.workspace(B, Hc, Wc).data_ptr(),
-                                      _stream_handle(stream))
-        _lib.check("spk_sur_infer", rc)
+        name = "spk_sur_infer_prepacked" if prepacked else "spk_sur_infer"
+        rc = getattr(_lib_sur(), name)(self.params.data_ptr(), win.data_ptr(), est.data_ptr(),
+                                       B, Hc, Wc, y.data_ptr(),
+                                       self.workspace(B, Hc, Wc).data_ptr(),
+                                       _stream_handle(stream))
+        _lib.check(name, rc)
         return y
 
     def backward(self, win, est, y, target, stream=None):

@@ -216,3 +216,17 @@ def test_sur_train_plan_rejects_bad_arguments():
     assert create([good, sur.SurSample(0x2000, 250, 400, 4096, 0, 0, 30, 0x3000)]) == -1
     assert lib.spk_sur_train_run(None, 1, None) == -1
     assert lib.spk_sur_train_destroy(None) == 0
+
+
+def test_sur_infer_prepacked_rejects_bad_arguments():
+    """The pre-packed inference validates its arguments on the host like
+    spk_sur_infer (no device access before that)."""
+    import paper_2412_11639_amd.surrogate as sur
+    lib = sur._lib_sur()
+    p = ctypes.c_void_p(0x1000)   # never dereferenced: rejected before use
+    for f in (lib.spk_sur_infer, lib.spk_sur_infer_prepacked):
+        assert f(None, p, p, 1, 8, 8, p, p, None) == -1
+        assert f(p, None, p, 1, 8, 8, p, p, None) == -1
+        assert f(p, p, p, 1, 8, 8, p, None, None) == -1
+        assert f(p, p, p, 0, 8, 8, p, p, None) == -1
+        assert f(p, p, p, 1, 0, 8, p, p, None) == -1

@@ -201,6 +201,28 @@ def test_fused_forward_equals_layer_by_layer(sur, shape):
     assert torch.equal(res[False][2], res[False][0])
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_prepacked_inference_equals_infer(sur, fused):
+    """spk_sur_infer_prepacked on new inputs, with the weights an earlier
+    inference packed into the workspace, equals a full inference bit for bit
+    (layer by layer and through the two-layer kernels)."""
+    import paper_2412_11639_amd as spk
+    rng = np.random.default_rng(12)
+    B, Hc, Wc = 2, 19, 37
+    model = sur.Surrogate(sur.init_params(7) + rng.normal(0, 0.05, sur.NPARAMS))
+    spk.set_surrogate_fused(fused)
+    try:
+        model.infer(*_to_dev(*_rand_batch(rng, B, Hc, Wc)))
+        for _ in range(2):
+            win, est = _to_dev(*_rand_batch(rng, B, Hc, Wc))
+            got = model.infer(win, est, prepacked=True).clone()
+            ref = model.infer(win, est).clone()
+            torch.cuda.synchronize()
+            assert torch.equal(got, ref)
+    finally:
+        spk.set_surrogate_fused(False)
+
+
 @pytest.mark.parametrize("shape", [(1, 70, 45), (2, 40, 100)])
 def test_conv_block_walk_is_bit_identical(sur, shape):
     """Each convolution workgroup walks a contiguous range of 16x16 blocks,
