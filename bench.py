@@ -303,6 +303,44 @@ def _encoded_leg(spk, torch, ds, H, W, T, frames, out, ref_idx, ref_kept):
                                 "algorithmic_bytes": dec_bytes}}
 
 
+def other_paths(spk, torch, ds, H, W, T, t_out, out):
+    """The other per-pixel paths on the bench stream with the same 2000
+    outputs: the third order and TFI through the reconstruction kernel, the
+    TFP-32 baseline and the static/motion mask (SSR, 64-frame window).
+    Each: time per call (2 warm-up, 5 timed, HIP events) and its
+    algorithmic bytes against the 8 TB/s HBM peak."""
+    n_out, HW = len(t_out), H * W
+    rec = algorithmic_bytes(H, W, T, n_out)
+    legs = {
+        "third_order": (lambda: spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.TSR, out=out),
+                        rec, "T/8 B in + 4 B per pixel-output"),
+        "TFI": (lambda: spk.reconstruct(ds, H, W, T, 1.0, t_out, order=spk.TFI, out=out),
+                rec, "T/8 B in + 4 B per pixel-output"),
+        "TFP-32": (lambda: spk.tfp(ds, H, W, T, 1.0, 32, t_out, out=out),
+                   n_out * HW * (32 // 8 + 4), "32/8 B in + 4 B out per pixel-output"),
+        "motion_SSR_64": (lambda: spk.motion(ds, H, W, T, 64, t_out, order=spk.SSR),
+                          T * HW // 8 + n_out * HW, "T/8 B in + 1 B per pixel-output"),
+    }
+    res = {}
+    for name, (fn, nbytes, what) in legs.items():
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4),
+                     "mpx_frames_per_s": round(HW * T / (ms * 1e-3) / 1e6, 1),
+                     "algorithmic_bytes": nbytes, "bytes": what,
+                     "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    return res
+
+
 def run_forward(args, spk, spkgen, torch, np):
     """The surrogate forward alone at 1000x1000: the window and estimate of
     the streaming scene after 64 frames, 50 timed inferences (random-init
@@ -842,6 +880,7 @@ def main():
                         "value": round(px_frames / (ms_other * 1e-3) / 1e6, 1)},
         "wall_s_timed": round(wall, 3),
     }
+    res["other_paths"] = other_paths(spk, torch, ds, H, W, T, t_out, out)
     del ds, out
     torch.cuda.empty_cache()
     bcheck, schecks = None, None
