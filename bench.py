@@ -110,7 +110,7 @@ def traffic_from_counters(d: str):
                 continue
             for kern in ("recon_kernel", "fixup_kernel"):
                 for o, key in (("1", "FSR"), ("2", "SSR")):
-                    if kern + "<" + o in n:
+                    if kern + "<" + o + ", 0, false, 0>" in n:
                         e = out.setdefault(key, {}).setdefault(cname, {"factor": factor})
                         e[kern + "_kib"] = v
                         e["bytes"] = e.get("bytes", 0.0) + v * 1024.0 * factor
@@ -120,7 +120,7 @@ def traffic_from_counters(d: str):
             continue
         for kern in ("recon_kernel", "fixup_kernel"):
             for o, key in (("1", "FSR"), ("2", "SSR")):
-                if kern + "<" + o in n:
+                if kern + "<" + o + ", 0, false, 0>" in n:
                     e = out.setdefault(key, {})
                     e["valu_per_launch"] = e.get("valu_per_launch", 0.0) + v
     for key, d2 in out.items():
@@ -727,6 +727,8 @@ def main():
                     help="only the surrogate forward at 1000x1000")
     ap.add_argument("--only-encoded", action="store_true",
                     help="only the streaming scene's single pass and segment lists + decode")
+    ap.add_argument("--no-other-paths", action="store_true",
+                    help="skip timing the third order, TFI, TFP-32 and the motion mask")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FSR/SSR/TFI/TFP quality comparison")
     ap.add_argument("--sur-steps", type=int, default=3000)
@@ -880,7 +882,8 @@ def main():
                         "value": round(px_frames / (ms_other * 1e-3) / 1e6, 1)},
         "wall_s_timed": round(wall, 3),
     }
-    res["other_paths"] = other_paths(spk, torch, ds, H, W, T, t_out, out)
+    if not args.no_other_paths:
+        res["other_paths"] = other_paths(spk, torch, ds, H, W, T, t_out, out)
     del ds, out
     torch.cuda.empty_cache()
     bcheck, schecks = None, None

@@ -145,6 +145,12 @@ __device__ __forceinline__ bool gaps_within(uint64_t w, int a, bool plus1, int32
 
 constexpr int kFastMaxGap = 62;  // word-level shortcut for intervals up to this
 
+// mask ? a : b, bit by bit (mask all ones or all zeros)
+__device__ __forceinline__ int32_t bsel(uint32_t mask, int32_t a, int32_t b)
+{
+    return (int32_t)__builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, mask, 0xE4);
+}
+
 // Segmentation state of one pixel (registers).
 struct SegState {
     int32_t flo, fhi;  // extremes of the open FSR segment's S1 values
@@ -402,9 +408,13 @@ struct SegState {
                 const bool seen3 = l >= p3;
                 const bool dodd = d & 1;
                 const int32_t c2 = odd ? c21 : c20, b2 = odd ? b21 : b20;
-                const int32_t m = odd ? (dodd ? m3 : m2) : (dodd ? m1 : m0);
-                const int32_t hl = odd ? (dodd ? hl3 : hl2) : (dodd ? hl1 : hl0);
-                const int32_t hh = odd ? (dodd ? hh3 : hh2) : (dodd ? hh1 : hh0);
+                // bitwise selects on the values: a ?: over the members
+                // becomes a load through a selected address, which keeps
+                // the whole state in scratch memory
+                const uint32_t mo = 0u - (uint32_t)odd, md = 0u - (uint32_t)dodd;
+                const int32_t m = bsel(mo, bsel(md, m3, m2), bsel(md, m1, m0));
+                const int32_t hl = bsel(mo, bsel(md, hl3, hl2), bsel(md, hl1, hl0));
+                const int32_t hh = bsel(mo, bsel(md, hh3, hh2), bsel(md, hh1, hh0));
                 const bool mvalid = seen3 && m >= b2;
                 const int32_t e = c2 - m;
                 const int32_t nl3 = min(hl, e), nh3 = max(hh, e);
