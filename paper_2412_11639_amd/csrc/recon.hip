@@ -37,12 +37,13 @@ namespace {
 // a fresh state at its first spike (speculation), and each wave records its
 // state at its chunk's end for the fixup pass, which makes the result exact.
 template <int ORDER, int MODE, bool WIN, int PMAP>
-// Four waves per SIMD (at most 128 VGPRs) for FSR, SSR and TFI: the SSR
-// state machine alone would take 140 and run three, and the walk is bound
-// by VALU issue, which the fourth wave keeps fuller (a few bytes of the
-// per-group state go to scratch, outside the per-spike loops).  The third
-// order's larger state keeps its natural allocation.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ORDER == 4 ? 1 : 4)))
+// Four waves per SIMD (at most 128 VGPRs) for every order: the SSR state
+// machine alone would take 140 and run three, and the walk is bound by VALU
+// issue, which the fourth wave keeps fuller (a few bytes of the per-group
+// state go to scratch, outside the per-spike loops).  The third order's
+// larger state spills more (240 bytes) and still gains: 3.78 ms against
+// 4.26 at two waves (180 VGPRs, no spill) on a 250x400x20000 stream.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 void recon_kernel(ReconParams P, int nblocks, ChunkPlan cp)
 {
     __shared__ uint64_t word_s[kGroup][64];
