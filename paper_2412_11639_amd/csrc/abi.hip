@@ -9,6 +9,7 @@
 #include <numeric>
 #include <vector>
 
+#include "recon_core.h"
 #include "spk.h"
 #include "spk_internal.h"
 
@@ -270,6 +271,32 @@ namespace {
 
 // Motion mask (see spk.h): the segment holding t started at a cut less than
 // `window` frames back.
+// Each pixel's first spike frame (-1: none).  One wave per 64-pixel strip
+// takes 64 frames at a time (lane j loads frame t0 + j's 8 bytes of the
+// strip; the transpose gives each lane its pixel's 64-frame word) until
+// every pixel of the strip has spiked or the stream ends.
+__global__ __launch_bounds__(64) void first_spike_kernel(const uint8_t *stream, int64_t HW,
+                                                         size_t fb, int32_t T, int32_t nstrips,
+                                                         int32_t *first)
+{
+    const int lane = threadIdx.x;
+    const int32_t strip = spk::xcd_strip(blockIdx.x, nstrips);
+    const int64_t p0 = (int64_t)strip * 64, p = p0 + lane;
+    const uint8_t *base = stream + (p0 >> 3);
+    const spk::Xpose X(lane);
+    int32_t f = -1;
+    for (int32_t t0 = 0; t0 < T; t0 += 64) {
+        const int32_t fr = t0 + lane;
+        uint2 v = make_uint2(0u, 0u);
+        if (fr < T) v = *(const uint2 *)(base + (int64_t)fr * fb);
+        const uint64_t w = spk::transpose64(v.x, v.y, X, lane);
+        if (f < 0 && w) f = t0 + spk::ctz64(w);
+        // padding pixels past H*W never spike
+        if (__ballot(f < 0 && p < HW) == 0) break;
+    }
+    if (p < HW) first[p] = f;
+}
+
 __global__ void motion_kernel(const int32_t *win_first, const int32_t *first_spike, int64_t HW,
                               int32_t window, const int32_t *t_sorted, const int32_t *plane,
                               uint8_t *mask)
@@ -379,18 +406,13 @@ int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t o
     // (the start of its first segment)
     rc = reconstruct_impl(stream, H, W, T, 1.0f, t_out, n_out, nullptr, wf, nullptr, nullptr,
                           order, hip_stream);
-    int32_t *count = nullptr;
-    if (!rc && hipMallocAsync((void **)&count, (size_t)HW * sizeof(int32_t), st) != hipSuccess)
-        rc = SPK_ENOMEM;
+    // the first segment of a pixel with two or more spikes starts at its
+    // first spike (f < 0 in the window, fewer spikes, never reads it)
     if (!rc) {
-        int32_t *last = nullptr, *nn = nullptr;
-        if (hipMallocAsync((void **)&last, 2 * (size_t)HW * sizeof(int32_t), st) != hipSuccess) {
-            rc = SPK_ENOMEM;
-        } else {
-            nn = last + HW;
-            rc = spk_segments(stream, H, W, T, order, 1, first, last, nn, count, hip_stream);
-            hipFreeAsync(last, st);
-        }
+        const int32_t nstrips = (int32_t)((HW + 63) / 64);
+        hipLaunchKernelGGL(first_spike_kernel, dim3((unsigned)nstrips), dim3(64), 0, st, stream,
+                           HW, spk_frame_bytes(H, W), T, nstrips, first);
+        if (hipGetLastError() != hipSuccess) rc = SPK_EHIP;
     }
     if (!rc) {
         spk::OutTables tab;
@@ -401,8 +423,7 @@ int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t o
             if (hipGetLastError() != hipSuccess) rc = SPK_EHIP;
         }
     }
-    if (count) hipFreeAsync(count, st);
-    hipFreeAsync(tmp, st);
+    (void)hipFreeAsync(tmp, st);
     return rc;
 }
 
