@@ -15,7 +15,8 @@
  *   stream   device pointer to T packed binary frames, frame-major: frame t
  *            starts at byte t * spk_frame_bytes(H, W); pixel p = y * W + x
  *            is bit (p & 7) of byte (p >> 3), least significant bit first;
- *            padding bits must be zero.  Frames are 16-byte aligned.
+ *            padding bits must be zero.  Frames are 16-byte aligned, and the
+ *            stream pointer must be too (SPK_EINVAL otherwise).
  *   t_out    host pointer to n_out output frame indices, 0 <= t < T, in any
  *            order, duplicates allowed; output plane k is for t_out[k].
  *   out      device pointer, float32 [n_out][H][W].

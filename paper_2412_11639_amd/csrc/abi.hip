@@ -193,6 +193,8 @@ int requested_warm()
 int check_common(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order)
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0) return SPK_EINVAL;
+    // frames are read as 8- and 16-byte words
+    if ((uintptr_t)stream & 15u) return SPK_EINVAL;
     if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
     if (order != SPK_FSR && order != SPK_SSR && order != SPK_TFI && order != SPK_TSR)
         return SPK_EINVAL;

@@ -270,6 +270,7 @@ int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32
         if (!J.stream || !J.out || J.H <= 0 || J.W <= 0 || J.T <= 0 || J.n_out <= 0 ||
             !J.t_out || !std::isfinite(J.theta) || !(J.theta > 0.0f))
             return SPK_EINVAL;
+        if ((uintptr_t)J.stream & 15u) return SPK_EINVAL;  // frames are read as words
         if ((int64_t)J.H * J.W > (int64_t)INT32_MAX - 128) return SPK_EINVAL;
         if ((int64_t)J.n_out * J.H * J.W > ((int64_t)1 << 60)) return SPK_EINVAL;
         for (int32_t k = 0; k < J.n_out; k++)

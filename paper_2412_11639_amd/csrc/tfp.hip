@@ -44,6 +44,7 @@ extern "C" int spk_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, f
                        void *hip_stream)
 {
     if (!stream || H <= 0 || W <= 0 || T <= 0 || window < 1 || n_out < 0) return SPK_EINVAL;
+    if ((uintptr_t)stream & 15u) return SPK_EINVAL;  // frames are read as 8-byte words
     if (!std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
     if (n_out == 0) return SPK_OK;
     if (!t_out || !out) return SPK_EINVAL;

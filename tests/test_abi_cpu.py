@@ -59,7 +59,7 @@ FAKE = 4096  # a non-null pointer value; validation must fail before any use
 
 
 @pytest.mark.parametrize("args", [
-    dict(stream=0),
+    dict(stream=0), dict(stream=FAKE + 8),  # null, not 16-byte aligned
     dict(H=0), dict(W=-1), dict(T=0),
     dict(theta=0.0), dict(theta=-1.0), dict(theta=float("nan")), dict(theta=float("inf")),
     dict(n_out=-1),
@@ -85,12 +85,13 @@ def test_segments_rejects_bad_arguments(lib):
     assert lib.spk_segments(FAKE, 4, 4, 10, 1, 4, 0, FAKE, FAKE, FAKE, None) == -1
     assert lib.spk_segments(FAKE, 4, 4, 10, 1, 4, FAKE, FAKE, FAKE, 0, None) == -1
     assert lib.spk_segments(FAKE, 4, 4, 10, 5, 4, FAKE, FAKE, FAKE, FAKE, None) == -1
+    assert lib.spk_segments(FAKE + 8, 4, 4, 10, 1, 4, FAKE, FAKE, FAKE, FAKE, None) == -1
 
 
 @pytest.mark.parametrize("args", [
-    dict(stream=0), dict(H=0), dict(T=-1), dict(theta=0.0), dict(theta=float("nan")),
-    dict(window=0), dict(window=-3), dict(n_out=-1), dict(t_out=[10]), dict(t_out=[-1]),
-    dict(out=0),
+    dict(stream=0), dict(stream=FAKE + 8), dict(H=0), dict(T=-1), dict(theta=0.0),
+    dict(theta=float("nan")), dict(window=0), dict(window=-3), dict(n_out=-1),
+    dict(t_out=[10]), dict(t_out=[-1]), dict(out=0),
 ])
 def test_tfp_rejects_bad_arguments(lib, args):
     a = dict(stream=FAKE, H=4, W=4, T=10, theta=1.0, window=5, t_out=[0, 5], n_out=None,
@@ -119,7 +120,8 @@ def test_decode_rejects_bad_arguments(lib, args):
 
 
 @pytest.mark.parametrize("args", [
-    dict(stream=0), dict(H=0), dict(order=0), dict(window=0), dict(n_out=-1),
+    dict(stream=0), dict(stream=FAKE + 8), dict(H=0), dict(order=0), dict(window=0),
+    dict(n_out=-1),
     dict(t_out=[10]), dict(mask=0),
 ])
 def test_motion_rejects_bad_arguments(lib, args):
@@ -149,7 +151,7 @@ def _job(lib, **kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(stream=0), dict(out=0), dict(H=0), dict(T=-1), dict(theta=0.0),
+    dict(stream=0), dict(stream=FAKE + 8), dict(out=0), dict(H=0), dict(T=-1), dict(theta=0.0),
     dict(theta=float("nan")), dict(n_out=0), dict(t_out=[0, 1, 2, 10]),
     dict(H=65536, W=65536)])
 def test_plan_create_rejects_bad_jobs(lib, bad):
