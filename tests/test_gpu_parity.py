@@ -499,3 +499,30 @@ def test_motion_mask(spk, order):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(got.cpu().numpy(),
                                       oracle.motion(s, H, W, T, 48, t_out, order=order))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_motion_mask_first_spike_edges(spk, order):
+    # first spikes in every 64-frame chunk, in the ragged last chunk and at
+    # the last frame, pixels that never fire or fire once, over a ragged
+    # pixel count (the first-spike pass scans 64 frames per lane)
+    H, W, T = 23, 57, 1000
+    rng = np.random.default_rng(31)
+    bits = spkgen.unpack(spkgen.blocks(H, W, T, seed=26, vx=0.3, vy=0.1), H, W).reshape(T, -1)
+    bits = bits.copy()
+    start = rng.integers(0, T, size=H * W)
+    kind = rng.integers(0, 4, size=H * W)
+    start[kind == 1] = T - 1 - rng.integers(0, 8, size=int((kind == 1).sum()))
+    for p in range(H * W):
+        bits[:start[p], p] = 0
+        if kind[p] == 2:
+            bits[:, p] = 0
+        elif kind[p] == 3:
+            bits[:, p] = 0
+            bits[start[p], p] = 1
+    s = spkgen.pack(bits)
+    t_out = list(range(0, T, 7)) + [T - 1, 0]
+    got = spk.motion(dev(s), H, W, T, 40, t_out, order=order)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(),
+                                  oracle.motion(s, H, W, T, 40, t_out, order=order))
