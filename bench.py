@@ -129,6 +129,36 @@ def traffic_from_counters(d: str):
     return out
 
 
+def run_small(spk, spkgen, torch, np):
+    """The small static configuration: 250x400 blocks, 1024 frames, 8
+    outputs at 64 + 128 k.  16 MB of algorithmic bytes per call, so a call
+    is bound by launch and latency, not HBM: timed as the mean of 200 calls
+    (HIP events around the loop) for SSR and FSR."""
+    wl = spkgen.BLOCKS_250x400
+    H, W, T = wl.H, wl.W, wl.T
+    t_out = wl.times().tolist()
+    ds = torch.from_numpy(wl.generate()).cuda()
+    out = torch.empty((len(t_out), H, W), dtype=torch.float32, device="cuda")
+    res = {"workload": wl.name, "n_out": len(t_out),
+           "algorithmic_bytes": algorithmic_bytes(H, W, T, len(t_out))}
+    for name, order in (("SSR", spk.SSR), ("FSR", spk.FSR)):
+        for _ in range(10):
+            spk.reconstruct(ds, H, W, T, 1.0, t_out, order=order, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(200):
+            spk.reconstruct(ds, H, W, T, 1.0, t_out, order=order, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 200
+        gbs = res["algorithmic_bytes"] / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4), "mpx_frames_per_s": round(H * W * T / (ms * 1e-3) / 1e6, 1),
+                     "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    del ds, out
+    return res
+
+
 def run_batched(args, spk, spkgen, torch, np):
     """16 streams of uneven size, 4096 frames each, 64 outputs each, in one
     autotuned plan (persistent kernel in a HIP graph).  Returns the result
@@ -576,6 +606,17 @@ def run_accuracy(spk, spkgen, torch, np):
                         "against the generator's true intensity", "psnr_db": res}
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 CPU_RUNS = 9  # timed oracle runs for the cpu_baseline figure (about 10 s on 16 threads)
 
 
@@ -586,7 +627,9 @@ def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
     PSNR and maximum absolute error for the surrogate."""
     import oracle
     import spkgen
-    n = min(16, os.cpu_count() or 1)
+    nproc = len(os.sched_getaffinity(0))
+    # one GPU's share of the host is 16 cores: never more threads than that
+    n = min(16, nproc)
     s, H, W, T, t_out, order, gpu_out = plain
     rows = min(args.cpu_rows, H)
     print("cpu baseline: oracle on %d rows" % rows, file=sys.stderr, flush=True)
@@ -607,7 +650,7 @@ def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
     dt1 = time.perf_counter() - t0
     res["cpu_baseline"] = {
         "value": round(rows * W * T / dt / 1e6, 1), "unit": "Mpixel-frames/s", "cores": n,
-        "kind": "oracle",
+        "nproc": nproc, "cpu_model": _cpu_model(), "kind": "oracle",
         "sample": "%d of %d rows, all %d frames and %d outputs (%s); median of %d runs "
                   "(%.2f s each) after a warm-up; GPU output on the same rows bit-exact: %s"
                   % (rows, H, T, len(t_out), "SSR" if order == 2 else "FSR", CPU_RUNS, dt, ok),
@@ -884,6 +927,7 @@ def main():
     }
     if not args.no_other_paths:
         res["other_paths"] = other_paths(spk, torch, ds, H, W, T, t_out, out)
+        res["small_static"] = run_small(spk, spkgen, torch, np)
     del ds, out
     torch.cuda.empty_cache()
     bcheck, schecks = None, None

@@ -31,6 +31,10 @@
  *   Ownership: the caller owns every buffer it passes.  The library keeps a
  *            small per-device workspace (sorted output times) that lives until
  *            process exit; plans own their device tables until destroyed.
+ *            Cached output-time tables are shared by calls on any stream:
+ *            a call that reuses tables uploaded on another stream makes its
+ *            own stream wait (hipStreamWaitEvent) for that upload, so calls
+ *            on different streams never read a table before it has landed.
  *   Errors:  arguments are checked on the host before anything is enqueued;
  *            on error nothing is written and a negative code is returned.
  *            A failed launch returns SPK_EHIP; faults inside kernels surface
@@ -84,12 +88,6 @@ int spk_version(void);
  *                        (the default; the SPK_CHUNKS environment variable
  *                        overrides it at first use).  Values above the
  *                        number of 64-frame tiles are clamped.
- *   SPK_OPT_SUR_FUSED    0 (default): one kernel per surrogate layer;
- *                        1: two layers per kernel with the intermediate
- *                        layer kept in LDS.  Same results bit for bit; the
- *                        two-layer kernels hold both layers' weights in
- *                        registers and run at lower occupancy, so they are
- *                        the slower of the two on gfx950.
  *   SPK_OPT_SUR_CONV_WG  at most this many workgroups per layer-by-layer
  *                        surrogate convolution, each walking a contiguous
  *                        range of 16 x 16 pixel blocks; 0 (default): as many
@@ -97,7 +95,7 @@ int spk_version(void);
  * spk_set_option returns SPK_OK or SPK_EINVAL (unknown option, value < 0);
  * spk_get_option returns the value or SPK_EINVAL.
  */
-enum { SPK_OPT_TIME_CHUNKS = 1, SPK_OPT_SUR_FUSED = 2, SPK_OPT_SUR_CONV_WG = 3 };
+enum { SPK_OPT_TIME_CHUNKS = 1, SPK_OPT_SUR_CONV_WG = 3 };
 int spk_set_option(int option, int value);
 int spk_get_option(int option);
 
@@ -272,9 +270,8 @@ int spk_sur_stream_step(const uint8_t *frame, int32_t H, int32_t W, float theta,
 int spk_sur_forward(const float *params, const uint32_t *win, const float *est, int32_t B,
                     int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream);
 
-/* As spk_sur_forward for inference only; y is identical.  With
- * SPK_OPT_SUR_FUSED = 1 the activations the backward pass reads are not
- * written (less memory traffic); layer by layer it equals spk_sur_forward. */
+/* As spk_sur_forward for inference only; y is identical (the activations
+ * are still written to the workspace). */
 int spk_sur_infer(const float *params, const uint32_t *win, const float *est, int32_t B,
                   int32_t Hc, int32_t Wc, float *y, void *workspace, void *hip_stream);
 

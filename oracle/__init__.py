@@ -82,7 +82,8 @@ def _ptr(a, t):
 
 
 def _nthreads(n):
-    return int(n if n is not None else min(16, os.cpu_count() or 1))
+    # at most 16 threads: one GPU's share of the host's cores
+    return int(n if n is not None else min(16, len(os.sched_getaffinity(0))))
 
 
 def segment_intervals(x, order: int = FSR, lib=None) -> list:

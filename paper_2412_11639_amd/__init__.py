@@ -52,15 +52,6 @@ def get_time_chunks() -> int:
     return int(_lib.load().spk_get_option(OPT_TIME_CHUNKS))
 
 
-OPT_SUR_FUSED = 2
-
-
-def set_surrogate_fused(on: bool) -> None:
-    """Surrogate forward two layers per kernel (on) or one layer per kernel
-    (off, the default and the faster on gfx950).  Results are identical."""
-    _lib.check("spk_set_option", _lib.load().spk_set_option(OPT_SUR_FUSED, int(bool(on))))
-
-
 OPT_SUR_CONV_WG = 3
 
 

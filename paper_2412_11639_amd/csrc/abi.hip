@@ -20,7 +20,10 @@ namespace {
 // times.  Kept in a small per-device cache
 // so repeated calls with the same output times upload nothing; a slot is
 // only overwritten after the device has drained (hipDeviceSynchronize), so
-// a kernel still reading it on another stream is never disturbed.
+// a kernel still reading it on another stream is never disturbed.  The
+// upload is queued on the stream of the call that filled the slot; `ready`
+// is recorded after it, and a call on any other stream that finds the slot
+// makes its stream wait for that event before its kernels read the tables.
 struct TableSlot {
     int dev = -1;
     int32_t T = 0;
@@ -30,6 +33,9 @@ struct TableSlot {
     size_t cap = 0;            // ints allocated in both buffers
     bool identity = true;
     uint64_t stamp = 0;
+    hipEvent_t ready = nullptr;     // recorded after the upload (on slot.dev)
+    int ev_dev = -1;                // device the event belongs to
+    hipStream_t owner = nullptr;    // stream the upload was queued on
 };
 
 constexpr int kSlots = 8;
@@ -61,6 +67,10 @@ int get_tables(int dev, int32_t T, const int32_t *t_out, int32_t n_out, hipStrea
     for (auto &s : g_slots) {
         if (s.dev == dev && s.T == T && (int32_t)s.key.size() == n_out &&
             std::equal(s.key.begin(), s.key.end(), t_out)) {
+            // the upload may still be queued on another stream: order this
+            // stream's kernels after it
+            if (stream != s.owner && hipStreamWaitEvent(stream, s.ready, 0) != hipSuccess)
+                return SPK_EHIP;
             s.stamp = ++g_clock;
             *out = &s;
             return SPK_OK;
@@ -118,9 +128,29 @@ int get_tables(int dev, int32_t T, const int32_t *t_out, int32_t n_out, hipStrea
         plane[j] = order[j];
         tsort[j] = t_out[order[j]];
     }
+    if (victim->ready && victim->ev_dev != dev) {
+        int cur = dev;
+        hipSetDevice(victim->ev_dev);
+        hipEventDestroy(victim->ready);
+        hipSetDevice(cur);
+        victim->ready = nullptr;
+        victim->ev_dev = -1;
+    }
+    if (!victim->ready) {
+        if (hipEventCreateWithFlags(&victim->ready, hipEventDisableTiming) != hipSuccess) {
+            victim->ready = nullptr;
+            return SPK_EHIP;
+        }
+        victim->ev_dev = dev;
+    }
     if (hipMemcpyAsync(victim->d_buf, victim->h_buf, need * sizeof(int32_t),
-                       hipMemcpyHostToDevice, stream) != hipSuccess)
+                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipEventRecord(victim->ready, stream) != hipSuccess) {
+        victim->dev = -1;  // contents unknown: never matched again
+        victim->key.clear();
         return SPK_EHIP;
+    }
+    victim->owner = stream;
     victim->dev = dev;
     victim->T = T;
     victim->key.assign(t_out, t_out + n_out);
@@ -247,7 +277,6 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
 
 namespace spk {
 
-int g_sur_fused = 0;
 int g_sur_conv_wg = 0;
 
 int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
@@ -344,10 +373,6 @@ int spk_set_option(int option, int value)
         if (value < 0) return SPK_EINVAL;
         g_chunks = value;
         return SPK_OK;
-    case SPK_OPT_SUR_FUSED:
-        if (value != 0 && value != 1) return SPK_EINVAL;
-        spk::g_sur_fused = value;
-        return SPK_OK;
     case SPK_OPT_SUR_CONV_WG:
         if (value < 0) return SPK_EINVAL;
         spk::g_sur_conv_wg = value;
@@ -362,7 +387,6 @@ int spk_get_option(int option)
     std::lock_guard<std::mutex> lock(g_mu);
     switch (option) {
     case SPK_OPT_TIME_CHUNKS: return requested_chunks();
-    case SPK_OPT_SUR_FUSED: return spk::g_sur_fused;
     case SPK_OPT_SUR_CONV_WG: return spk::g_sur_conv_wg;
     default: return SPK_EINVAL;
     }

@@ -65,9 +65,6 @@ struct OutTables {
 int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t stream,
                OutTables *out);
 
-// SPK_OPT_SUR_FUSED: surrogate forward layer by layer (0, default) or
-// through the two-layer kernels (1).
-extern int g_sur_fused;
 // SPK_OPT_SUR_CONV_WG: workgroup cap of the surrogate convolutions (0: by
 // occupancy).
 extern int g_sur_conv_wg;

@@ -564,212 +564,6 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// forward, two layers per kernel: layer 1 + 2 (P = 0) and layer 3 + 4
-// (P = 1).  A workgroup computes a 16 x 16 block of the second layer's
-// output.  It stages the 20 x 20 input halo, runs the first layer of the
-// pair on the 18 x 18 region the second needs (bias, ReLU, bfloat16, and
-// zero outside the image -- the second layer's padding) into LDS, and runs
-// the second layer from there.  The first layer's output on the block
-// itself goes to global memory too when `save` is set (the backward pass
-// reads it).  Rounding points and MFMA step order are those of conv_kernel,
-// so the result is the same bit for bit.
-
-struct FusedArgs {
-    int B, Hc, Wc;
-    int bx, by, nblocks;
-    const uint32_t *win;     // P = 0
-    const float *est;        // P = 0: layer-1 input channel; P = 1: the residual
-    const __bf16 *act;       // P = 1: input activations (NHWC 32 ch)
-    const __bf16 *packA, *packB;
-    const float *biasA, *biasB;
-    __bf16 *save;            // first layer's output (may be NULL)
-    __bf16 *out;             // P = 0: second layer's output (NHWC 32 ch)
-    float *out_f32;          // P = 1
-};
-
-template <int P>
-__global__ __launch_bounds__(256) void fused_kernel(FusedArgs A)
-{
-    constexpr int KA = P == 0 ? CK_FIRST : CK_MID, KB = P == 0 ? CK_MID : CK_LAST;
-    using SA = ConvShape<KA>;
-    using SB = ConvShape<KB>;
-    __shared__ __attribute__((aligned(16))) __bf16 tin[20 * 20 * C];
-    __shared__ __attribute__((aligned(16))) __bf16 tmid[18 * 18 * C];
-    __shared__ float tsc[P == 0 ? 20 * 20 : 1];
-    __shared__ __attribute__((aligned(16))) __bf16 stage[4][16 * C];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i = lane & 15, g = lane >> 4;
-    bf16x8 BopA[SA::steps][SA::nb], BopB[SB::steps][SB::nb];
-#pragma unroll
-    for (int s = 0; s < SA::steps; s++)
-#pragma unroll
-        for (int n = 0; n < SA::nb; n++)
-            BopA[s][n] = *(const bf16x8 *)(A.packA + ((s * SA::nb + n) * 64 + lane) * 8);
-#pragma unroll
-    for (int s = 0; s < SB::steps; s++)
-#pragma unroll
-        for (int n = 0; n < SB::nb; n++)
-            BopB[s][n] = *(const bf16x8 *)(A.packB + ((s * SB::nb + n) * 64 + lane) * 8);
-    float biasA[2], biasB[SB::nb];
-#pragma unroll
-    for (int n = 0; n < 2; n++) biasA[n] = A.biasA[n * 16 + i];
-#pragma unroll
-    for (int n = 0; n < SB::nb; n++) biasB[n] = P == 0 ? A.biasB[n * 16 + i] : A.biasB[0];
-
-    for (int blk = blockIdx.x; blk < A.nblocks; blk += gridDim.x) {
-        const int b = blk / (A.bx * A.by);
-        const int y0 = ((blk / A.bx) % A.by) * 16, x0 = (blk % A.bx) * 16;
-        // input halo: rows y0-2 .. y0+17, columns x0-2 .. x0+17
-        for (int it = tid; it < 20 * 20 * 4; it += 256) {
-            const int q = it >> 2, part = it & 3;
-            const int y = y0 - 2 + q / 20, x = x0 - 2 + q % 20;
-            bf16x8 v;
-#pragma unroll
-            for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
-            if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc) {
-                const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                if constexpr (P == 0) v = bits_to_bf16((A.win[pix] >> (8 * part)) & 0xFFu);
-                else v = *(const bf16x8 *)(A.act + pix * C + part * 8);
-            }
-            *(bf16x8 *)(&tin[q * C + part * 8]) = v;
-        }
-        if constexpr (P == 0) {
-            for (int q = tid; q < 20 * 20; q += 256) {
-                const int y = y0 - 2 + q / 20, x = x0 - 2 + q % 20;
-                float v = 0.0f;
-                if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc)
-                    v = A.est[((int64_t)b * A.Hc + y) * A.Wc + x];
-                tsc[q] = v;
-            }
-        }
-        __syncthreads();
-        // first layer on the 18 x 18 region (rows y0-1 .., columns x0-1 ..),
-        // pixels taken 16 at a time in row-major order, one tile per wave per
-        // pass (more tiles per pass raise register use and cost occupancy)
-        constexpr int kTiles = (18 * 18 + 15) / 16, kPer = 1;
-        for (int t0 = wave * kPer; t0 < kTiles; t0 += 4 * kPer) {
-            int ry[kPer], rx[kPer];
-#pragma unroll
-            for (int u = 0; u < kPer; u++) {
-                const int q = min((t0 + u) * 16 + i, 18 * 18 - 1);  // this lane's pixel
-                ry[u] = q / 18;
-                rx[u] = q % 18;
-            }
-            f32x4 acc[kPer][2];
-#pragma unroll
-            for (int u = 0; u < kPer; u++)
-#pragma unroll
-                for (int n = 0; n < 2; n++) acc[u][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int s = 0; s < SA::steps; s++) {
-#pragma unroll
-                for (int u = 0; u < kPer; u++) {
-                    bf16x8 a;
-                    if (P == 0 && s == 9) {
-#pragma unroll
-                        for (int e = 0; e < 8; e++) {
-                            const int k = g * 8 + e;
-                            a[e] = k < 9 ? (__bf16)tsc[(ry[u] + k / 3) * 20 + rx[u] + k % 3]
-                                         : (__bf16)0.0f;
-                        }
-                    } else {
-                        a = *(const bf16x8 *)(&tin[((ry[u] + s / 3) * 20 + rx[u] + s % 3) * C +
-                                                   8 * g]);
-                    }
-#pragma unroll
-                    for (int n = 0; n < 2; n++)
-                        acc[u][n] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, BopA[s][n], acc[u][n], 0, 0, 0);
-                }
-            }
-            // lane holds D[pixel 4g + e][channel 16n + i] of each tile
-#pragma unroll
-            for (int u = 0; u < kPer; u++)
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int qq = (t0 + u) * 16 + 4 * g + e;
-                    if (t0 + u < kTiles && qq < 18 * 18) {
-                        const int y = y0 - 1 + qq / 18, x = x0 - 1 + qq % 18;
-                        const bool in = y >= 0 && y < A.Hc && x >= 0 && x < A.Wc;
-#pragma unroll
-                        for (int n = 0; n < 2; n++) {
-                            const float v = in ? fmaxf(acc[u][n][e] + biasA[n], 0.0f) : 0.0f;
-                            tmid[qq * C + 16 * n + i] = to_bf16(v);
-                        }
-                    }
-                }
-        }
-        __syncthreads();
-        // second layer on the block, wave w on rows 4w .. 4w+3 (all four
-        // rows per step: eight independent accumulators)
-        f32x4 accB[4][SB::nb];
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-#pragma unroll
-            for (int n = 0; n < SB::nb; n++) accB[r][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < SB::steps; s++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const bf16x8 a = *(const bf16x8 *)(&tmid[((4 * wave + r + s / 3) * 18 + i + s % 3) *
-                                                             C + 8 * g]);
-#pragma unroll
-                for (int n = 0; n < SB::nb; n++)
-                    accB[r][n] =
-                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, BopB[s][n], accB[r][n], 0, 0, 0);
-            }
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int y = y0 + 4 * wave + r;
-            if constexpr (P == 1) {
-                // residual on the plain short-window estimate
-                if (i == 0 && y < A.Hc) {
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const int x = x0 + 4 * g + e;
-                        if (x < A.Wc) {
-                            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                            A.out_f32[pix] = A.est[pix] + (accB[r][0][e] + biasB[0]);
-                        }
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int n = 0; n < SB::nb; n++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        stage[wave][(4 * g + e) * C + 16 * n + i] =
-                            to_bf16(fmaxf(accB[r][n][e] + biasB[n], 0.0f));
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int px = lane >> 2, part = lane & 3;
-                const int x = x0 + px;
-                const bf16x8 v = *(const bf16x8 *)(&stage[wave][px * C + part * 8]);
-                if (x < A.Wc && y < A.Hc)
-                    *(bf16x8 *)(A.out + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8) = v;
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-        }
-        // the first layer's output on the block itself, for the backward pass
-        if (A.save) {
-            for (int it = tid; it < 16 * 16 * 4; it += 256) {
-                const int q = it >> 2, part = it & 3;
-                const int y = y0 + q / 16, x = x0 + q % 16;
-                if (y < A.Hc && x < A.Wc) {
-                    const int qq = (q / 16 + 1) * 18 + q % 16 + 1;
-                    *(bf16x8 *)(A.save + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8) =
-                        *(const bf16x8 *)(&tmid[qq * C + part * 8]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // loss: dL/dy = 2 (y - target) / N, rounded to bfloat16 like every gradient
 // the GEMMs consume; per-block partial sums of the squared error
 
@@ -1241,46 +1035,8 @@ void launch_reduce(const RedArgs &R, hipStream_t st)
                        st, R);
 }
 
-// Forward through the two fused kernels; with save, the activations of
-// layers 1 and 3 are kept for the backward pass (layer 2's always are).
-void forward_fused(const float *params, const uint32_t *win, const float *est, int B, int Hc,
-                   int Wc, float *y, const Workspace &w, bool save, hipStream_t st,
-                   bool pack = true)
-{
-    if (pack)
-        hipLaunchKernelGGL(pack_kernel, dim3((PACK_TOTAL + 255) / 256), dim3(256), 0, st,
-                           params, w.packed);
-    const ConvArgs c = conv_args(B, Hc, Wc);
-    FusedArgs f{};
-    f.B = B;
-    f.Hc = Hc;
-    f.Wc = Wc;
-    f.bx = c.bx;
-    f.by = c.by;
-    f.nblocks = c.nblocks;
-    const int blocks = c.nblocks < kConvMaxBlocks ? c.nblocks : kConvMaxBlocks;
-    f.win = win;
-    f.est = est;
-    f.packA = w.packed + pack_offset(PK_FIRST);
-    f.packB = w.packed + pack_offset(PK_MID2);
-    f.biasA = params + OFF_B1;
-    f.biasB = params + OFF_B2;
-    f.save = save ? w.a1 : nullptr;
-    f.out = w.a2;
-    hipLaunchKernelGGL(fused_kernel<0>, dim3(blocks), dim3(256), 0, st, f);
-    f.act = w.a2;
-    f.packA = w.packed + pack_offset(PK_MID3);
-    f.packB = w.packed + pack_offset(PK_LAST);
-    f.biasA = params + OFF_B3;
-    f.biasB = params + OFF_B4;
-    f.save = save ? w.a3 : nullptr;
-    f.out = nullptr;
-    f.out_f32 = y;
-    hipLaunchKernelGGL(fused_kernel<1>, dim3(blocks), dim3(256), 0, st, f);
-}
-
-// Layer by layer (SPK_OPT_SUR_FUSED = 0).
-// (pack = false: the packed weights are already in the workspace)
+// Layer by layer (pack = false: the packed weights are already in the
+// workspace).
 void forward_all(const float *params, const uint32_t *win, const float *est, int B, int Hc,
                  int Wc, float *y, const Workspace &w, hipStream_t st, bool pack = true)
 {
@@ -1317,10 +1073,7 @@ void forward_all(const float *params, const uint32_t *win, const float *est, int
 void forward_train(const float *params, const uint32_t *win, const float *est, int B, int Hc,
                    int Wc, float *y, const Workspace &w, hipStream_t st)
 {
-    if (spk::g_sur_fused)
-        forward_fused(params, win, est, B, Hc, Wc, y, w, true, st);
-    else
-        forward_all(params, win, est, B, Hc, Wc, y, w, st);
+    forward_all(params, win, est, B, Hc, Wc, y, w, st);
 }
 
 // MSE gradient: loss (dL/dy and the loss partial sums, into a per-step row
@@ -1430,6 +1183,8 @@ static bool sample_ok(const spk_sur_sample &S, int32_t Hc, int32_t Wc, bool need
         S.ox < 0 || S.oy + Hc > S.H || S.ox + Wc > S.W)
         return false;
     if ((int64_t)S.H * S.W > (int64_t)INT32_MAX - 128) return false;
+    // frames are read as 8-byte words from 16-byte aligned rows
+    if ((uintptr_t)S.stream & 15u) return false;
     return !need_target || S.target;
 }
 
@@ -1476,10 +1231,7 @@ static int sur_infer(const float *params, const uint32_t *win, const float *est,
 {
     if (!params || !win || !est || !y || !workspace || check_batch(B, Hc, Wc)) return SPK_EINVAL;
     const Workspace w = carve(workspace, B, Hc, Wc);
-    if (spk::g_sur_fused)
-        forward_fused(params, win, est, B, Hc, Wc, y, w, false, (hipStream_t)hip_stream, pack);
-    else
-        forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream, pack);
+    forward_all(params, win, est, B, Hc, Wc, y, w, (hipStream_t)hip_stream, pack);
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
 }
 

@@ -181,8 +181,9 @@ def test_options(lib):
     assert lib.spk_set_option(99, 1) == -1
     assert lib.spk_set_option(1, -1) == -1
     assert lib.spk_get_option(99) == -1
-    # surrogate options: two-layer kernels on/off, convolution workgroup cap
-    assert lib.spk_set_option(2, 2) == -1
+    # option 2 (a former two-layer surrogate kernel switch) no longer exists;
+    # surrogate convolution workgroup cap
+    assert lib.spk_set_option(2, 0) == -1 and lib.spk_get_option(2) == -1
     assert lib.spk_set_option(3, -1) == -1
     assert lib.spk_set_option(3, 5) == 0 and lib.spk_get_option(3) == 5
     assert lib.spk_set_option(3, 0) == 0 and lib.spk_get_option(3) == 0
@@ -216,6 +217,8 @@ def test_sur_train_plan_rejects_bad_arguments():
     assert create([good, sur.SurSample(0x2000, 250, 400, 4096, 0, 0, 100, None)]) == -1
     assert create([good, sur.SurSample(0x2000, 250, 400, 4096, 200, 0, 100, 0x3000)]) == -1
     assert create([good, sur.SurSample(0x2000, 250, 400, 4096, 0, 0, 30, 0x3000)]) == -1
+    # stream not 16-byte aligned (frames are read as 8-byte words of 16-byte rows)
+    assert create([good, sur.SurSample(0x2008, 250, 400, 4096, 0, 0, 100, 0x3000)]) == -1
     assert lib.spk_sur_train_run(None, 1, None) == -1
     assert lib.spk_sur_train_destroy(None) == 0
 
@@ -232,3 +235,15 @@ def test_sur_infer_prepacked_rejects_bad_arguments():
         assert f(p, p, p, 1, 8, 8, p, None, None) == -1
         assert f(p, p, p, 0, 8, 8, p, p, None) == -1
         assert f(p, p, p, 1, 0, 8, p, p, None) == -1
+
+
+def test_sur_input_rejects_unaligned_stream():
+    """spk_sur_input checks every crop record like the rest of the ABI: a
+    stream pointer that is not 16-byte aligned is rejected before any
+    launch."""
+    import paper_2412_11639_amd.surrogate as sur
+    lib = sur._lib_sur()
+    p = ctypes.c_void_p(0x1000)   # never dereferenced: rejected before use
+    for base, rc in ((0x2008, -1), (0x2004, -1), (0x2001, -1)):
+        arr = (sur.SurSample * 1)(sur.SurSample(base, 250, 400, 4096, 0, 0, 100, None))
+        assert lib.spk_sur_input(arr, 1, 8, 8, 1.0, p, p, p, None, None) == rc
