@@ -57,6 +57,16 @@ def _bind(lib):
     lib.spk_oracle_window.argtypes = [P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, P_f64,
                                       ctypes.POINTER(ctypes.c_uint8)]
+    lib.spk_oracle_stream_create.restype = ctypes.c_void_p
+    lib.spk_oracle_stream_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_int32, P_i32, ctypes.c_int32, P_f64, P_i32,
+                                             P_i32, P_i32]
+    lib.spk_oracle_stream_feed.restype = ctypes.c_int32
+    lib.spk_oracle_stream_feed.argtypes = [ctypes.c_void_p, P_u8, ctypes.c_int32]
+    lib.spk_oracle_stream_finish.restype = ctypes.c_int32
+    lib.spk_oracle_stream_finish.argtypes = [ctypes.c_void_p]
+    lib.spk_oracle_stream_destroy.restype = None
+    lib.spk_oracle_stream_destroy.argtypes = [ctypes.c_void_p]
     lib.spk_oracle_segments.restype = ctypes.c_int32
     lib.spk_oracle_segments.argtypes = [
         P_u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -178,3 +188,41 @@ def window_estimate(stream, H, W, T, theta, t, lib=None):
     if rc != 0:
         raise ValueError("spk_oracle_window: bad arguments")
     return est, st.astype(bool)
+
+
+class Stream:
+    """The method online (O-5): frames fed in pieces, a small per-pixel
+    state carried between pieces; ``finish`` writes every output still
+    waiting.  After finish, ``out`` (and with ``windows`` the first/last/n
+    arrays) hold what ``reconstruct`` gives on the whole stream."""
+
+    def __init__(self, H, W, theta, t_out, order=FSR, windows=False, lib=None):
+        self.lib = lib or load()
+        self.H, self.W = H, W
+        self.t_out = np.ascontiguousarray(t_out, dtype=np.int32)
+        n_out = len(self.t_out)
+        self.out = np.zeros((n_out, H, W), dtype=np.float64)
+        self.wf = self.wl = self.wn = None
+        if windows:
+            self.wf = np.zeros((n_out, H, W), dtype=np.int32)
+            self.wl = np.zeros((n_out, H, W), dtype=np.int32)
+            self.wn = np.zeros((n_out, H, W), dtype=np.int32)
+        self._h = self.lib.spk_oracle_stream_create(
+            H, W, float(theta), order, _ptr(self.t_out, P_i32), n_out, _ptr(self.out, P_f64),
+            _ptr(self.wf, P_i32), _ptr(self.wl, P_i32), _ptr(self.wn, P_i32))
+        if not self._h:
+            raise ValueError("spk_oracle_stream_create: bad arguments")
+
+    def feed(self, frames):
+        frames = np.ascontiguousarray(frames, dtype=np.uint8)
+        if self.lib.spk_oracle_stream_feed(self._h, _ptr(frames, P_u8), frames.shape[0]) != 0:
+            raise ValueError("spk_oracle_stream_feed: bad arguments")
+
+    def finish(self):
+        self.lib.spk_oracle_stream_finish(self._h)
+        return (self.out, self.wf, self.wl, self.wn) if self.wf is not None else self.out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self.lib.spk_oracle_stream_destroy(self._h)
+            self._h = None

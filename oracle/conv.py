@@ -155,3 +155,105 @@ def adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 def psnr(x, ref, peak=1.0):
     mse = float(np.mean((np.asarray(x, np.float64) - np.asarray(ref, np.float64)) ** 2))
     return float("inf") if mse == 0 else 10.0 * np.log10(peak * peak / mse)
+
+
+# ---------------------------------------------------------------------------
+# Layer-by-layer checks of an implementation that rounds at the same points
+#
+# A device implementation stores the same kinds of bfloat16 values as the
+# bf16=True reference (weights, input channels, activations, dL/dy and the
+# masked backpropagated gradients) but accumulates its sums in float32.
+# Given the values it stored, every stored value and every output can be
+# checked element by element against the float64 reference computed from the
+# device's own inputs to that layer:
+#   - a float32 sum of k terms lies within GAMMA(k) times the sum of the
+#     terms' magnitudes of the exact sum (the standard bound k*eps/(1 - k*eps);
+#     products of two bfloat16 values are exact in float32);
+#   - a stored bfloat16 value is the round-to-nearest-even of such a sum, so
+#     it lies between the roundings of the interval's two ends (rounding is
+#     monotone); ReLU before rounding likewise.
+# A layer whose input the device does not keep (the gradient into the third
+# activation is overwritten by the next layer's) is carried as the interval
+# of bfloat16 values it can hold.
+
+def GAMMA(k):
+    # eps = 2^-23 rather than the round-to-nearest 2^-24: the bound then also
+    # holds for an accumulator that rounds toward zero
+    e = 2.0 ** -23
+    return k * e / (1.0 - k * e)
+
+
+def _in_rounded_interval(dev, lo, hi):
+    """dev (bfloat16 values) between the roundings of [lo, hi]."""
+    return (dev >= bf16(lo)) & (dev <= bf16(hi))
+
+
+def layer_checks(params, win, est, target, dev):
+    """Checks every value the device stored or returned for one forward and
+    backward pass.  ``dev`` holds, as float64 arrays in this module's layouts:
+    a1, a2, a3 (activations, [B,H,W,32]), y ([B,H,W]), dy (dL/dy, [B,H,W]),
+    g1, g2 (gradients into a1 and a2, after the ReLU mask, [B,H,W,32]) and
+    grad (the flat parameter gradient); without dy only the forward values
+    are checked.  Returns {name: number of elements outside their bound}
+    (all zero for a correct implementation)."""
+    p = unflatten(params)
+    W = {k: bf16(p[k]) for k in ("W1", "W2", "W3", "W4")}
+    aW = {k: np.abs(v) for k, v in W.items()}
+    x0 = make_input(win, est, bf=True)
+    est = np.asarray(est, dtype=np.float64)
+    target = np.asarray(target, dtype=np.float64)
+    res = {}
+    # forward: each layer from the device's own input activation
+    ins = {"a1": x0, "a2": dev["a1"], "a3": dev["a2"]}
+    for l, name in ((1, "a1"), (2, "a2"), (3, "a3")):
+        a_in = ins[name]
+        z = conv3x3(a_in, W["W%d" % l], p["b%d" % l])
+        e = GAMMA(9 * a_in.shape[-1] + 1) * conv3x3(np.abs(a_in), aW["W%d" % l],
+                                                    np.abs(p["b%d" % l]))
+        ok = _in_rounded_interval(dev[name], np.maximum(z - e, 0.0), np.maximum(z + e, 0.0))
+        res[name] = int((~ok).sum())
+    a3 = dev["a3"]
+    y = conv3x3(a3, W["W4"], p["b4"])[..., 0] + est
+    ey = GAMMA(9 * 32 + 2) * (conv3x3(a3, aW["W4"], np.abs(p["b4"]))[..., 0] + np.abs(est))
+    res["y"] = int((np.abs(dev["y"] - y) > ey).sum())
+    if "dy" not in dev:
+        return res   # a forward pass only
+    # dL/dy from the device's output: (y - t) and the division by n round
+    n = dev["y"].size
+    h = 2.0 * (dev["y"] - target) / n
+    e = GAMMA(2) * np.abs(h)
+    res["dy"] = int((~_in_rounded_interval(dev["dy"], h - e, h + e)).sum())
+    g4 = dev["dy"][..., None]
+    # gradient into a3 (not kept by the device): the interval of its values
+    hh = conv3x3_input_grad(g4, W["W4"])
+    e = GAMMA(9) * conv3x3_input_grad(np.abs(g4), aW["W4"])
+    on3 = a3 > 0
+    g3_lo, g3_hi = bf16((hh - e) * on3), bf16((hh + e) * on3)
+    g3_mid, g3_rad = 0.5 * (g3_lo + g3_hi), 0.5 * (g3_hi - g3_lo)
+    # gradient into a2 and a1 (kept), each from the layer above
+    hh = conv3x3_input_grad(g3_mid, W["W3"])
+    e = (conv3x3_input_grad(g3_rad, aW["W3"]) +
+         GAMMA(9 * 32) * conv3x3_input_grad(np.abs(g3_mid) + g3_rad, aW["W3"]))
+    on2 = dev["a2"] > 0
+    res["g2"] = int((~_in_rounded_interval(dev["g2"], (hh - e) * on2, (hh + e) * on2)).sum())
+    hh = conv3x3_input_grad(dev["g2"], W["W2"])
+    e = GAMMA(9 * 32) * conv3x3_input_grad(np.abs(dev["g2"]), aW["W2"])
+    on1 = dev["a1"] > 0
+    res["g1"] = int((~_in_rounded_interval(dev["g1"], (hh - e) * on1, (hh + e) * on1)).sum())
+    # parameter gradients: sums over all n pixels of stored gradients times
+    # stored activations
+    ref, bnd = {}, {}
+    for l, g, g_rad, a_in in ((4, g4, 0.0, a3), (3, g3_mid, g3_rad, dev["a2"]),
+                              (2, dev["g2"], 0.0, dev["a1"]), (1, dev["g1"], 0.0, x0)):
+        ga = np.abs(g) + g_rad
+        ref["W%d" % l] = conv3x3_weight_grad(g, a_in)
+        bnd["W%d" % l] = (conv3x3_weight_grad(g_rad + 0 * g, np.abs(a_in)) +
+                          GAMMA(n) * conv3x3_weight_grad(ga, np.abs(a_in)))
+        ref["b%d" % l] = g.sum(axis=(0, 1, 2))
+        bnd["b%d" % l] = (g_rad + 0 * g).sum(axis=(0, 1, 2)) + GAMMA(n) * ga.sum(axis=(0, 1, 2))
+    gref, gbnd = flatten(ref), flatten(bnd)
+    bad = np.abs(np.asarray(dev["grad"], dtype=np.float64) - gref) > gbnd
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in SHAPES])
+    for (name, _), a, b in zip(SHAPES, offs[:-1], offs[1:]):
+        res["grad_" + name] = int(bad[a:b].sum())
+    return res

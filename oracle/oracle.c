@@ -579,3 +579,278 @@ int32_t spk_oracle_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, d
     }
     return 0;
 }
+
+/* ---- O-5: carry state -------------------------------------------------
+ * The method run online, one spike at a time, with a small per-pixel state
+ * carried from one batch of frames to the next (the FPGA design of Sec.
+ * III-C processes the live stream in 32-frame blocks as they arrive).
+ * Feeding a stream in any number of pieces and finishing gives exactly what
+ * spk_oracle_reconstruct gives on the whole stream.
+ *
+ * State of one pixel: the last spike frame and the number of spikes; the
+ * open FSR segment's S1 extremes (lo, hi); the S2 tracks of the open SSR
+ * piece (at most two interval values: value, index of its latest
+ * occurrence, extremes of its gaps) and, for the third order, the tracks of
+ * the open third-order piece; the open segment's first spike and interval
+ * count; and the first output (in time order) that waits for it.  The
+ * three stages keep the order of the whole-stream functions above: an FSR
+ * cut starts fresh SSR and third-order tracks, an SSR cut fresh SSR and
+ * third-order tracks, a third-order cut fresh third-order tracks only (SSR
+ * pieces do not see third-order cuts). */
+typedef struct {
+    int32_t lastspk, K;          /* last spike frame (-1: none), spikes so far */
+    int32_t lo, hi;              /* open FSR segment: extremes of its intervals */
+    s2_track tr[2];              /* open SSR piece: S2 tracks */
+    int32_t ntr;
+    v_track tt[2];               /* open third-order piece: tracks */
+    int32_t ntt;
+    int32_t seg_first, seg_n;    /* open segment: first spike, intervals */
+    int32_t k0;                  /* first sorted output waiting for it */
+} pixel_state;
+
+struct spk_oracle_stream {
+    int32_t H, W, order, n_out, fed;
+    double theta;
+    int32_t *t_sorted, *plane;   /* output times in time order (stable), their slots */
+    double *out;
+    int32_t *win_first, *win_last, *win_n;
+    pixel_state *px;
+};
+typedef struct spk_oracle_stream spk_oracle_stream;
+
+/* number of output times <= t */
+static int32_t outputs_upto(const spk_oracle_stream *s, int32_t t)
+{
+    int32_t lo = 0, hi = s->n_out;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) / 2;
+        if (s->t_sorted[mid] <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+static void put_window(const spk_oracle_stream *s, int64_t p, int32_t k0, int32_t k1,
+                       int32_t first, int32_t last, int32_t n)
+{
+    int64_t hw = (int64_t)s->H * s->W;
+    for (int32_t k = k0; k < k1; k++) {
+        int64_t o = (int64_t)s->plane[k] * hw + p;
+        /* O-7, Eq. 6; no interval (n = 0): 0 and the window (-1, -1, 0) */
+        double I = n > 0 ? (s->theta * (double)n) / (double)(last - first) : 0.0;
+        if (s->out) s->out[o] = I;
+        if (s->win_first) s->win_first[o] = n > 0 ? first : -1;
+        if (s->win_last) s->win_last[o] = n > 0 ? last : -1;
+        if (s->win_n) s->win_n[o] = n;
+    }
+}
+
+/* SSR stage on interval x at index m (inside the open FSR segment):
+ * returns 1 when x opens a new SSR piece (ssr_refine's rule). */
+static int ssr_step(pixel_state *q, int32_t x, int32_t m)
+{
+    for (int32_t k = 0; k < q->ntr; k++) {
+        if (q->tr[k].value != x) continue;
+        s2_track *t = &q->tr[k];
+        int32_t d = m - t->last;
+        int32_t glo = t->has_gap && t->gap_lo < d ? t->gap_lo : d;
+        int32_t ghi = t->has_gap && t->gap_hi > d ? t->gap_hi : d;
+        if (!zero_order_stable(glo, ghi)) return 1;
+        t->gap_lo = glo;
+        t->gap_hi = ghi;
+        t->has_gap = 1;
+        t->last = m;
+        return 0;
+    }
+    if (q->ntr >= 2) abort(); /* an FSR segment holds at most two values */
+    q->tr[q->ntr++] = (s2_track){x, m, 0, 0, 0};
+    return 0;
+}
+
+/* third-order stage on interval x at index m (inside the open SSR piece):
+ * returns 1 when x opens a new third-order piece (tsr_refine's rule). */
+static int tsr_step(pixel_state *q, int32_t x, int32_t m)
+{
+    for (int32_t k = 0; k < q->ntt; k++) {
+        if (q->tt[k].value != x) continue;
+        v_track *t = &q->tt[k];
+        int32_t d = m - t->last;
+        int32_t j = -1;
+        for (int32_t i = 0; i < t->nt3; i++)
+            if (t->t3[i].value == d) j = i;
+        if (j >= 0) {
+            s3_track *u = &t->t3[j];
+            int32_t g = t->n2 - u->last;
+            int32_t glo = u->has_gap && u->gap_lo < g ? u->gap_lo : g;
+            int32_t ghi = u->has_gap && u->gap_hi > g ? u->gap_hi : g;
+            if (!zero_order_stable(glo, ghi)) return 1;
+            u->gap_lo = glo;
+            u->gap_hi = ghi;
+            u->has_gap = 1;
+            u->last = t->n2;
+        } else {
+            if (t->nt3 >= 2) abort(); /* S2 of a value inside an SSR piece */
+            t->t3[t->nt3++] = (s3_track){d, t->n2, 0, 0, 0};
+        }
+        t->n2++;
+        t->last = m;
+        return 0;
+    }
+    if (q->ntt >= 2) abort();
+    v_track *t = &q->tt[q->ntt++];
+    t->value = x;
+    t->last = m;
+    t->n2 = 0;
+    t->nt3 = 0;
+    return 0;
+}
+
+static void tracks_fresh(pixel_state *q, int32_t x, int32_t m, int ssr_too)
+{
+    if (ssr_too) {
+        q->ntr = 1;
+        q->tr[0] = (s2_track){x, m, 0, 0, 0};
+    }
+    q->ntt = 1;
+    q->tt[0].value = x;
+    q->tt[0].last = m;
+    q->tt[0].n2 = 0;
+    q->tt[0].nt3 = 0;
+}
+
+/* One spike at frame f of pixel p. */
+static void online_spike(spk_oracle_stream *s, int64_t p, int32_t f)
+{
+    pixel_state *q = &s->px[p];
+    if (q->K == 0) {
+        q->lastspk = f;
+        q->K = 1;
+        return;
+    }
+    int32_t x = f - q->lastspk;  /* O-2: interval T0 ending at this spike */
+    int32_t m = q->K - 1;        /* its 0-based index in S1 */
+    int cut = 0;
+    if (m == 0) {
+        /* the first interval opens the first segment */
+        q->lo = q->hi = x;
+        q->ntr = 0;
+        tracks_fresh(q, x, m, 1);
+        q->seg_first = q->lastspk;
+        q->seg_n = 0;
+        q->k0 = 0;
+    } else if (s->order == ORACLE_TFI) {
+        cut = 1;
+    } else {
+        int32_t nlo = x < q->lo ? x : q->lo, nhi = x > q->hi ? x : q->hi;
+        if (!zero_order_stable(nlo, nhi)) {          /* O-3 */
+            cut = 1;
+            q->lo = q->hi = x;
+            tracks_fresh(q, x, m, 1);
+        } else {
+            q->lo = nlo;
+            q->hi = nhi;
+            if (s->order != ORACLE_FSR) {
+                if (ssr_step(q, x, m)) {             /* O-4 */
+                    cut = 1;
+                    tracks_fresh(q, x, m, 1);
+                } else if (s->order == ORACLE_TSR && tsr_step(q, x, m)) {
+                    cut = 1;
+                    tracks_fresh(q, x, m, 0);
+                }
+            }
+        }
+    }
+    if (cut) {
+        /* the open segment ends at the previous spike: its outputs are the
+         * waiting ones up to that spike (O-6) */
+        int32_t kc = outputs_upto(s, q->lastspk);
+        put_window(s, p, q->k0, kc, q->seg_first, q->lastspk, q->seg_n);
+        q->seg_first = q->lastspk;
+        q->seg_n = 0;
+        q->k0 = kc;
+    }
+    q->seg_n++;
+    q->lastspk = f;
+    q->K++;
+}
+
+/* Outputs go to out / win_* ([n_out][H*W], any may be NULL) as segments
+ * close; t_out in any order, times >= 0.  Returns NULL on a bad argument. */
+spk_oracle_stream *spk_oracle_stream_create(int32_t H, int32_t W, double theta, int32_t order,
+                                            const int32_t *t_out, int32_t n_out, double *out,
+                                            int32_t *win_first, int32_t *win_last,
+                                            int32_t *win_n)
+{
+    if (H <= 0 || W <= 0 || n_out < 0 || (n_out > 0 && !t_out) || !ORACLE_ORDER_OK(order))
+        return NULL;
+    for (int32_t k = 0; k < n_out; k++)
+        if (t_out[k] < 0) return NULL;
+    spk_oracle_stream *s = (spk_oracle_stream *)calloc(1, sizeof(*s));
+    if (!s) return NULL;
+    s->H = H;
+    s->W = W;
+    s->order = order;
+    s->theta = theta;
+    s->n_out = n_out;
+    s->out = out;
+    s->win_first = win_first;
+    s->win_last = win_last;
+    s->win_n = win_n;
+    size_t n1 = (size_t)(n_out > 0 ? n_out : 1);
+    s->t_sorted = (int32_t *)malloc(sizeof(int32_t) * n1);
+    s->plane = (int32_t *)malloc(sizeof(int32_t) * n1);
+    s->px = (pixel_state *)calloc((size_t)H * (size_t)W, sizeof(pixel_state));
+    if (!s->t_sorted || !s->plane || !s->px) abort();
+    /* time order, equal times in slot order (insertion sort: plain) */
+    for (int32_t k = 0; k < n_out; k++) {
+        int32_t j = k;
+        while (j > 0 && s->t_sorted[j - 1] > t_out[k]) {
+            s->t_sorted[j] = s->t_sorted[j - 1];
+            s->plane[j] = s->plane[j - 1];
+            j--;
+        }
+        s->t_sorted[j] = t_out[k];
+        s->plane[j] = k;
+    }
+    for (int64_t p = 0; p < (int64_t)H * W; p++) s->px[p].lastspk = -1;
+    return s;
+}
+
+/* The next nframes packed frames (frame-major, as spk_oracle_reconstruct
+ * reads them). */
+int32_t spk_oracle_stream_feed(spk_oracle_stream *s, const uint8_t *frames, int32_t nframes)
+{
+    if (!s || nframes < 0 || (nframes > 0 && !frames)) return -1;
+    size_t fb = frame_bytes(s->H, s->W);
+    for (int32_t j = 0; j < nframes; j++)
+        for (int64_t p = 0; p < (int64_t)s->H * s->W; p++)
+            if ((frames[(size_t)j * fb + (size_t)(p >> 3)] >> (p & 7)) & 1)
+                online_spike(s, p, s->fed + j);
+    s->fed += nframes;
+    return 0;
+}
+
+/* Every output not yet written takes the open segment (times past the last
+ * spike use the last interval, O-6), or 0 and (-1, -1, 0) for a pixel with
+ * fewer than two spikes. */
+int32_t spk_oracle_stream_finish(spk_oracle_stream *s)
+{
+    if (!s) return -1;
+    for (int64_t p = 0; p < (int64_t)s->H * s->W; p++) {
+        pixel_state *q = &s->px[p];
+        if (q->K >= 2)
+            put_window(s, p, q->k0, s->n_out, q->seg_first, q->lastspk, q->seg_n);
+        else
+            put_window(s, p, 0, s->n_out, -1, -1, 0);
+    }
+    return 0;
+}
+
+void spk_oracle_stream_destroy(spk_oracle_stream *s)
+{
+    if (!s) return;
+    free(s->t_sorted);
+    free(s->plane);
+    free(s->px);
+    free(s);
+}

@@ -42,8 +42,15 @@ MUTANTS = {
                               "int32_t f0 = t - window < 0 ? 0 : t - window;"),
     "tsr_no_reset_at_cut": ("                start[nseg++] = m;\n                ntr = 0;\n                tr[ntr].value = v;",
                             "                start[nseg++] = m;\n                tr[ntr].value = v;"),
-    "tsr_last_not_updated": ("            u->has_gap = 1;\n            u->last = t->n2;",
-                             "            u->has_gap = 1;"),
+    "tsr_last_not_updated": ("            u->has_gap = 1;\n            u->last = t->n2;\n        } else {\n            /* S2(v)",
+                             "            u->has_gap = 1;\n        } else {\n            /* S2(v)"),
+    "stream_tsr_last_not_updated": ("            u->has_gap = 1;\n            u->last = t->n2;\n        } else {\n            if (t->nt3",
+                                    "            u->has_gap = 1;\n        } else {\n            if (t->nt3"),
+    "stream_ssr_cut_keeps_tracks": ("                    cut = 1;\n                    tracks_fresh(q, x, m, 1);\n                } else if",
+                                    "                    cut = 1;\n                    tracks_fresh(q, x, m, 0);\n                } else if"),
+    "stream_close_before_last_spike": ("int32_t kc = outputs_upto(s, q->lastspk);",
+                                       "int32_t kc = outputs_upto(s, q->lastspk - 1);"),
+    "stream_forgets_frames_fed": ("online_spike(s, p, s->fed + j);", "online_spike(s, p, j);"),
     "first_segment_start": ("    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0];",
                             "    start[nseg++] = 0;\n    int32_t lo = x[0], hi = x[0] + 1;"),
 }
@@ -119,6 +126,19 @@ def _battery(lib):
     cnt = bits[91:101].sum(axis=0)
     if not np.array_equal(tp[0, 0], cnt / 10.0):
         failed.append("tfp")
+    # carry-state form: any split of a stream == the whole stream
+    H, W, T = 4, 9, 300
+    s = spkgen.gratings(H, W, T, seed=63)
+    t_out = list(range(0, T, 3))
+    for order in (oracle.FSR, oracle.SSR, oracle.TSR):
+        ref = oracle.reconstruct(s, H, W, T, 1.0, t_out, order=order, windows=True, lib=lib)
+        st = oracle.Stream(H, W, 1.0, t_out, order=order, windows=True, lib=lib)
+        for a in range(0, T, 37):
+            st.feed(s[a:a + 37])
+        got = st.finish()
+        if not all(np.array_equal(g, r) for g, r in zip(got, ref)):
+            failed.append("stream_resume")
+            break
     # causal reading == the method on each prefix
     H, W, T = 4, 9, 60
     s = spkgen.blocks(H, W, T, seed=62, block=3, vx=0.7)

@@ -148,3 +148,105 @@ def test_window_estimate_constant_rate():
     assert est[0, 1] == 0.125 and stable[0, 1]
     assert est[0, 2] == 1.0 / 32 and not stable[0, 2]
     assert est[0, 3] == 0.0 and not stable[0, 3]
+
+
+# ---------------------------------------------------------------------------
+# The layer-by-layer checks of oracle.conv.layer_checks, pinned against an
+# independent float32 implementation (torch CPU conv2d and its gradient
+# routines) that rounds to bfloat16 at the same storage points: every value
+# it stores must pass, and planted mistakes in it must fail.
+
+def _f32_network(params, win, est, target, mistake=None):
+    """float32 forward and backward with bfloat16 storage (torch CPU).
+    Returns the stored values in layer_checks' layout."""
+    F = torch.nn.functional
+    bf = lambda t: t.to(torch.bfloat16).to(torch.float32)   # round to nearest even
+    p = {k: torch.tensor(v, dtype=torch.float32) for k, v in oc.unflatten(params).items()}
+
+    def w(name):  # [Cout, 9, Cin] -> [Cout, Cin, 3, 3], bfloat16 values
+        t = bf(p[name])
+        return t.reshape(t.shape[0], 3, 3, t.shape[2]).permute(0, 3, 1, 2).contiguous()
+
+    x0 = torch.tensor(oc.make_input(win, est, bf=True), dtype=torch.float32)
+    x0 = x0.permute(0, 3, 1, 2).contiguous()
+    acts, cur = [x0], x0
+    for l in (1, 2, 3):
+        cur = bf(torch.relu(F.conv2d(cur, w("W%d" % l), p["b%d" % l], padding=1)))
+        if mistake == "act" and l == 2:
+            cur[0, 3, 2, 2] += 0.25
+        acts.append(cur)
+    y = F.conv2d(cur, w("W4"), p["b4"], padding=1)[:, 0] + torch.tensor(est, dtype=torch.float32)
+    n = y.numel()
+    dy = bf(2.0 * (y - torch.tensor(target, dtype=torch.float32)) / n)
+    g = dy[:, None]
+    grads, kept = {}, {}
+    for l in (4, 3, 2, 1):
+        a_in = acts[l - 1]
+        gw = torch.nn.grad.conv2d_weight(a_in, (g.shape[1], a_in.shape[1], 3, 3), g, padding=1)
+        grads["W%d" % l] = gw.permute(0, 2, 3, 1).reshape(g.shape[1], 9, a_in.shape[1])
+        grads["b%d" % l] = g.sum(dim=(0, 2, 3))
+        if l == 1:
+            break
+        h = torch.nn.grad.conv2d_input(a_in.shape, w("W%d" % l), g, padding=1)
+        mask = (a_in > 0).to(torch.float32)
+        if mistake == "no_mask" and l == 3:
+            mask = torch.ones_like(mask)
+        g = bf(h * mask)
+        kept[l - 1] = g
+    flat = oc.flatten({k: v.double().numpy() for k, v in grads.items()})
+    if mistake == "sign":
+        flat[oc.NPARAMS // 2] *= -1.0
+    if mistake == "tap":
+        # a transposed tap in the first layer's weight gradient
+        w1 = flat[:32 * 9 * 33].reshape(32, 9, 33)
+        w1[:, [0, 2]] = w1[:, [2, 0]]
+    nhwc = lambda t: t.permute(0, 2, 3, 1).double().numpy()
+    return {"a1": nhwc(acts[1]), "a2": nhwc(acts[2]), "a3": nhwc(acts[3]),
+            "y": y.double().numpy(), "dy": dy.double().numpy(), "g2": nhwc(kept[2]),
+            "g1": nhwc(kept[1]), "grad": flat}
+
+
+def _case(seed, B=2, H=12, W=17):
+    rng = np.random.default_rng(seed)
+    params = rand_params(rng, 0.08)
+    win = rng.integers(0, 1 << 32, size=(B, H, W), dtype=np.uint64).astype(np.uint32)
+    win &= rng.integers(0, 1 << 32, size=(B, H, W), dtype=np.uint64).astype(np.uint32)
+    est = rng.uniform(0, 1, size=(B, H, W)).astype(np.float32)
+    target = rng.uniform(0, 1, size=(B, H, W)).astype(np.float32)
+    return params, win, est, target
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_float32_implementation_passes_layer_checks(seed):
+    params, win, est, target = _case(seed)
+    dev = _f32_network(params, win, est, target)
+    res = oc.layer_checks(params, win, est, target, dev)
+    assert all(v == 0 for v in res.values()), res
+
+
+@pytest.mark.parametrize("mistake,where", [("sign", "grad_W2"), ("no_mask", "g2"),
+                                           ("tap", "grad_W1"), ("act", "a2")])
+def test_layer_checks_catch_planted_mistakes(mistake, where):
+    params, win, est, target = _case(5)
+    dev = _f32_network(params, win, est, target, mistake=mistake)
+    res = oc.layer_checks(params, win, est, target, dev)
+    assert res[where] > 0, res
+
+
+def test_layer_checks_pass_the_reference_itself():
+    """The float64 reference's own stored values pass (its sums are exact up
+    to float64 rounding, far inside every bound)."""
+    params, win, est, target = _case(7)
+    x0 = oc.make_input(win, est, bf=True)
+    p = oc.unflatten(params)
+    y, (a0, a1, a2, a3) = oc.forward(params, x0, bf=True, est=est.astype(np.float64))
+    n = y.size
+    dy = oc.bf16(2.0 * (y - target) / n)
+    g3 = oc.bf16(oc.conv3x3_input_grad(dy[..., None], oc.bf16(p["W4"])) * (a3 > 0))
+    g2 = oc.bf16(oc.conv3x3_input_grad(g3, oc.bf16(p["W3"])) * (a2 > 0))
+    g1 = oc.bf16(oc.conv3x3_input_grad(g2, oc.bf16(p["W2"])) * (a1 > 0))
+    _, grad, _ = oc.loss_and_grad(params, x0, target.astype(np.float64), bf=True,
+                                  est=est.astype(np.float64))
+    dev = {"a1": a1, "a2": a2, "a3": a3, "y": y, "dy": dy, "g2": g2, "g1": g1, "grad": grad}
+    res = oc.layer_checks(params, win, est, target, dev)
+    assert all(v == 0 for v in res.values()), res
