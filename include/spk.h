@@ -92,10 +92,23 @@ int spk_version(void);
  *                        surrogate convolution, each walking a contiguous
  *                        range of 16 x 16 pixel blocks; 0 (default): as many
  *                        as fit on the device at once.
- * spk_set_option returns SPK_OK or SPK_EINVAL (unknown option, value < 0);
- * spk_get_option returns the value or SPK_EINVAL.
+ *   SPK_OPT_PLAN_KGROUP, SPK_OPT_PLAN_WAVES_PER_WG, SPK_OPT_PLAN_WPE
+ *                        the launch shape of batched plans created without
+ *                        SPK_PLAN_AUTOTUNE (see spk_plan_shape): 64-frame
+ *                        tiles per prefetch group (4, 8, 16), waves per
+ *                        workgroup (1, 2, 4), register target variant (0:
+ *                        four waves per SIMD, 1: five); 0 = default
+ *                        (8, 1, 0).
+ * spk_set_option returns SPK_OK or SPK_EINVAL (unknown option, value out of
+ * range); spk_get_option returns the value or SPK_EINVAL.
  */
-enum { SPK_OPT_TIME_CHUNKS = 1, SPK_OPT_SUR_CONV_WG = 3 };
+enum {
+    SPK_OPT_TIME_CHUNKS = 1,
+    SPK_OPT_SUR_CONV_WG = 3,
+    SPK_OPT_PLAN_KGROUP = 4,
+    SPK_OPT_PLAN_WAVES_PER_WG = 5,
+    SPK_OPT_PLAN_WPE = 6
+};
 int spk_set_option(int option, int value);
 int spk_get_option(int option);
 
@@ -173,6 +186,47 @@ int spk_decode(const int32_t *seg_first, const int32_t *seg_last, const int32_t 
                const int32_t *t_out, int32_t n_out, float *out, void *hip_stream);
 
 /*
+ * Carry-state reconstruction of a live stream (the paper's hardware
+ * processes the camera's frames in 32-frame blocks as they arrive,
+ * Sec. III-C): frames are fed in pieces of any length, each pixel's state
+ * (last spike, the open segment with its FSR / SSR / third-order state, and
+ * the first output that waits for it) stays in device memory between
+ * pieces, and every output is written as soon as the segment holding it
+ * closes.  After spk_stream_finish the outputs equal what spk_reconstruct /
+ * spk_reconstruct_windows give on the concatenated stream (bit for bit), as
+ * long as every t_out is below the number of frames fed; an output time at
+ * or past the end takes the last segment (no later spike was seen).
+ *
+ * spk_stream_create: H, W, theta, order as spk_reconstruct; t_out (host,
+ *   any order, duplicates allowed, t >= 0) is copied; out, win_first,
+ *   win_last, win_n: device [n_out][H][W] buffers or NULL, written by the
+ *   feeds and the finish (they must stay valid until the finish has run).
+ *   Allocates the per-pixel state (at most 37 ints per pixel) on the
+ *   current device.  SPK_EINVAL, SPK_ENOMEM, SPK_EHIP, SPK_EUNSUPPORTED.
+ * spk_stream_feed: the next nframes packed frames (device, frame-major,
+ *   16-byte aligned, layout as spk_reconstruct's stream), enqueued on
+ *   hip_stream.  nframes == 0 is a no-op.  The frames must stay valid
+ *   until the call's work has run.
+ * spk_stream_finish: writes every output still waiting (the open segment
+ *   of each pixel; 0 and (-1, -1, 0) for pixels with fewer than two spikes).
+ *   No feed is accepted afterwards.
+ * spk_stream_frames: frames fed so far (or SPK_EINVAL for NULL).
+ * spk_stream_destroy: waits for the device and frees the state (NULL: no-op).
+ * All calls on one spk_stream_t must run in order: enqueue them on one HIP
+ * stream, or synchronise between them.  A stream object belongs to the
+ * device current at its creation.
+ */
+typedef struct spk_stream_s *spk_stream_t;
+int spk_stream_create(spk_stream_t *stream, int32_t H, int32_t W, float theta, int32_t order,
+                      const int32_t *t_out, int32_t n_out, float *out, int32_t *win_first,
+                      int32_t *win_last, int32_t *win_n);
+int spk_stream_feed(spk_stream_t stream, const uint8_t *frames, int32_t nframes,
+                    void *hip_stream);
+int spk_stream_finish(spk_stream_t stream, void *hip_stream);
+int spk_stream_frames(spk_stream_t stream);
+int spk_stream_destroy(spk_stream_t stream);
+
+/*
  * Batched plans: many streams of uneven size reconstructed by one
  * persistent kernel (one wave per 64-pixel strip of a stream at a time,
  * strips taken from per-XCD work counters), captured once in a HIP graph.
@@ -183,11 +237,17 @@ int spk_decode(const int32_t *seg_first, const int32_t *seg_last, const int32_t 
  *
  * spk_plan_create validates every job on the host (SPK_EINVAL on any bad
  * field, nothing allocated), uploads the job table and the sorted output
- * times, chooses the launch shape (with SPK_PLAN_AUTOTUNE: by timing a few
- * shapes on the real jobs, which writes their outputs; the choice is
- * cached per job-size signature in the process and, if the environment
- * variable SPK_TUNE_CACHE names a file, in that JSON file), captures the
- * graph (unless SPK_PLAN_NO_GRAPH) and synchronises before returning.
+ * times, chooses the launch shape, captures the graph (unless
+ * SPK_PLAN_NO_GRAPH) and synchronises before returning.  The shape is the
+ * total waves and workgroups, strips per counter grab, 64-frame tiles per
+ * prefetch group, waves per workgroup and the register target (see
+ * spk_plan_info, spk_plan_shape).  With SPK_PLAN_AUTOTUNE it is found by
+ * timing about 20 candidate shapes on the real jobs in stages (waves x
+ * grab, group size, register target, waves per workgroup, waves x grab
+ * again), which writes their outputs; the choice is cached per job-size
+ * signature in the process and, if the environment variable
+ * SPK_TUNE_CACHE names a file, in that JSON file.  Without it the shape is
+ * the default or the one set with the SPK_OPT_PLAN_* options.
  * The streams must stay valid and unchanged in place for the plan's life;
  * their contents may change between executions.
  *
@@ -213,9 +273,15 @@ enum { SPK_PLAN_AUTOTUNE = 1, SPK_PLAN_NO_GRAPH = 2 };
 int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32_t order,
                     int32_t flags);
 int spk_plan_execute(spk_plan_t plan, void *hip_stream);
-/* Launch shape and size: workgroups (one wave each), strips taken per
- * counter grab, total strips.  Any pointer may be NULL. */
+/* Launch shape and size: workgroups, strips taken per counter grab, total
+ * strips.  Any pointer may be NULL. */
 int spk_plan_info(spk_plan_t plan, int32_t *grid, int32_t *grab, int32_t *items);
+/* The rest of the launch shape: 64-frame tiles per prefetch group (4, 8 or
+ * 16), waves per workgroup (1, 2 or 4, each taking its own strips) and the
+ * waves per SIMD the kernel's registers were allocated for (4 or 5).
+ * Any pointer may be NULL. */
+int spk_plan_shape(spk_plan_t plan, int32_t *kgroup, int32_t *waves_per_wg,
+                   int32_t *waves_per_simd);
 int spk_plan_destroy(spk_plan_t plan);
 
 /*
@@ -251,6 +317,18 @@ typedef struct spk_sur_sample {
 } spk_sur_sample;
 
 size_t spk_sur_workspace_bytes(int32_t B, int32_t Hc, int32_t Wc);
+
+/* Where the workspace keeps what the network stored, for inspection (tests
+ * check every stored value against a CPU reference).  offsets receives
+ * SPK_SUR_WS_VIEWS byte offsets into a workspace for (B, Hc, Wc), in this
+ * order: the packed weights; the activations a1, a2, a3 after each ReLU
+ * (bfloat16 [B][Hc][Wc][32], written by spk_sur_forward and spk_sur_infer);
+ * after spk_sur_backward, the gradients into a1 and a2 after their ReLU
+ * masks (bfloat16 [B][Hc][Wc][32]; the gradient into a3 is not kept) and
+ * dL/dy (float32 [B][Hc][Wc], values of bfloat16).  SPK_EINVAL on a bad
+ * shape or NULL offsets. */
+#define SPK_SUR_WS_VIEWS 7
+int spk_sur_workspace_layout(int32_t B, int32_t Hc, int32_t Wc, size_t *offsets);
 
 /* Window, short-window estimate and stability flag for B <= 64 crops
  * (samples is a host array).  win[b][y][x] bit j = frame t-31+j; est = the

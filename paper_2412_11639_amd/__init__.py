@@ -52,6 +52,18 @@ def get_time_chunks() -> int:
     return int(_lib.load().spk_get_option(OPT_TIME_CHUNKS))
 
 
+OPT_PLAN_KGROUP, OPT_PLAN_WAVES_PER_WG, OPT_PLAN_WPE = 4, 5, 6
+
+
+def set_plan_shape(kgroup: int = 0, waves_per_wg: int = 0, wpe_variant: int = 0) -> None:
+    """Launch shape of plans created without autotuning (0 = default).
+    Results are identical for every shape."""
+    lib = _lib.load()
+    for opt, v in ((OPT_PLAN_KGROUP, kgroup), (OPT_PLAN_WAVES_PER_WG, waves_per_wg),
+                   (OPT_PLAN_WPE, wpe_variant)):
+        _lib.check("spk_set_option", lib.spk_set_option(opt, int(v)))
+
+
 OPT_SUR_CONV_WG = 3
 
 
@@ -180,6 +192,64 @@ def segments(stream_t, H, W, T, order=FSR, cap=64, stream=None):
     return sf, sl, sn, cnt
 
 
+class Stream:
+    """Carry-state reconstruction of a live stream (``spk_stream_*``):
+    ``feed`` device frames in pieces of any length, then ``finish``; the
+    outputs (float32 [n_out, H, W], and with ``windows`` the first / last /
+    n int32 arrays) then equal ``reconstruct`` on the whole stream.  All
+    calls go on one HIP stream (the current one unless given)."""
+
+    def __init__(self, H: int, W: int, theta: float, t_out, order: int = FSR,
+                 windows: bool = False, device="cuda"):
+        import ctypes
+        self.H, self.W = int(H), int(W)
+        self._t, tp = _host_times(t_out)
+        n_out = len(self._t)
+        self.out = torch.empty((n_out, H, W), dtype=torch.float32, device=device)
+        self.windows = None
+        if windows:
+            self.windows = tuple(torch.empty((n_out, H, W), dtype=torch.int32, device=device)
+                                 for _ in range(3))
+        wp = [w.data_ptr() for w in self.windows] if windows else [None, None, None]
+        h = ctypes.c_void_p()
+        _lib.check("spk_stream_create", _lib.load().spk_stream_create(
+            ctypes.byref(h), self.H, self.W, float(theta), order, tp, n_out,
+            self.out.data_ptr(), *wp))
+        self._h = h
+        self._frames = []   # pieces stay alive until finish
+
+    def feed(self, frames: torch.Tensor, stream=None):
+        if not isinstance(frames, torch.Tensor) or not frames.is_cuda:
+            raise TypeError("frames must be a device tensor")
+        fb = frame_bytes(self.H, self.W)
+        n = frames.shape[0] if frames.numel() else 0
+        if frames.dtype != torch.uint8 or not frames.is_contiguous() or frames.numel() != n * fb:
+            raise ValueError("frames must be contiguous uint8 [n, %d]" % fb)
+        self._frames.append(frames)
+        _lib.check("spk_stream_feed", _lib.load().spk_stream_feed(
+            self._h, frames.data_ptr() if n else None, n, _stream_handle(stream)))
+
+    def frames(self) -> int:
+        return int(_lib.load().spk_stream_frames(self._h))
+
+    def finish(self, stream=None):
+        _lib.check("spk_stream_finish", _lib.load().spk_stream_finish(self._h,
+                                                                      _stream_handle(stream)))
+        return (self.out,) + self.windows if self.windows else self.out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check("spk_stream_destroy", _lib.load().spk_stream_destroy(self._h))
+            self._h = None
+            self._frames = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """A batched reconstruction of several streams (``spk_plan_*``).
 
@@ -224,6 +294,14 @@ class Plan:
         _lib.check("spk_plan_info", _lib.load().spk_plan_info(self._h, ctypes.byref(g),
                                                               ctypes.byref(b), ctypes.byref(n)))
         return {"grid": g.value, "grab": b.value, "items": n.value}
+
+    def shape(self):
+        """Tiles per prefetch group, waves per workgroup, waves per SIMD."""
+        import ctypes
+        k, w, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check("spk_plan_shape", _lib.load().spk_plan_shape(
+            self._h, ctypes.byref(k), ctypes.byref(w), ctypes.byref(e)))
+        return {"kgroup": k.value, "waves_per_wg": w.value, "waves_per_simd": e.value}
 
     def outputs(self):
         return [j["out"] for j in self.jobs]

@@ -70,9 +70,17 @@ class SpkJob(ctypes.Structure):
 
 
 EXTRA_DECLS: dict = {
+    "spk_stream_create": [ctypes.POINTER(ctypes.c_void_p), c_i32, c_i32, ctypes.c_float, c_i32,
+                          P_i32, c_i32, P_f32, P_i32, P_i32, P_i32],
+    "spk_stream_feed": [ctypes.c_void_p, P_u8, c_i32, ctypes.c_void_p],
+    "spk_stream_finish": [ctypes.c_void_p, ctypes.c_void_p],
+    "spk_stream_frames": [ctypes.c_void_p],
+    "spk_stream_destroy": [ctypes.c_void_p],
     "spk_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SpkJob), c_i32, c_i32,
                         c_i32],
     "spk_plan_execute": [ctypes.c_void_p, ctypes.c_void_p],
+    "spk_plan_shape": [ctypes.c_void_p, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                       ctypes.POINTER(c_i32)],
     "spk_plan_info": [ctypes.c_void_p, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
                       ctypes.POINTER(c_i32)],
     "spk_plan_destroy": [ctypes.c_void_p],

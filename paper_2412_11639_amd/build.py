@@ -15,7 +15,8 @@ LIB = os.path.join(PKG, "libspk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["abi.hip", "recon.hip", "batch.hip", "tfp.hip", "decode.hip", "surrogate.hip"]
+SOURCES = ["abi.hip", "recon.hip", "batch.hip", "batch_k4.hip", "batch_k8.hip", "batch_k16.hip",
+           "tfp.hip", "decode.hip", "surrogate.hip", "stream.hip"]
 
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -377,6 +377,10 @@ int spk_set_option(int option, int value)
         if (value < 0) return SPK_EINVAL;
         spk::g_sur_conv_wg = value;
         return SPK_OK;
+    case SPK_OPT_PLAN_KGROUP:
+    case SPK_OPT_PLAN_WAVES_PER_WG:
+    case SPK_OPT_PLAN_WPE:
+        return spk::set_plan_option(option, value);
     default:
         return SPK_EINVAL;
     }
@@ -388,6 +392,9 @@ int spk_get_option(int option)
     switch (option) {
     case SPK_OPT_TIME_CHUNKS: return requested_chunks();
     case SPK_OPT_SUR_CONV_WG: return spk::g_sur_conv_wg;
+    case SPK_OPT_PLAN_KGROUP:
+    case SPK_OPT_PLAN_WAVES_PER_WG:
+    case SPK_OPT_PLAN_WPE: return spk::get_plan_option(option);
     default: return SPK_EINVAL;
     }
 }

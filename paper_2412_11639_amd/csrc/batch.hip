@@ -1,14 +1,8 @@
 // Batched reconstruction: many streams of uneven size in one persistent
-// kernel, captured once in a HIP graph, with launch shapes chosen by a
-// small autotuner.
-//
-// Work items are 64-pixel strips of every job, each walked over the job's
-// whole stream by one wave (the same per-strip walk as the plain kernel).
-// The items are split into 8 contiguous ranges, one per XCD, each with its
-// own counter: a wave first takes items from its own XCD's range (so the
-// 16 strips that share each 128-byte line of a frame stay in one L2), then
-// helps the other ranges.  Every wave leaves once all counters are past
-// their range's end; nothing waits on another wave.
+// kernel (batch_kernels.h), captured once in a HIP graph, with the launch
+// shape -- total waves, strips per counter grab, tiles per prefetch group,
+// waves per workgroup and the waves-per-SIMD register target -- chosen by a
+// small autotuner that times candidate shapes on the plan's own jobs.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -23,97 +17,14 @@
 #include "recon_core.h"
 #include "spk.h"
 
-namespace spk {
-namespace {
-
-constexpr int kXcds = 8;
-
-struct JobDesc {
-    const uint8_t *stream;
-    int64_t fb;
-    int32_t T, HW;
-    double theta;
-    const int32_t *cnt_le;
-    const int32_t *plane;  // NULL: identity
-    int32_t n_out;
-    float *out;
-    int32_t strip0;        // first item of this job
-    int32_t nstrips;
-};
-
-struct Ranges {
-    int32_t begin[kXcds + 1];  // item range of each XCD
-};
-
-__device__ __forceinline__ int find_job(const JobDesc *jobs, int n_jobs, int32_t item)
-{
-    int lo = 0, hi = n_jobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].strip0 <= item) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__global__ void reset_counters(int32_t *counters)
-{
-    if (threadIdx.x < kXcds) counters[threadIdx.x] = 0;
-}
-
-template <int ORDER, int PMAP>
-__global__ __launch_bounds__(64) void batch_kernel(const JobDesc *jobs, int n_jobs, Ranges R,
-                                                   int grab, int32_t *counters)
-{
-    __shared__ uint64_t word_s[kGroup][64];
-    __shared__ int32_t cnt_s[kGroup][64];
-    const int lane = threadIdx.x;
-    const Xpose X(lane);
-    const int home = blockIdx.x % kXcds;
-    for (int k = 0; k < kXcds; k++) {
-        const int x = (home + k) % kXcds;
-        const int32_t n = R.begin[x + 1] - R.begin[x];
-        while (true) {
-            int32_t i0 = 0;
-            if (lane == 0) i0 = atomicAdd(&counters[x], grab);
-            i0 = __shfl(i0, 0, 64);
-            if (i0 >= n) break;
-            const int32_t i1 = min(n, i0 + grab);
-            for (int32_t i = i0; i < i1; i++) {
-                const int32_t item = R.begin[x] + i;
-                const JobDesc &J = jobs[find_job(jobs, n_jobs, item)];
-                ReconParams P{};
-                P.stream = J.stream;
-                P.fb = J.fb;
-                P.T = J.T;
-                P.HW = J.HW;
-                P.theta = J.theta;
-                P.cnt_le = J.cnt_le;
-                P.plane = J.plane;
-                P.n_out = J.n_out;
-                P.out = J.out;
-                const int64_t p0 = (int64_t)(item - J.strip0) * 64;
-                const int64_t p = p0 + lane;
-                Emitter<MODE_RECON, false, PMAP> em{P, nullptr, p, p < P.HW, 0, 0};
-                Run run;
-                run.reset(0, 0);
-                int32_t cum_base = 0;
-                walk<ORDER, false>(P, em, run, P.stream + (p0 >> 3), X, lane, 0, 0,
-                                   (P.T + 63) / 64, word_s, cnt_s, nullptr, 0, cum_base);
-                if (run.cum >= 2)
-                    em.close(run.first, run.lastspk, (run.cum - 1) - run.first_idx, run.k0,
-                             P.n_out);
-                else
-                    em.empty();
-            }
-        }
-    }
-}
-
-}  // namespace
-}  // namespace spk
+#include "batch_kernels.h"
 
 using spk::JobDesc;
+
+// A launch shape (see batch_kernels.h).  grid counts workgroups.
+struct Shape {
+    int grid = 0, grab = 1, kg = 8, wpg = 1, wpe = 0;
+};
 
 struct spk_plan_s {
     int dev = -1;
@@ -121,7 +32,7 @@ struct spk_plan_s {
     int n_jobs = 0;
     int32_t total_items = 0;
     bool identity = true;
-    int grid = 0, grab = 1;
+    Shape shape;
     bool use_graph = true;
     JobDesc *d_jobs = nullptr;
     int32_t *d_tables = nullptr;
@@ -135,13 +46,29 @@ struct spk_plan_s {
 
 namespace {
 
+__global__ void reset_counters(int32_t *counters)
+{
+    if (threadIdx.x < spk::kXcds) counters[threadIdx.x] = 0;
+}
+
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;  // signature -> (grid, grab)
+std::map<std::string, Shape> g_tune;  // signature -> shape
 bool g_tune_loaded = false;
+
+// Shape set by spk_set_option for plans created without autotuning
+// (0 = the default of each field).
+int g_force_kg = 0, g_force_wpg = 0, g_force_wpe = 0;
 
 const char *tune_path() { return std::getenv("SPK_TUNE_CACHE"); }
 
-// The tuning cache is a flat JSON object {"signature": [grid, grab], ...}.
+bool shape_ok(const Shape &h)
+{
+    return h.grid > 0 && h.grab > 0 && (h.kg == 4 || h.kg == 8 || h.kg == 16) &&
+           (h.wpg == 1 || h.wpg == 2 || h.wpg == 4) && (h.wpe == 0 || h.wpe == 1);
+}
+
+// The tuning cache is a flat JSON object
+// {"signature": [grid, grab, kgroup, waves_per_wg, wpe_variant], ...}.
 void tune_load()
 {
     if (g_tune_loaded) return;
@@ -160,10 +87,11 @@ void tune_load()
         const size_t end = text.find('"', pos + 1);
         if (end == std::string::npos) break;
         const std::string key = text.substr(pos + 1, end - pos - 1);
-        int grid = 0, grab = 0;
-        if (std::sscanf(text.c_str() + end + 1, " : [ %d , %d ]", &grid, &grab) == 2 && grid > 0 &&
-            grab > 0)
-            g_tune[key] = {grid, grab};
+        Shape h;
+        if (std::sscanf(text.c_str() + end + 1, " : [ %d , %d , %d , %d , %d ]", &h.grid, &h.grab,
+                        &h.kg, &h.wpg, &h.wpe) == 5 &&
+            shape_ok(h))
+            g_tune[key] = h;
         pos = end + 1;
     }
 }
@@ -178,66 +106,113 @@ void tune_store()
     std::fprintf(f, "{\n");
     size_t i = 0;
     for (const auto &kv : g_tune)
-        std::fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.first,
-                     kv.second.second, ++i < g_tune.size() ? "," : "");
+        std::fprintf(f, "  \"%s\": [%d, %d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.grid,
+                     kv.second.grab, kv.second.kg, kv.second.wpg, kv.second.wpe,
+                     ++i < g_tune.size() ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
     std::rename(tmp.c_str(), path);
 }
 
-hipError_t launch_batch(const spk_plan_s *pl, int grid, int grab, hipStream_t st)
+hipError_t launch_batch(const spk_plan_s *pl, const Shape &h, hipStream_t st)
 {
-    hipLaunchKernelGGL(spk::reset_counters, dim3(1), dim3(64), 0, st, pl->d_counters);
-#define SPK_BATCH_LAUNCH(O)                                                                  \
-    if (pl->identity)                                                                          \
-        hipLaunchKernelGGL((spk::batch_kernel<O, spk::PMAP_IDENT>), dim3(grid), dim3(64), 0,   \
-                           st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);      \
-    else                                                                                       \
-        hipLaunchKernelGGL((spk::batch_kernel<O, spk::PMAP_GLOBAL>), dim3(grid), dim3(64), 0,  \
-                           st, pl->d_jobs, pl->n_jobs, pl->ranges, grab, pl->d_counters);
-    switch (pl->order) {
-    case SPK_FSR: SPK_BATCH_LAUNCH(1) break;
-    case SPK_SSR: SPK_BATCH_LAUNCH(2) break;
-    case SPK_TFI: SPK_BATCH_LAUNCH(3) break;
-    default: SPK_BATCH_LAUNCH(4) break;
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, pl->d_counters);
+    spk::BatchLaunch b;
+    b.jobs = pl->d_jobs;
+    b.n_jobs = pl->n_jobs;
+    b.ranges = pl->ranges;
+    b.counters = pl->d_counters;
+    b.order = pl->order;
+    b.identity = pl->identity;
+    b.grid = h.grid;
+    b.grab = h.grab;
+    b.waves_per_wg = h.wpg;
+    b.wpe_variant = h.wpe;
+    switch (h.kg) {
+    case 4: return spk::launch_batch_k4(b, st);
+    case 16: return spk::launch_batch_k16(b, st);
+    default: return spk::launch_batch_k8(b, st);
     }
-#undef SPK_BATCH_LAUNCH
-    return hipGetLastError();
 }
 
-// Time each candidate launch shape twice (the second run counts) and keep
-// the fastest.  Every shape gives the same output.
+// Time one shape: two runs, the second counts.  Every shape gives the same
+// output.
+int time_shape(spk_plan_s *pl, const Shape &h, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+               float *ms)
+{
+    for (int rep = 0; rep < 2; rep++) {
+        if (hipEventRecord(e0, st) != hipSuccess) return SPK_EHIP;
+        if (launch_batch(pl, h, st) != hipSuccess) return SPK_EHIP;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return SPK_EHIP;
+        if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return SPK_EHIP;
+    }
+    return SPK_OK;
+}
+
+// Staged search over the launch shape, each stage keeping the fastest:
+// total waves (4, 8, 16, 32 per CU) x strips per grab (1, 4) at 8 tiles
+// per group, one wave per workgroup, the order's default register target;
+// then the group size (4, 16); the other register target; waves per
+// workgroup (2, 4); and the total waves and grab once more at the shape
+// found.  About 20 timed shapes.
 int autotune(spk_plan_s *pl, hipStream_t st)
 {
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, pl->dev) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
-    const int grids[] = {cus * 4, cus * 8, cus * 16, cus * 32};
-    const int grabs[] = {1, 4};
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SPK_EHIP;
-    float best = 1e30f;
-    for (int g : grids) {
-        for (int b : grabs) {
-            float ms = 0.0f;
-            for (int rep = 0; rep < 2; rep++) {
-                hipEventRecord(e0, st);
-                if (launch_batch(pl, g, b, st) != hipSuccess) return SPK_EHIP;
-                hipEventRecord(e1, st);
-                if (hipEventSynchronize(e1) != hipSuccess) return SPK_EHIP;
-                hipEventElapsedTime(&ms, e0, e1);
-            }
-            if (ms < best) {
-                best = ms;
-                pl->grid = g;
-                pl->grab = b;
-            }
-        }
+    if (hipEventCreate(&e0) != hipSuccess) return SPK_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return SPK_EHIP;
     }
+    Shape best;
+    float best_ms = 1e30f;
+    int rc = SPK_OK;
+    auto consider = [&](Shape h) {
+        if (rc != SPK_OK) return;
+        float ms = 0.0f;
+        rc = time_shape(pl, h, st, e0, e1, &ms);
+        if (rc == SPK_OK && ms < best_ms) {
+            best_ms = ms;
+            best = h;
+        }
+    };
+    auto waves_grab = [&]() {
+        const Shape base = best;
+        for (int w : {4, 8, 16, 32})
+            for (int b : {1, 4}) {
+                Shape h = base;
+                h.grid = cus * w / h.wpg;
+                h.grab = b;
+                consider(h);
+            }
+    };
+    best.grid = cus * 16;
+    waves_grab();
+    for (int kg : {4, 16}) {
+        Shape h = best;
+        h.kg = kg;
+        consider(h);
+    }
+    {
+        Shape h = best;
+        h.wpe = 1 - h.wpe;
+        consider(h);
+    }
+    for (int wpg : {2, 4}) {
+        Shape h = best;
+        h.grid = best.grid * best.wpg / wpg;
+        h.wpg = wpg;
+        consider(h);
+    }
+    waves_grab();
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    return SPK_OK;
+    if (rc == SPK_OK) pl->shape = best;
+    return rc;
 }
 
 void plan_free(spk_plan_s *pl)
@@ -252,6 +227,42 @@ void plan_free(spk_plan_s *pl)
 }
 
 }  // namespace
+
+namespace spk {
+
+int set_plan_option(int option, int value)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    switch (option) {
+    case SPK_OPT_PLAN_KGROUP:
+        if (value != 0 && value != 4 && value != 8 && value != 16) return SPK_EINVAL;
+        g_force_kg = value;
+        return SPK_OK;
+    case SPK_OPT_PLAN_WAVES_PER_WG:
+        if (value != 0 && value != 1 && value != 2 && value != 4) return SPK_EINVAL;
+        g_force_wpg = value;
+        return SPK_OK;
+    case SPK_OPT_PLAN_WPE:
+        if (value != 0 && value != 1) return SPK_EINVAL;
+        g_force_wpe = value;
+        return SPK_OK;
+    default:
+        return SPK_EINVAL;
+    }
+}
+
+int get_plan_option(int option)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    switch (option) {
+    case SPK_OPT_PLAN_KGROUP: return g_force_kg;
+    case SPK_OPT_PLAN_WAVES_PER_WG: return g_force_wpg;
+    case SPK_OPT_PLAN_WPE: return g_force_wpe;
+    default: return SPK_EINVAL;
+    }
+}
+
+}  // namespace spk
 
 extern "C" {
 
@@ -363,18 +374,22 @@ int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32
         std::lock_guard<std::mutex> lock(g_tune_mu);
         tune_load();
         auto it = g_tune.find(pl->signature);
-        if (it != g_tune.end()) {
-            pl->grid = it->second.first;
-            pl->grab = it->second.second;
+        if ((flags & SPK_PLAN_AUTOTUNE) && it != g_tune.end()) {
+            pl->shape = it->second;
         } else if (flags & SPK_PLAN_AUTOTUNE) {
             rc = autotune(pl, pl->capture_stream);
             if (rc == SPK_OK) {
-                g_tune[pl->signature] = {pl->grid, pl->grab};
+                g_tune[pl->signature] = pl->shape;
                 tune_store();
             }
         } else {
-            pl->grid = prop.multiProcessorCount * 16;
-            pl->grab = 1;
+            Shape h;
+            h.kg = g_force_kg ? g_force_kg : 8;
+            h.wpg = g_force_wpg ? g_force_wpg : 1;
+            h.wpe = g_force_wpe;
+            h.grid = prop.multiProcessorCount * 16 / h.wpg;
+            h.grab = 1;
+            pl->shape = h;
         }
     }
     if (rc != SPK_OK) {
@@ -384,7 +399,7 @@ int spk_plan_create(spk_plan_t *plan, const spk_job *jobs, int32_t n_jobs, int32
     if (pl->use_graph) {
         if (hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal) !=
                 hipSuccess ||
-            launch_batch(pl, pl->grid, pl->grab, pl->capture_stream) != hipSuccess ||
+            launch_batch(pl, pl->shape, pl->capture_stream) != hipSuccess ||
             hipStreamEndCapture(pl->capture_stream, &pl->graph) != hipSuccess ||
             hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
             plan_free(pl);
@@ -405,17 +420,28 @@ int spk_plan_execute(spk_plan_t plan, void *hip_stream)
     hipStream_t st = (hipStream_t)hip_stream;
     if (plan->use_graph)
         return hipGraphLaunch(plan->exec, st) == hipSuccess ? SPK_OK : SPK_EHIP;
-    return launch_batch(plan, plan->grid, plan->grab, st) == hipSuccess ? SPK_OK : SPK_EHIP;
+    return launch_batch(plan, plan->shape, st) == hipSuccess ? SPK_OK : SPK_EHIP;
 }
 
 int spk_plan_info(spk_plan_t plan, int32_t *grid, int32_t *grab, int32_t *items)
 {
     if (!plan) return SPK_EINVAL;
-    if (grid) *grid = plan->grid;
-    if (grab) *grab = plan->grab;
+    if (grid) *grid = plan->shape.grid;
+    if (grab) *grab = plan->shape.grab;
     if (items) *items = plan->total_items;
     return SPK_OK;
 }
+
+int spk_plan_shape(spk_plan_t plan, int32_t *kgroup, int32_t *waves_per_wg,
+                   int32_t *waves_per_simd)
+{
+    if (!plan) return SPK_EINVAL;
+    if (kgroup) *kgroup = plan->shape.kg;
+    if (waves_per_wg) *waves_per_wg = plan->shape.wpg;
+    if (waves_per_simd) *waves_per_simd = spk::wpe_of(plan->order, plan->shape.wpe);
+    return SPK_OK;
+}
+
 
 int spk_plan_destroy(spk_plan_t plan)
 {

@@ -1,0 +1,9 @@
+// Batched-plan kernels with 4 tiles per prefetch group (every order, plane
+// map and waves-per-SIMD variant); see batch_kernels.h.
+#include "batch_kernels.h"
+
+namespace spk {
+
+hipError_t launch_batch_k4(const BatchLaunch &b, hipStream_t st) { return launch_kg<4>(b, st); }
+
+}  // namespace spk

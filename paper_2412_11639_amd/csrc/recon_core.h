@@ -863,21 +863,40 @@ __device__ __forceinline__ bool same_decisions(const SegState &a, const SegState
 
 
 // One wave walks tiles [tilew, tile1) of its 64-pixel strip starting at
-// p0, prefetching a group of tiles ahead.  In a chunked run (CHUNKED) the
-// tiles before tile0 only warm the state up, the state at tile0 is saved to
+// p0, prefetching a group of tiles ahead.  Row r of the stream at base (and
+// of P.cnt_le) is frame f0 + r.  In a chunked run (CHUNKED) the tiles
+// before tile0 only warm the state up, the state at tile0 is saved to
 // rec_start, and the first tiles after tile0 keep what the fixup pass needs.
-template <int ORDER, bool CHUNKED, class EM>
+// KG tiles per prefetch group.  The LDS rows (word_s, cnt_s: KG x 64) are
+// the wave's own; WAVE_SYNC orders their writes and reads with wave-scope
+// fences instead of a workgroup barrier, for workgroups of several waves
+// that each walk their own strips (a wave's LDS accesses complete in
+// order, so a compiler fence is all a lane needs to see its neighbours').
+template <bool WAVE_SYNC>
+__device__ __forceinline__ void tile_sync()
+{
+    if constexpr (WAVE_SYNC) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int ORDER, bool CHUNKED, int KG = kGroup, bool WAVE_SYNC = false, class EM>
 __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
                                      const uint8_t *base, const Xpose &X, int lane,
                                      int32_t tilew, int32_t tile0, int32_t tile1,
                                      uint64_t (*word_s)[64], int32_t (*cnt_s)[64],
-                                     int32_t *rec_start, int64_t fstride, int32_t &cum_base)
+                                     int32_t *rec_start, int64_t fstride, int32_t &cum_base,
+                                     int32_t f0 = 0)
 {
-    uint32_t rlo[kGroup], rhi[kGroup];
-    int32_t rc[kGroup];
+    uint32_t rlo[KG], rhi[KG];
+    int32_t rc[KG];
     auto fetch = [&](int32_t tg) {
 #pragma unroll
-        for (int i = 0; i < kGroup; i++) {
+        for (int i = 0; i < KG; i++) {
             const int32_t tr = (tg + i) * 64 + lane;
             rlo[i] = rhi[i] = 0;
             rc[i] = 0;
@@ -890,17 +909,17 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
         }
     };
     fetch(tilew);
-    for (int32_t tg = tilew; tg < tile1; tg += kGroup) {
+    for (int32_t tg = tilew; tg < tile1; tg += KG) {
         // the group's rows are in registers: transpose into LDS, then start
         // fetching the next group
 #pragma unroll
-        for (int i = 0; i < kGroup; i++) {
+        for (int i = 0; i < KG; i++) {
             word_s[i][lane] = transpose64(rlo[i], rhi[i], X, lane);
             cnt_s[i][lane] = rc[i];
         }
-        fetch(tg + kGroup);
-        __syncthreads();
-        const int32_t ni = min(kGroup, tile1 - tg);
+        fetch(tg + KG);
+        tile_sync<WAVE_SYNC>();
+        const int32_t ni = min(KG, tile1 - tg);
         for (int i = 0; i < ni; i++) {
             const int32_t t = tg + i;
             const uint64_t w = word_s[i][lane];
@@ -912,13 +931,13 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
                 }
                 // the first tiles of a later chunk keep what the fixup needs
                 if (ORDER == 1 && rec_start && t >= tile0 && t < tile0 + kCaptureTiles) {
-                    if (w) run.template word<ORDER, true, CHUNKED>(t * 64, w, cnt_s[i], em);
+                    if (w) run.template word<ORDER, true, CHUNKED>(f0 + t * 64, w, cnt_s[i], em);
                     continue;
                 }
             }
-            if (w) run.template word<ORDER, false, CHUNKED>(t * 64, w, cnt_s[i], em);
+            if (w) run.template word<ORDER, false, CHUNKED>(f0 + t * 64, w, cnt_s[i], em);
         }
-        __syncthreads();
+        tile_sync<WAVE_SYNC>();
     }
 }
 

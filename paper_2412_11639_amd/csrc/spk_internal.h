@@ -69,6 +69,10 @@ int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t strea
 // occupancy).
 extern int g_sur_conv_wg;
 
+// SPK_OPT_PLAN_*: the launch shape of plans created without autotuning.
+int set_plan_option(int option, int value);
+int get_plan_option(int option);
+
 // Enqueue the plain FSR/SSR reconstruction (or segment listing) on stream.
 hipError_t launch_recon(const ReconParams &p, int order, Mode mode, const ChunkPlan &cp,
                         hipStream_t stream);

@@ -1168,10 +1168,23 @@ size_t spk_sur_workspace_bytes(int32_t B, int32_t Hc, int32_t Wc)
     return (size_t)workspace_bytes(B, Hc, Wc);
 }
 
+
 static int check_batch(int32_t B, int32_t Hc, int32_t Wc)
 {
     if (B <= 0 || Hc <= 0 || Wc <= 0) return SPK_EINVAL;
     if ((int64_t)B * Hc * Wc > ((int64_t)1 << 31) / C) return SPK_EINVAL;
+    return SPK_OK;
+}
+
+int spk_sur_workspace_layout(int32_t B, int32_t Hc, int32_t Wc, size_t *offsets)
+{
+    if (!offsets || check_batch(B, Hc, Wc)) return SPK_EINVAL;
+    // carve an address range that is never dereferenced
+    const uintptr_t base = (uintptr_t)1 << 20;
+    const Workspace w = carve((void *)base, B, Hc, Wc);
+    const void *views[SPK_SUR_WS_VIEWS] = {w.packed, w.a1, w.a2, w.a3, w.g1, w.g2, w.dy};
+    for (int k = 0; k < SPK_SUR_WS_VIEWS; k++)
+        offsets[k] = (size_t)((uintptr_t)views[k] - base);
     return SPK_OK;
 }
 

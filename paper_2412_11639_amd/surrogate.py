@@ -58,6 +58,9 @@ def _lib_sur():
     if not getattr(lib, "_sur_declared", False):
         lib.spk_sur_workspace_bytes.restype = ctypes.c_size_t
         lib.spk_sur_workspace_bytes.argtypes = [_i32, _i32, _i32]
+        lib.spk_sur_workspace_layout.restype = ctypes.c_int
+        lib.spk_sur_workspace_layout.argtypes = [_i32, _i32, _i32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]
         for name, argtypes in _lib.EXTRA_DECLS.items():
             if name.startswith("spk_sur_"):
                 f = getattr(lib, name)
@@ -104,6 +107,26 @@ class Surrogate:
             n = int(_lib_sur().spk_sur_workspace_bytes(B, Hc, Wc))
             self._ws[key] = torch.empty(n, dtype=torch.uint8, device=self.device)
         return self._ws[key]
+
+    def stored(self, B, Hc, Wc):
+        """The values the last forward and backward of this batch shape left
+        in its workspace (spk_sur_workspace_layout): dict of float32 device
+        tensors a1, a2, a3, g1, g2 ([B, Hc, Wc, 32]) and dy ([B, Hc, Wc])."""
+        offs = (ctypes.c_size_t * 7)()
+        _lib.check("spk_sur_workspace_layout",
+                   _lib_sur().spk_sur_workspace_layout(B, Hc, Wc, offs))
+        ws = self.workspace(B, Hc, Wc)
+        P = B * Hc * Wc
+        out = {}
+        for k, name in enumerate(("packed", "a1", "a2", "a3", "g1", "g2", "dy")):
+            if name == "packed":
+                continue
+            if name == "dy":
+                t = ws[offs[k]:offs[k] + 4 * P].view(torch.float32).reshape(B, Hc, Wc)
+            else:
+                t = ws[offs[k]:offs[k] + 2 * P * 32].view(torch.bfloat16).reshape(B, Hc, Wc, 32)
+            out[name] = t.to(torch.float32)
+        return out
 
     # -- inputs ---------------------------------------------------------------
     @staticmethod

@@ -187,6 +187,14 @@ def test_options(lib):
     assert lib.spk_set_option(3, -1) == -1
     assert lib.spk_set_option(3, 5) == 0 and lib.spk_get_option(3) == 5
     assert lib.spk_set_option(3, 0) == 0 and lib.spk_get_option(3) == 0
+    # batched plan shape: group size, waves per workgroup, register target
+    for opt, good, bad in ((4, (4, 8, 16, 0), (3, 32, -1)), (5, (1, 2, 4, 0), (3, 8, -1)),
+                           (6, (1, 0), (2, -1))):
+        for v in good:
+            assert lib.spk_set_option(opt, v) == 0 and lib.spk_get_option(opt) == v
+        for v in bad:
+            assert lib.spk_set_option(opt, v) == -1
+        assert lib.spk_get_option(opt) == 0
 
 
 def test_sur_train_plan_rejects_bad_arguments():
@@ -247,3 +255,26 @@ def test_sur_input_rejects_unaligned_stream():
     for base, rc in ((0x2008, -1), (0x2004, -1), (0x2001, -1)):
         arr = (sur.SurSample * 1)(sur.SurSample(base, 250, 400, 4096, 0, 0, 100, None))
         assert lib.spk_sur_input(arr, 1, 8, 8, 1.0, p, p, p, None, None) == rc
+
+
+def test_stream_rejects_bad_arguments(lib):
+    """spk_stream_create / feed / finish validate on the host; nothing is
+    allocated or enqueued for a bad argument."""
+    h = ctypes.c_void_p()
+    t = (ctypes.c_int32 * 2)(0, 5)
+    bad_t = (ctypes.c_int32 * 2)(0, -1)
+    create = lib.spk_stream_create
+    assert create(None, 4, 4, 1.0, 1, t, 2, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 0, 4, 1.0, 1, t, 2, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 4, 4, 0.0, 1, t, 2, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 4, 4, float("inf"), 1, t, 2, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 4, 4, 1.0, 5, t, 2, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 4, 4, 1.0, 1, None, 2, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 4, 4, 1.0, 1, bad_t, 2, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 4, 4, 1.0, 1, t, -1, FAKE, None, None, None) == -1
+    assert create(ctypes.byref(h), 65536, 65536, 1.0, 1, t, 2, FAKE, None, None, None) == -1
+    assert not h.value
+    assert lib.spk_stream_feed(None, FAKE, 4, None) == -1
+    assert lib.spk_stream_finish(None, None) == -1
+    assert lib.spk_stream_frames(None) == -1
+    assert lib.spk_stream_destroy(None) == 0

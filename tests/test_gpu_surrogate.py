@@ -89,27 +89,16 @@ def _to_dev(win, est):
     return (torch.from_numpy(win.view(np.int32).copy()).cuda(), torch.from_numpy(est).cuda())
 
 
-@pytest.mark.parametrize("shape", [(2, 16, 16), (3, 19, 37), (1, 64, 80)])
-def test_forward_matches_reference(sur, shape):
-    rng = np.random.default_rng(1)
-    B, Hc, Wc = shape
-    params = sur.init_params(2) + rng.normal(0, 0.05, sur.NPARAMS)
-    model = sur.Surrogate(params)
-    win, est = _rand_batch(rng, B, Hc, Wc)
-    y = model.forward(*_to_dev(win, est)).cpu().numpy().astype(np.float64)
-    ref, _ = oc.forward(model.params.cpu().numpy().astype(np.float64),
-                        oc.make_input(win, est.astype(np.float64), bf=True), bf=True,
-                        est=est.astype(np.float64))
-    scale = np.abs(ref).max()
-    err = np.abs(y - ref)
-    assert err.max() <= 2e-2 * scale, err.max()
-    assert err.mean() <= 1e-3 * scale, err.mean()
-
-
-@pytest.mark.parametrize("shape", [(2, 16, 16), (2, 21, 35)])
-def test_backward_matches_reference(sur, shape):
+@pytest.mark.parametrize("shape", [(2, 16, 16), (3, 19, 37), (1, 64, 80), (2, 21, 35)])
+def test_every_stored_value_and_gradient_matches_reference(sur, shape):
+    """One forward and backward pass, checked element by element: every
+    activation, the output, dL/dy, the kept input gradients and every
+    parameter gradient against the float64 reference computed from the
+    device's own inputs to each layer, within the float32-accumulation and
+    bfloat16-rounding bounds of oracle.conv.layer_checks."""
     rng = np.random.default_rng(3)
     B, Hc, Wc = shape
+    print("surrogate layers B=%d Hc=%d Wc=%d" % shape, flush=True)
     params = sur.init_params(4) + rng.normal(0, 0.05, sur.NPARAMS)
     model = sur.Surrogate(params)
     win, est = _rand_batch(rng, B, Hc, Wc)
@@ -117,17 +106,74 @@ def test_backward_matches_reference(sur, shape):
     dwin, dest = _to_dev(win, est)
     y = model.forward(dwin, dest)
     lp = model.backward(dwin, dest, y, torch.from_numpy(target).cuda())
-    g = model.grad.cpu().numpy().astype(np.float64)
-    loss_ref, g_ref, _ = oc.loss_and_grad(model.params.cpu().numpy().astype(np.float64),
-                                          oc.make_input(win, est.astype(np.float64), bf=True),
+    dev = {k: v.cpu().numpy().astype(np.float64) for k, v in model.stored(B, Hc, Wc).items()}
+    dev["y"] = y.cpu().numpy().astype(np.float64)
+    dev["grad"] = model.grad.cpu().numpy().astype(np.float64)
+    p64 = model.params.cpu().numpy().astype(np.float64)
+    res = oc.layer_checks(p64, win, est, target, dev)
+    assert all(v == 0 for v in res.values()), res
+    # diagnostics: loss, and the relative L2 distance per block from the
+    # reference run on its own (float64 sums, its own roundings)
+    loss_ref, g_ref, _ = oc.loss_and_grad(p64, oc.make_input(win, est.astype(np.float64), bf=True),
                                           target.astype(np.float64), bf=True,
                                           est=est.astype(np.float64))
     loss = float(lp.sum().cpu()) / target.size
     assert abs(loss - loss_ref) <= 1e-3 * loss_ref
     offs = np.cumsum([0] + [int(np.prod(s)) for _, s in oc.SHAPES])
     for (name, _), a, b in zip(oc.SHAPES, offs[:-1], offs[1:]):
-        d = np.linalg.norm(g[a:b] - g_ref[a:b]) / max(np.linalg.norm(g_ref[a:b]), 1e-30)
-        assert d <= 2e-2, (name, d)
+        d = np.linalg.norm(dev["grad"][a:b] - g_ref[a:b]) / max(np.linalg.norm(g_ref[a:b]), 1e-30)
+        print("  %s: relative L2 from the reference's own pass %.2e" % (name, d))
+
+
+def test_streaming_loop_matches_oracle(sur):
+    """The per-frame serving loop on a moving scene, 300 frames: advance the
+    32-frame window by one frame, run the pre-packed inference, apply the
+    fallback mux.  Every frame from 31 on: the window bits, the short-window
+    estimate and the stability flag equal the oracle's
+    (oracle.window_estimate on the stream), the mux output equals the
+    select of the device's network output and the oracle's estimate by the
+    oracle's flag, element by element; every 30th frame the network's
+    stored activations and output pass the forward layer checks."""
+    H, W, T = 48, 80, 300
+    s = spkgen.blocks(H, W, T, seed=61, vx=0.9, vy=-0.6)
+    ds = torch.from_numpy(s).cuda()
+    bits = spkgen.unpack(s, H, W).astype(np.uint64)
+    rng = np.random.default_rng(14)
+    model = sur.Surrogate(sur.init_params(8) + rng.normal(0, 0.05, sur.NPARAMS))
+    p64 = model.params.cpu().numpy().astype(np.float64)
+    win = torch.zeros((1, H, W), dtype=torch.int32, device="cuda")
+    est = torch.zeros((1, H, W), dtype=torch.float32, device="cuda")
+    st = torch.zeros((1, H, W), dtype=torch.uint8, device="cuda")
+    y = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    mx = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    n_stable = 0
+    for t in range(T):
+        sur.Surrogate.stream_step(ds[t], H, W, 1.0, win, est, st)
+        if t < 31:
+            continue
+        model.infer(win, est, out=y, prepacked=t > 31)
+        sur.Surrogate.mux(y, est, st, out=mx)
+        torch.cuda.synchronize()
+        e_ref, st_ref = oracle.window_estimate(s, H, W, T, 1.0, t)
+        w_ref = sum(bits[t - 31 + j] << np.uint64(j) for j in range(32)).astype(np.uint32)
+        w_got = win[0].cpu().numpy().view(np.uint32)
+        np.testing.assert_array_equal(w_got, w_ref, err_msg="window t=%d" % t)
+        e32 = e_ref.astype(np.float32)
+        np.testing.assert_array_equal(est[0].cpu().numpy(), e32, err_msg="estimate t=%d" % t)
+        np.testing.assert_array_equal(st[0].cpu().numpy().astype(bool), st_ref,
+                                      err_msg="flag t=%d" % t)
+        y_got = y[0].cpu().numpy()
+        np.testing.assert_array_equal(mx[0].cpu().numpy(), np.where(st_ref, y_got, e32),
+                                      err_msg="mux t=%d" % t)
+        n_stable += int(st_ref.sum())
+        if t % 30 == 0:
+            dev = {k: v.cpu().numpy().astype(np.float64)
+                   for k, v in model.stored(1, H, W).items() if k in ("a1", "a2", "a3")}
+            dev["y"] = y.cpu().numpy().astype(np.float64)
+            res = oc.layer_checks(p64, w_ref[None], e32[None], None, dev)
+            assert all(v == 0 for v in res.values()), (t, res)
+    # both branches of the mux were taken
+    assert 0 < n_stable < H * W * (T - 31)
 
 
 def test_adam_matches_reference(sur):
