@@ -56,7 +56,8 @@ enum {
     SPK_EINVAL = -1,      /* bad argument                                  */
     SPK_ENOMEM = -2,      /* device or host allocation failed              */
     SPK_EHIP = -3,        /* a HIP runtime call or launch failed           */
-    SPK_EUNSUPPORTED = -4 /* no usable gfx950 device                       */
+    SPK_EUNSUPPORTED = -4, /* no usable gfx950 device                      */
+    SPK_ERANGE = -5        /* beyond the fixed scratch of spk_reconstruct_noalloc */
 };
 
 /*
@@ -132,6 +133,28 @@ int spk_reconstruct_windows(const uint8_t *stream, int32_t H, int32_t W, int32_t
                             float theta, const int32_t *t_out, int32_t n_out, float *out,
                             int32_t *win_first, int32_t *win_last, int32_t *win_n,
                             int32_t order, void *hip_stream);
+
+/*
+ * For callers that cannot allocate device memory -- code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation --
+ * spk_reconstruct with no allocation of any kind: every device buffer beyond
+ * the caller's stream and out (the output-time tables and the per-chunk
+ * records of long streams) lives in a fixed array of
+ * SPK_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds from
+ * library load until the process ends.  The output times reach the device
+ * as kernel arguments (no host staging).  Results are identical to
+ * spk_reconstruct's.  Limits: n_out <= 2^20 and T + 2 * n_out <= 2^24 - 64
+ * (else SPK_ERANGE, nothing enqueued); a long stream is split into fewer
+ * time chunks when their records do not fit the rest of the array (same
+ * results, less parallelism).  Every call on a GPU uses that GPU's one
+ * array: calls on one GPU whose work overlaps (two host threads, or two
+ * streams whose work runs at the same time) race on it and must be
+ * serialised by the caller.  Other arguments and errors as spk_reconstruct.
+ */
+#define SPK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int spk_reconstruct_noalloc(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
+                            const int32_t *t_out, int32_t n_out, float *out, int32_t order,
+                            void *hip_stream);
 
 /*
  * Every segment of every pixel (the full segmentation of Sec. III-B).

@@ -111,6 +111,21 @@ def reconstruct(stream_t: torch.Tensor, H: int, W: int, T: int, theta: float, t_
     return out
 
 
+def reconstruct_noalloc(stream_t: torch.Tensor, H: int, W: int, T: int, theta: float, t_out,
+                        out: torch.Tensor, order: int = FSR, stream=None) -> torch.Tensor:
+    """``reconstruct`` through the allocation-free entry point
+    (``spk_reconstruct_noalloc``): the caller passes ``out``; the library
+    allocates nothing and uses its fixed per-GPU scratch array."""
+    _check_stream_tensor(stream_t, H, W, T)
+    t, tp = _host_times(t_out)
+    n_out = len(t)
+    assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n_out * H * W
+    rc = _lib.load().spk_reconstruct_noalloc(stream_t.data_ptr(), H, W, T, float(theta), tp,
+                                             n_out, out.data_ptr(), order, _stream_handle(stream))
+    _lib.check("spk_reconstruct_noalloc", rc)
+    return out
+
+
 def tfp(stream_t, H, W, T, theta, window, t_out, out=None, stream=None):
     """TFP baseline: theta * (spikes in the ``window`` frames ending at t) /
     window length (clipped at frame 0), float32 [n_out, H, W]."""

@@ -70,6 +70,8 @@ class SpkJob(ctypes.Structure):
 
 
 EXTRA_DECLS: dict = {
+    "spk_reconstruct_noalloc": [P_u8, c_i32, c_i32, c_i32, ctypes.c_float, P_i32, c_i32, P_f32,
+                                c_i32, ctypes.c_void_p],
     "spk_stream_create": [ctypes.POINTER(ctypes.c_void_p), c_i32, c_i32, ctypes.c_float, c_i32,
                           P_i32, c_i32, P_f32, P_i32, P_i32, P_i32],
     "spk_stream_feed": [ctypes.c_void_p, P_u8, c_i32, ctypes.c_void_p],

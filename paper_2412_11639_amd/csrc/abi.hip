@@ -343,6 +343,85 @@ __global__ void motion_kernel(const int32_t *win_first, const int32_t *first_spi
 
 }  // namespace
 
+// ---- allocation-free reconstruction ---------------------------------------
+//
+// spk_reconstruct_noalloc takes every device buffer beyond the caller's
+// inputs and outputs from `scratch`, a fixed array each GPU holds from
+// library load to process exit: the output-time tables first (cnt_le [T],
+// plane map [n_out], sorted times [n_out]), then the chunk records of the
+// time-chunked walk.  Host code never passes the array's name to a kernel:
+// its device address on each GPU comes from hipGetSymbolAddress, taken once
+// per device with that device current.  The tables reach the device as
+// kernel arguments (no host staging buffer, nothing a capture could replay
+// from stale host memory), and cnt_le is built on the device from the
+// sorted times.  Every word a kernel reads is written earlier in the same
+// call, so nothing needs clearing between calls.
+
+static __device__ __align__(256) int32_t scratch[SPK_NOALLOC_SCRATCH_BYTES / sizeof(int32_t)];
+
+namespace {
+
+constexpr size_t kNoAllocInts = SPK_NOALLOC_SCRATCH_BYTES / sizeof(int32_t);
+int32_t *g_scratch_ptr[64];  // device address of `scratch` on each device (NULL: not yet)
+
+int noalloc_scratch(int dev, int32_t **out)
+{
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return SPK_EHIP;
+        g_scratch_ptr[dev] = (int32_t *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPK_OK;
+}
+
+// Up to kPutInts table words as a kernel argument (a few KB of kernarg).
+constexpr int kPutInts = 960;
+struct PutChunk {
+    int32_t n;
+    int32_t v[kPutInts];
+};
+
+__global__ __launch_bounds__(256) void put_kernel(int32_t *dst, PutChunk c)
+{
+    for (int i = threadIdx.x; i < c.n; i += 256) dst[i] = c.v[i];
+}
+
+// cnt_le[t] = number of sorted times <= t, for t < T
+__global__ __launch_bounds__(256) void cnt_le_kernel(const int32_t *t_sorted, int32_t n_out,
+                                                     int32_t T, int32_t *cnt_le)
+{
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= T) return;
+    int32_t lo = 0, hi = n_out;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (t_sorted[mid] <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    cnt_le[t] = lo;
+}
+
+// Sort keys for the output times (time, then index: a stable order).
+constexpr int32_t kNoAllocMaxOut = 1 << 20;
+static int64_t g_keys[kNoAllocMaxOut];
+
+hipError_t put_ints(int32_t *dst, const int32_t *src, int32_t n, hipStream_t st)
+{
+    for (int32_t i = 0; i < n; i += kPutInts) {
+        PutChunk c;
+        c.n = std::min(kPutInts, n - i);
+        std::memcpy(c.v, src + i, (size_t)c.n * sizeof(int32_t));
+        hipLaunchKernelGGL(put_kernel, dim3(1), dim3(256), 0, st, dst + i, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t spk_frame_bytes(int32_t H, int32_t W)
@@ -359,6 +438,7 @@ const char *spk_strerror(int code)
     case SPK_ENOMEM: return "out of memory";
     case SPK_EHIP: return "HIP runtime error";
     case SPK_EUNSUPPORTED: return "unsupported device (needs gfx950)";
+    case SPK_ERANGE: return "request exceeds the allocation-free entry point's fixed scratch";
     default: return "unknown error";
     }
 }
@@ -415,6 +495,74 @@ int spk_reconstruct_windows(const uint8_t *stream, int32_t H, int32_t W, int32_t
 {
     return reconstruct_impl(stream, H, W, T, theta, t_out, n_out, out, win_first, win_last,
                             win_n, order, hip_stream);
+}
+
+int spk_reconstruct_noalloc(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
+                            const int32_t *t_out, int32_t n_out, float *out, int32_t order,
+                            void *hip_stream)
+{
+    int rc = check_common(stream, H, W, T, order);
+    if (rc) return rc;
+    if (!std::isfinite(theta) || !(theta > 0.0f) || n_out < 0) return SPK_EINVAL;
+    if (n_out == 0) return SPK_OK;
+    if (!t_out || !out) return SPK_EINVAL;
+    if ((int64_t)n_out * (int64_t)H * (int64_t)W > ((int64_t)1 << 60)) return SPK_EINVAL;
+    for (int32_t k = 0; k < n_out; k++)
+        if (t_out[k] < 0 || t_out[k] >= T) return SPK_EINVAL;
+    // the tables must fit in the fixed scratch (records shrink to fit)
+    const size_t tab_ints = ((size_t)T + 2 * (size_t)n_out + 63) / 64 * 64;
+    if (n_out > kNoAllocMaxOut || tab_ints > kNoAllocInts) return SPK_ERANGE;
+    std::lock_guard<std::mutex> lock(g_mu);
+    int dev = 0;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    int32_t *base = nullptr;
+    rc = noalloc_scratch(dev, &base);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    // sorted order of the output times (stable), the plane map and the times
+    for (int32_t k = 0; k < n_out; k++) g_keys[k] = ((int64_t)t_out[k] << 32) | k;
+    std::sort(g_keys, g_keys + n_out);
+    bool identity = true;
+    for (int32_t j = 0; j < n_out; j++) {
+        if ((int32_t)(g_keys[j] & 0xffffffff) != j) identity = false;
+        if (j > 0 && (g_keys[j] >> 32) == (g_keys[j - 1] >> 32)) identity = false;
+    }
+    int32_t *cnt_le = base, *plane = base + T, *t_sorted = base + T + n_out;
+    int32_t buf[kPutInts];
+    for (int pass = 0; pass < 2; pass++) {
+        if (pass == 0 && identity) continue;  // the plane map is not read
+        int32_t *dst = pass == 0 ? plane : t_sorted;
+        for (int32_t i = 0; i < n_out; i += kPutInts) {
+            const int32_t n = std::min(kPutInts, n_out - i);
+            for (int32_t j = 0; j < n; j++)
+                buf[j] = pass == 0 ? (int32_t)(g_keys[i + j] & 0xffffffff)
+                                   : (int32_t)(g_keys[i + j] >> 32);
+            if (put_ints(dst + i, buf, n, st) != hipSuccess) return SPK_EHIP;
+        }
+    }
+    hipLaunchKernelGGL(cnt_le_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
+                       t_sorted, n_out, T, cnt_le);
+    if (hipGetLastError() != hipSuccess) return SPK_EHIP;
+    spk::ReconParams p{};
+    p.stream = stream;
+    p.fb = (int64_t)spk_frame_bytes(H, W);
+    p.T = T;
+    p.HW = H * W;
+    p.theta = (double)theta;
+    p.cnt_le = cnt_le;
+    p.plane = identity ? nullptr : plane;
+    p.n_out = n_out;
+    p.out = out;
+    // chunk records in the rest of the scratch: as many chunks as the
+    // automatic plan wants, fewer if their records do not fit
+    const size_t room = kNoAllocInts - tab_ints;
+    spk::ChunkPlan cp = spk::plan_chunks(p.HW, T, order, requested_chunks(), requested_warm());
+    for (int c = cp.nchunks; c > 1 && spk::chunk_record_ints(cp, p.HW) > room;)
+        cp = spk::plan_chunks(p.HW, T, order, --c, requested_warm());
+    if (spk::chunk_record_ints(cp, p.HW) > room) cp = spk::plan_chunks(p.HW, T, order, 1);
+    cp.rec = cp.nchunks > 1 ? base + tab_ints : nullptr;
+    return spk::launch_recon(p, order, spk::MODE_RECON, cp, st) == hipSuccess ? SPK_OK : SPK_EHIP;
 }
 
 int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,

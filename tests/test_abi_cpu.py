@@ -257,6 +257,22 @@ def test_sur_input_rejects_unaligned_stream():
         assert lib.spk_sur_input(arr, 1, 8, 8, 1.0, p, p, p, None, None) == rc
 
 
+def test_noalloc_rejects_what_does_not_fit(lib):
+    """spk_reconstruct_noalloc checks its fixed scratch limits on the host,
+    before any device access: output-time tables past the array are
+    SPK_ERANGE, bad arguments SPK_EINVAL as for spk_reconstruct."""
+    fake = FAKE   # never dereferenced
+    t = (ctypes.c_int32 * 2)(0, 1)
+    f = lib.spk_reconstruct_noalloc
+    assert f(fake, 8, 8, 1 << 24, 1.0, t, 2, fake, 1, None) == -5
+    assert f(fake, 8, 8, 100, 1.0, t, 2, 0, 1, None) == -1        # no out
+    assert f(fake + 8, 8, 8, 100, 1.0, t, 2, fake, 1, None) == -1  # unaligned stream
+    assert f(fake, 8, 8, 100, 0.0, t, 2, fake, 1, None) == -1      # theta
+    assert f(fake, 8, 8, 1, 1.0, t, 2, fake, 1, None) == -1        # t_out >= T
+    assert f(fake, 8, 8, 100, 1.0, t, 0, fake, 1, None) == 0       # nothing to do
+    assert lib.spk_strerror(-5)
+
+
 def test_stream_rejects_bad_arguments(lib):
     """spk_stream_create / feed / finish validate on the host; nothing is
     allocated or enqueued for a bad argument."""
@@ -278,3 +294,4 @@ def test_stream_rejects_bad_arguments(lib):
     assert lib.spk_stream_finish(None, None) == -1
     assert lib.spk_stream_frames(None) == -1
     assert lib.spk_stream_destroy(None) == 0
+
