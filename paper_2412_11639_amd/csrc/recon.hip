@@ -31,23 +31,30 @@
 namespace spk {
 namespace {
 
+// Tiles per prefetch group of the main pass.  Four keep the SSR state
+// machine and the prefetched rows within 128 VGPRs (124, no scratch; eight
+// needed 128 plus 28 bytes of scratch per lane), and four tiles of loads in
+// flight are far ahead of memory latency at this kernel's integer work per
+// tile (measured on 250x400x20000: FSR 1.35 -> 1.33 ms, SSR unchanged,
+// third order 3.76 -> 3.69 ms).
+constexpr int kReconGroup = 4;
+
 // Main pass.  With nchunks == 1 a wave walks its strip's whole stream and
 // finishes every segment.  With nchunks > 1 the stream is cut into chunks
 // of chunk_tiles tiles; chunk 0 runs exactly, every later chunk starts from
 // a fresh state at its first spike (speculation), and each wave records its
 // state at its chunk's end for the fixup pass, which makes the result exact.
 template <int ORDER, int MODE, bool WIN, int PMAP>
-// Four waves per SIMD (at most 128 VGPRs) for every order: the SSR state
-// machine alone would take 140 and run three, and the walk is bound by VALU
-// issue, which the fourth wave keeps fuller (a few bytes of the per-group
-// state go to scratch, outside the per-spike loops).  The third order's
-// larger state spills more (240 bytes) and still gains: 3.78 ms against
-// 4.26 at two waves (180 VGPRs, no spill) on a 250x400x20000 stream.
+// Four waves per SIMD (at most 128 VGPRs) for every order: the walk is
+// bound by VALU issue, which the fourth wave keeps fuller.  The third
+// order's larger state spills (a few hundred bytes) and still gains: 3.78
+// ms against 4.26 at two waves (180 VGPRs, no spill) on a 250x400x20000
+// stream.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 void recon_kernel(ReconParams P, int nblocks, ChunkPlan cp)
 {
-    __shared__ uint64_t word_s[kGroup][64];
-    __shared__ int32_t cnt_s[kGroup][64];
+    __shared__ uint64_t word_s[kReconGroup][64];
+    __shared__ int32_t cnt_s[kReconGroup][64];
     extern __shared__ int32_t plane_dyn[];
     const int lane = threadIdx.x;
     const int L = xcd_strip(blockIdx.x, nblocks * cp.nchunks);
@@ -72,12 +79,12 @@ void recon_kernel(ReconParams P, int nblocks, ChunkPlan cp)
     run.reset(tilew > 0 && MODE == MODE_RECON ? P.cnt_le[tilew * 64 - 1] : 0, tile0 * 64);
     int32_t cum_base = 0;  // spikes seen before tile0
     if (cp.nchunks > 1)
-        walk<ORDER, true>(P, em, run, base, X, lane, tilew, tile0, tile1, word_s, cnt_s,
-                          chunk > 0 ? rec_start(cp, chunk, p, P.HW) : nullptr, fstride,
-                          cum_base);
+        walk<ORDER, true, kReconGroup>(P, em, run, base, X, lane, tilew, tile0, tile1, word_s,
+                                       cnt_s, chunk > 0 ? rec_start(cp, chunk, p, P.HW) : nullptr,
+                                       fstride, cum_base);
     else
-        walk<ORDER, false>(P, em, run, base, X, lane, tilew, tile0, tile1, word_s, cnt_s,
-                           nullptr, fstride, cum_base);
+        walk<ORDER, false, kReconGroup>(P, em, run, base, X, lane, tilew, tile0, tile1, word_s,
+                                        cnt_s, nullptr, fstride, cum_base);
     if (cp.nchunks > 1) {
         // end-of-chunk record, spike indices relative to the chunk's start
         run.cum -= cum_base;

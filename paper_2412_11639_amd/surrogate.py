@@ -229,27 +229,89 @@ class Surrogate:
         return {"params": self.params.cpu().numpy().copy(), "m": self.m.cpu().numpy().copy(),
                 "v": self.v.cpu().numpy().copy(), "step": self.step_count}
 
+    # -- checkpoints ----------------------------------------------------------
+    CKPT_VERSION = 1
+
+    def save(self, path, extra: dict | None = None):
+        """Write parameters, both Adam moments and the step count (float32
+        values exactly as on the device) to a NumPy .npz file; ``extra``
+        (JSON-serialisable, e.g. a sampler's random state) is stored beside
+        them.  No pickled objects: load() reads it with allow_pickle=False."""
+        import json
+        st = self.state()
+        blob = np.frombuffer(json.dumps(extra or {}).encode(), dtype=np.uint8)
+        with open(path, "wb") as f:
+            np.savez(f, version=np.int64(self.CKPT_VERSION), params=st["params"], m=st["m"],
+                     v=st["v"], step=np.int64(st["step"]), extra=blob)
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        """A Surrogate restored from save(): returns (model, extra)."""
+        import json
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["version"]) != cls.CKPT_VERSION:
+                raise ValueError("checkpoint version %d" % int(z["version"]))
+            model = cls(z["params"], device=device)
+            model.m.copy_(torch.from_numpy(z["m"].astype(np.float32)))
+            model.v.copy_(torch.from_numpy(z["v"].astype(np.float32)))
+            model.step_count = int(z["step"])
+            extra = json.loads(bytes(z["extra"]).decode() or "{}")
+        return model, extra
+
 
 # ---------------------------------------------------------------------------
 # training data: seeded static block scenes, targets from the plain method
 
+def scene_velocity(seed: int, vmax: float = 2.0):
+    """The translation velocity (px/frame) of a moving block scene: speed
+    uniform in (0, vmax], direction uniform, both from the scene's seed."""
+    import spkgen
+    speed = vmax * (1.0 - spkgen.rng_u64(seed, 7, 0) / 2.0 ** 64)
+    ang = 2.0 * math.pi * (spkgen.rng_u64(seed, 7, 1) / 2.0 ** 64)
+    return speed * math.cos(ang), speed * math.sin(ang)
+
+
 class SceneSet:
-    """Block scenes resident on the device with long-window plain targets
-    (FSR over the whole stream) at a few times per scene."""
+    """Block scenes resident on the device with long-window plain targets at
+    a few times per scene.  ``moving``: the blocks translate at
+    scene_velocity(seed) instead of standing still.  ``target``: "whole"
+    (FSR over the whole stream, valued at t) or "causal" (FSR over the
+    frames up to t alone, valued at t: what a live system can know)."""
 
     def __init__(self, seeds, H=250, W=400, T=4096, target_times=(31, 1055, 2079, 3103, 4095),
-                 theta=1.0, device="cuda", nthreads=None):
+                 theta=1.0, device="cuda", nthreads=None, moving=False, target="whole",
+                 keep_host=True):
         import spkgen
+        assert target in ("whole", "causal")
         self.H, self.W, self.T, self.theta = H, W, T, theta
         self.seeds = list(seeds)
         self.target_times = list(target_times)
         self.streams, self.targets, self.host = [], [], []
         for sd in self.seeds:
-            s = spkgen.blocks(H, W, T, sd, nthreads=nthreads)
+            vx, vy = scene_velocity(sd) if moving else (0.0, 0.0)
+            s = spkgen.blocks(H, W, T, sd, vx=vx, vy=vy, nthreads=nthreads)
             ds = torch.from_numpy(s).to(device)
             self.streams.append(ds)
-            self.targets.append(reconstruct(ds, H, W, T, theta, self.target_times, order=FSR))
-            self.host.append(s)
+            if target == "whole":
+                tg = reconstruct(ds, H, W, T, theta, self.target_times, order=FSR)
+            else:
+                tg = torch.empty((len(self.target_times), H, W), dtype=torch.float32,
+                                 device=device)
+                for k, t in enumerate(self.target_times):
+                    reconstruct(ds[:t + 1], H, W, t + 1, theta, [t], order=FSR, out=tg[k])
+            self.targets.append(tg)
+            if keep_host:
+                self.host.append(s)
+
+    def extend(self, other: "SceneSet"):
+        """Add another set's scenes (same shape and target times)."""
+        assert (other.H, other.W, other.T) == (self.H, self.W, self.T)
+        assert other.target_times == self.target_times
+        self.seeds += other.seeds
+        self.streams += other.streams
+        self.targets += other.targets
+        self.host += other.host
+        return self
 
     def samples(self, rng, B, Hc, Wc):
         out = []
@@ -264,15 +326,22 @@ class SceneSet:
 
 
 def train(model: Surrogate, scenes: SceneSet, steps: int, B: int = 16, Hc: int = 64,
-          Wc: int = 64, lr: float = 2e-3, seed: int = 0, log_every: int = 0):
-    """Adam on random crops; returns the per-step losses (host floats)."""
-    rng = np.random.default_rng(seed)
+          Wc: int = 64, lr: float = 2e-3, seed: int = 0, log_every: int = 0, rng=None,
+          schedule_steps: int | None = None):
+    """Adam on random crops; returns the per-step losses (host floats).
+    ``rng`` (a numpy Generator) replaces the seed, e.g. to continue a run
+    from a checkpoint; the cosine learning-rate schedule runs over
+    ``schedule_steps`` (default ``steps``) and is indexed by the model's
+    step count, so a resumed run continues it."""
+    rng = np.random.default_rng(seed) if rng is None else rng
+    total = max(1, schedule_steps if schedule_steps is not None else steps)
+    first = model.step_count if schedule_steps is not None else 0
     losses = []
     n = B * Hc * Wc
     parts = []
     for step in range(steps):
         # cosine decay of the learning rate
-        lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(1, steps)))
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * (first + step) / total))
         win, est, st, tgt = Surrogate.input(scenes.samples(rng, B, Hc, Wc), Hc, Wc,
                                             scenes.theta, with_target=True)
         parts.append(model.train_step(win, est, tgt, lr=lr_t))

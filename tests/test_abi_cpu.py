@@ -295,3 +295,24 @@ def test_stream_rejects_bad_arguments(lib):
     assert lib.spk_stream_frames(None) == -1
     assert lib.spk_stream_destroy(None) == 0
 
+
+def test_surrogate_checkpoint_round_trip(tmp_path):
+    """A checkpoint is a plain .npz (no pickles) that restores parameters,
+    both Adam moments, the step count and the extra state exactly (CPU
+    tensors; the device path is the same code)."""
+    import numpy as np
+    import torch
+    import paper_2412_11639_amd.surrogate as sur
+    rng = np.random.default_rng(0)
+    m = sur.Surrogate(sur.init_params(1) + rng.normal(0, 0.01, sur.NPARAMS), device="cpu")
+    m.m.copy_(torch.from_numpy(rng.normal(0, 1, sur.NPARAMS).astype(np.float32)))
+    m.v.copy_(torch.from_numpy(rng.uniform(0, 1, sur.NPARAMS).astype(np.float32)))
+    m.step_count = 123
+    p = str(tmp_path / "c.npz")
+    m.save(p, extra={"rng": rng.bit_generator.state, "note": "x"})
+    with np.load(p, allow_pickle=False) as z:
+        assert set(z.files) == {"version", "params", "m", "v", "step", "extra"}
+    r, extra = sur.Surrogate.load(p, device="cpu")
+    assert torch.equal(r.params, m.params) and torch.equal(r.m, m.m) and torch.equal(r.v, m.v)
+    assert r.step_count == 123 and extra["note"] == "x"
+    assert extra["rng"] == rng.bit_generator.state
