@@ -271,18 +271,69 @@ def run_surrogate(args, spk, spkgen, torch, np):
     checks["surrogate"] = dict(host=held.host, H=H, W=W, T=T, times=eval_times,
                                y=np.stack(ys), est=np.stack(ests), mux=np.stack(muxs),
                                plain_long=np.stack(plain_long))
+    # the same training step at the largest batch the plans take (64 crops
+    # of 128x128, 1 M px per step): the step's MFMA utilisation when
+    # launch latency is amortised (timing only; the network is discarded)
+    Bl, Hl, Wl, nl = 64, 128, 128, 60
+    big = sur.Surrogate(seed=0)
+    rng_l = np.random.default_rng(3)
+    plan = sur.TrainPlan(big, [scenes.samples(rng_l, Bl, Hl, Wl) for _ in range(nl)],
+                         [lr] * nl, Hl, Wl)
+    plan.run(10)
+    torch.cuda.synchronize()
+    e0.record()
+    plan.run(nl - 10)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_l = e0.elapsed_time(e1) / (nl - 10)
+    plan.close()
+    del big
+    tf_l = SUR_TRAIN_FLOP_PER_PX * Bl * Hl * Wl / (ms_l * 1e-3) / 1e12
+    out["surrogate"]["large_batch_step"] = {
+        "batch": "%d crops of %dx%d" % (Bl, Hl, Wl), "ms_per_step": round(ms_l, 4),
+        "tflops": round(tf_l, 2), "mfma_frac": round(tf_l / MFMA_BF16_PEAK_TFLOPS, 5)}
     del scenes, held
     torch.cuda.empty_cache()
-    out["streaming"], checks["streaming"] = run_streaming(args, spk, spkgen, torch, np, model, sur)
+    # a second network for the moving streaming scene: the same training on
+    # block scenes that translate at up to 2 px/frame (the streaming
+    # scene's generator, other seeds), whole-stream targets
+    t0 = time.perf_counter()
+    print("surrogate: %d moving training scenes" % args.sur_moving_scenes, file=sys.stderr,
+          flush=True)
+    mscenes = sur.SceneSet([40000 + i for i in range(args.sur_moving_scenes)], H=H, W=W, T=T,
+                           moving=True, keep_host=False)
+    mgen_s = time.perf_counter() - t0
+    motion = sur.Surrogate(seed=0)
+    rng = np.random.default_rng(2)
+    plan = sur.TrainPlan(motion, [mscenes.samples(rng, B, Hc, Wc) for _ in range(steps)],
+                         [lr * 0.5 * (1 + math.cos(math.pi * k / steps)) for k in range(steps)],
+                         Hc, Wc)
+    e0.record()
+    plan.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    mper = plan.losses()
+    out["surrogate"]["moving_model"] = {
+        "workload": "blocks_250x400_T4096 translating at up to 2 px/frame: %d training scenes "
+                    "(seeds 40000+), whole-stream targets" % args.sur_moving_scenes,
+        "train_steps": steps, "train_ms_per_step": round(e0.elapsed_time(e1) / steps, 3),
+        "loss_curve": [float("%.4g" % float(mper[k:k + chunk].mean()))
+                       for k in range(0, steps, chunk)],
+        "data_gen_s": round(mgen_s, 1)}
+    plan.close()
+    del mscenes
+    torch.cuda.empty_cache()
+    out["streaming"], checks["streaming"] = run_streaming(args, spk, spkgen, torch, np, motion,
+                                                          sur, static_model=model)
     return out, checks
 
 
 def _streaming_scene(spkgen, np, H, W, T):
     """The streaming workload: blocks translating at one velocity,
     |v| in (0, 2] px/frame, direction and speed from seed 5."""
-    speed = 2.0 * (1.0 - spkgen.rng_u64(5, 7, 0) / 2.0 ** 64)    # (0, 2]
-    ang = 2.0 * np.pi * (spkgen.rng_u64(5, 7, 1) / 2.0 ** 64)
-    vx, vy = speed * np.cos(ang), speed * np.sin(ang)
+    import paper_2412_11639_amd.surrogate as sur
+    vx, vy = sur.scene_velocity(5)
+    speed = math.hypot(vx, vy)
     print("streaming: generating %dx%dx%d" % (H, W, T), file=sys.stderr, flush=True)
     return spkgen.blocks(H, W, T, 5, vx=vx, vy=vy), speed, vx, vy
 
@@ -436,13 +487,15 @@ def run_encoded(args, spk, spkgen, torch, np):
     return res
 
 
-def run_streaming(args, spk, spkgen, torch, np, model, sur):
+def run_streaming(args, spk, spkgen, torch, np, model, sur, static_model=None):
     """1000x1000 blocks translating at one velocity, |v| in (0, 2] px/frame
-    (seed 5).  Per frame: advance the 32-frame window, run the surrogate and
-    the fallback mux; latency from HIP events around each frame.  Beside it
-    the plain method two ways: one pass over the whole stream with an output
-    every frame, and the latency-bound form that re-scans the last 4096
-    frames for each output frame."""
+    (seed 5).  Per frame: advance the 32-frame window, run the surrogate
+    (``model``, trained on moving scenes) and the fallback mux; latency from
+    HIP events around each frame.  At the checked frames the network trained
+    on static scenes (``static_model``) runs too, outside the timed region.
+    Beside it the plain method two ways: one pass over the whole stream with
+    an output every frame, and the latency-bound form that re-scans the last
+    4096 frames for each output frame."""
     H = W = 1000
     T = args.stream_frames
     s, speed, vx, vy = _streaming_scene(spkgen, np, H, W, T)
@@ -454,8 +507,11 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     mx = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
     n_check = min(400, T - 31)
     check_t = sorted(set(np.linspace(31, T - 1, n_check).astype(int).tolist()))
+    names = ["surrogate", "surrogate_with_fallback", "plain_short_window"]
+    if static_model is not None:
+        names.append("surrogate_static_trained")
     kept = {k: torch.empty((len(check_t), H, W), dtype=torch.float32, device="cuda")
-            for k in ("surrogate", "surrogate_with_fallback", "plain_short_window")}
+            for k in names}
     slot = {t: i for i, t in enumerate(check_t)}
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(T)]
@@ -475,6 +531,8 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
             kept["surrogate"][slot[t]].copy_(y[0])
             kept["surrogate_with_fallback"][slot[t]].copy_(mx[0])
             kept["plain_short_window"][slot[t]].copy_(est[0])
+            if static_model is not None:
+                static_model.infer(win, est, out=kept["surrogate_static_trained"][slot[t]][None])
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     lat = np.array([evs[t][0].elapsed_time(evs[t][1]) for t in range(31, T)])
@@ -504,6 +562,22 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1)
     plain_kept = plain_out[[t - 31 for t in check_t]].cpu().numpy()
+    # the live form: the same stream fed 32 frames at a time (the paper's
+    # hardware block), each pixel's state kept on the device between pieces,
+    # the same every-frame outputs
+    plain_out.fill_(-1.0)
+    live = spk.Stream(H, W, 1.0, frames, order=spk.FSR, out=plain_out)
+    torch.cuda.synchronize()
+    e0.record()
+    for a in range(0, T, 32):
+        live.feed(ds[a:a + 32])
+    live.finish()
+    e1.record()
+    torch.cuda.synchronize()
+    live_ms = e0.elapsed_time(e1)
+    live_same = bool(np.array_equal(plain_out[[t - 31 for t in check_t]].cpu().numpy(),
+                                    plain_kept))
+    live.close()
     # the same through the segment encoding: one pass writes each pixel's
     # segment list, a second expands it to every frame
     enc = _encoded_leg(spk, torch, ds, H, W, T, frames, plain_out,
@@ -535,6 +609,10 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
            "plain_single_pass": {"mpx_frames_per_s": round(H * W * T / (plain_ms * 1e-3) / 1e6, 1),
                                  "ms": round(plain_ms, 3),
                                  "outputs": "every frame 31..%d" % (T - 1)},
+           "plain_live_32_frame_pieces": {
+               "mpx_frames_per_s": round(H * W * T / (live_ms * 1e-3) / 1e6, 1),
+               "ms": round(live_ms, 3), "pieces": (T + 31) // 32,
+               "equals_single_pass": live_same},
            "plain_encoded": enc,
            "plain_rescan_%d" % Wn: {"mpx_frames_per_s": round(H * W / (rs_ms * 1e-3) / 1e6, 1),
                                     "latency_ms": round(rs_ms, 4)},
@@ -544,9 +622,7 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur):
     # the scene itself (the generator's per-frame intensity) as a third reference
     truth = spkgen.blocks_truth(H, W, check_t, 5, vx=vx, vy=vy)
     check["truth"] = truth
-    res["vs_scene_truth_psnr_db"] = {
-        k: round(_psnr(check[k], truth, np), 2)
-        for k in ("surrogate", "surrogate_with_fallback", "plain_short_window")}
+    res["vs_scene_truth_psnr_db"] = {k: round(_psnr(check[k], truth, np), 2) for k in names}
     res["vs_scene_truth_psnr_db"]["plain_whole_stream"] = round(_psnr(plain_kept, truth, np), 2)
     del ds, kept
     torch.cuda.empty_cache()
@@ -688,12 +764,10 @@ def cpu_baseline_leg(args, plain, batched, sur_checks, res, np):
             if r is None:
                 r = oracle.reconstruct(c["stream"], c["H"], c["W"], c["T"], 1.0, c["times"],
                                        order=1, nthreads=n, causal=True)
-            q[name] = {"psnr_db": {k: round(_psnr(c[k], r, np), 2)
-                                   for k in ("surrogate", "surrogate_with_fallback",
-                                             "plain_short_window")},
-                       "max_abs": {k: float("%.4g" % np.abs(c[k] - r).max())
-                                   for k in ("surrogate", "surrogate_with_fallback",
-                                             "plain_short_window")}}
+            keys = [k for k in ("surrogate", "surrogate_with_fallback", "plain_short_window",
+                                "surrogate_static_trained") if k in c]
+            q[name] = {"psnr_db": {k: round(_psnr(c[k], r, np), 2) for k in keys},
+                       "max_abs": {k: float("%.4g" % np.abs(c[k] - r).max()) for k in keys}}
             if name == "causal":
                 res["streaming"]["vs_scene_truth_psnr_db"]["plain_causal"] = round(
                     _psnr(r, c["truth"], np), 2)
@@ -783,6 +857,7 @@ def main():
                     help="skip the FSR/SSR/TFI/TFP quality comparison")
     ap.add_argument("--sur-steps", type=int, default=3000)
     ap.add_argument("--sur-scenes", type=int, default=256)
+    ap.add_argument("--sur-moving-scenes", type=int, default=128)
     ap.add_argument("--stream-frames", type=int, default=40000,
                     help="frames of the 1000x1000 streaming run (the configuration's 40000)")
     ap.add_argument("--parse-rocprof", default=None)

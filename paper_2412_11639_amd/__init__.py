@@ -215,12 +215,15 @@ class Stream:
     calls go on one HIP stream (the current one unless given)."""
 
     def __init__(self, H: int, W: int, theta: float, t_out, order: int = FSR,
-                 windows: bool = False, device="cuda"):
+                 windows: bool = False, device="cuda", out: torch.Tensor | None = None):
         import ctypes
         self.H, self.W = int(H), int(W)
         self._t, tp = _host_times(t_out)
         n_out = len(self._t)
-        self.out = torch.empty((n_out, H, W), dtype=torch.float32, device=device)
+        if out is None:
+            out = torch.empty((n_out, H, W), dtype=torch.float32, device=device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n_out * H * W
+        self.out = out
         self.windows = None
         if windows:
             self.windows = tuple(torch.empty((n_out, H, W), dtype=torch.int32, device=device)
