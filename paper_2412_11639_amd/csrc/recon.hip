@@ -164,6 +164,65 @@ __global__ __launch_bounds__(64) void fixup_kernel(ReconParams P, int nblocks, C
                 ncv = P.cnt_le[f];
             }
         };
+        // The stopping rules, tried after the true and the speculative
+        // machines have both taken the spike at tau (see above).
+        auto stop_checks = [&](int32_t tau) {
+            if (ORDER == 1 && rc.fb1 >= tau && tr.st.flo <= sp.st.flo &&
+                sp.st.fhi <= tr.st.fhi &&
+                max(tr.st.fhi, rc.fwhi) - min(tr.st.flo, rc.fwlo) <= 1) {
+                // FSR: the true window holds the speculative one and stays
+                // stable with every interval up to the main pass's next
+                // cut, so the true machine makes that same cut next and
+                // both restart there: close the true segment at that cut
+                // and take the main pass's record from then on
+                em.close(tr.first, rc.fb1, cum_start + rc.fi1 - tr.first_idx, tr.k0,
+                         P.cnt_le[rc.fb1]);
+                tr = rc;
+                tr.cum = cum_start + rc.cum;
+                tr.first_idx = cum_start + rc.first_idx;
+                done = true;
+            } else if (ORDER == 1 && rc.lastb < tau && tr.st.flo <= sp.st.flo &&
+                sp.st.fhi <= tr.st.fhi &&
+                max(tr.st.fhi, rc.st.fhi) - min(tr.st.flo, rc.st.flo) <= 1) {
+                // FSR: the main pass makes no cut after this spike, the
+                // true window holds the speculative one, and together
+                // with every interval still to come (the main pass's final
+                // window) it stays stable: no true cut either, and the
+                // true window at the chunk's end is the union
+                const int32_t first = tr.first, first_idx = tr.first_idx, k0 = tr.k0;
+                const int32_t flo = min(tr.st.flo, rc.st.flo), fhi = max(tr.st.fhi, rc.st.fhi);
+                tr = rc;
+                tr.cum = cum_start + rc.cum;
+                tr.first = first;
+                tr.first_idx = first_idx;
+                tr.k0 = k0;
+                tr.st.flo = flo;
+                tr.st.fhi = fhi;
+                done = true;
+            } else if (same_decisions<ORDER>(tr.st, sp.st)) {
+                if (rc.lastb < tau) {
+                    const int32_t first = tr.first, first_idx = tr.first_idx, k0 = tr.k0;
+                    tr = rc;
+                    tr.cum = cum_start + rc.cum;
+                    tr.first = first;
+                    tr.first_idx = first_idx;
+                    tr.k0 = k0;
+                    done = true;
+                } else if (tr.first == sp.first && tr.k0 >= sp.k0) {
+                    // same open segment: the main pass writes its outputs
+                    // from the chunk's start on (those it gave it below
+                    // tr.k0 were rewritten by this pass); earlier ones
+                    // are written here, from the main pass's record of
+                    // where this segment closes
+                    if (tr.k0 < kmin && rc.fb1 >= 0)
+                        em.close(tr.first, rc.fb1, rc.fn1, tr.k0, kmin);
+                    tr = rc;
+                    tr.cum = cum_start + rc.cum;
+                    tr.first_idx = cum_start + rc.first_idx;
+                    done = true;
+                }
+            }
+        };
         if (__any(!done)) fetch(tile0);
         for (int32_t t = tile0; t < tile1 && __any(!done); t++) {
             const uint32_t lo = nlo, hi = nhi;
@@ -171,6 +230,29 @@ __global__ __launch_bounds__(64) void fixup_kernel(ReconParams P, int nblocks, C
             fetch(t + 1);
             uint64_t w = transpose64(lo, hi, X, lane);
             __syncthreads();
+            // A word that cuts neither machine is taken whole by both with
+            // the main pass's word shortcut; the stopping rules are then
+            // tried at its last spike.  Without it a chunk whose speculative
+            // state never becomes equivalent to the true one (constant
+            // light: the true S2 extremes hold gaps the warm-up never saw)
+            // would be replayed spike by spike to its end.
+            if (!done && w && tr.lastspk >= 0 && tr.lastspk == sp.lastspk) {
+                const int32_t c = popc64(w);
+                const int32_t x0 = t * 64 + ctz64(w) - tr.lastspk;
+                SegState a = tr.st, b = sp.st;
+                if (a.template fast_word<ORDER>(w, x0, c) &&
+                    b.template fast_word<ORDER>(w, x0, c)) {
+                    tr.st = a;
+                    sp.st = b;
+                    const int hp = hibit64(w);
+                    const int32_t tau = t * 64 + hp;
+                    tr.lastspk = sp.lastspk = tau;
+                    tr.cum += c;
+                    tr.cnt_last = cnt_s[hp];
+                    w = 0;
+                    stop_checks(tau);
+                }
+            }
             while (!done && w) {
                 const int pos = ctz64(w);
                 w &= w - 1;
@@ -194,61 +276,7 @@ __global__ __launch_bounds__(64) void fixup_kernel(ReconParams P, int nblocks, C
                 tr.lastspk = sp.lastspk = tau;
                 tr.cum++;
                 tr.cnt_last = cnt_s[pos];
-                if (ORDER == 1 && rc.fb1 >= tau && tr.st.flo <= sp.st.flo &&
-                    sp.st.fhi <= tr.st.fhi &&
-                    max(tr.st.fhi, rc.fwhi) - min(tr.st.flo, rc.fwlo) <= 1) {
-                    // FSR: the true window holds the speculative one and stays
-                    // stable with every interval up to the main pass's next
-                    // cut, so the true machine makes that same cut next and
-                    // both restart there: close the true segment at that cut
-                    // and take the main pass's record from then on
-                    em.close(tr.first, rc.fb1, cum_start + rc.fi1 - tr.first_idx, tr.k0,
-                             P.cnt_le[rc.fb1]);
-                    tr = rc;
-                    tr.cum = cum_start + rc.cum;
-                    tr.first_idx = cum_start + rc.first_idx;
-                    done = true;
-                } else if (ORDER == 1 && rc.lastb < tau && tr.st.flo <= sp.st.flo &&
-                    sp.st.fhi <= tr.st.fhi &&
-                    max(tr.st.fhi, rc.st.fhi) - min(tr.st.flo, rc.st.flo) <= 1) {
-                    // FSR: the main pass makes no cut after this spike, the
-                    // true window holds the speculative one, and together
-                    // with every interval still to come (the main pass's final
-                    // window) it stays stable: no true cut either, and the
-                    // true window at the chunk's end is the union
-                    const int32_t first = tr.first, first_idx = tr.first_idx, k0 = tr.k0;
-                    const int32_t flo = min(tr.st.flo, rc.st.flo), fhi = max(tr.st.fhi, rc.st.fhi);
-                    tr = rc;
-                    tr.cum = cum_start + rc.cum;
-                    tr.first = first;
-                    tr.first_idx = first_idx;
-                    tr.k0 = k0;
-                    tr.st.flo = flo;
-                    tr.st.fhi = fhi;
-                    done = true;
-                } else if (same_decisions<ORDER>(tr.st, sp.st)) {
-                    if (rc.lastb < tau) {
-                        const int32_t first = tr.first, first_idx = tr.first_idx, k0 = tr.k0;
-                        tr = rc;
-                        tr.cum = cum_start + rc.cum;
-                        tr.first = first;
-                        tr.first_idx = first_idx;
-                        tr.k0 = k0;
-                        done = true;
-                    } else if (tr.first == sp.first && tr.k0 >= sp.k0) {
-                        // same open segment: the main pass writes its outputs
-                        // from the chunk's start on (those it gave it below
-                        // tr.k0 were rewritten by this pass); earlier ones
-                        // are written here, from the main pass's record of
-                        // where this segment closes
-                        if (tr.k0 < kmin && rc.fb1 >= 0)
-                            em.close(tr.first, rc.fb1, rc.fn1, tr.k0, kmin);
-                        tr = rc;
-                        tr.cum = cum_start + rc.cum;
-                        tr.first_idx = cum_start + rc.first_idx;
-                        done = true;
-                    }
-                }
+                stop_checks(tau);
             }
             __syncthreads();
         }

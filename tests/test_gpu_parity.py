@@ -282,6 +282,23 @@ def test_time_chunks_static_and_moving_blocks(spk, chunks, order, n_chunks):
                 list(range(3, T, 11)), order)
 
 
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("n_chunks", [2, 6, 16])
+def test_time_chunks_constant_light_full_frame(spk, chunks, order, n_chunks):
+    """The small static workload (250x400, 1024 frames, constant light per
+    16x16 block) cut into chunks: the fixup takes words that cut neither
+    the true nor the speculative machine whole, and its result equals the
+    oracle and the unchunked run."""
+    H, W, T = 250, 400, 1024
+    s = spkgen.blocks(H, W, T, seed=1)
+    t_out = [64 + 128 * k for k in range(8)] + [0, T - 1]
+    chunks(0)
+    ref = spk.reconstruct(dev(s), H, W, T, 1.0, t_out, order=order).cpu().numpy()
+    chunks(n_chunks)
+    out = check_recon(spk, s, H, W, T, t_out, order)
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("n_chunks", [5, 64])
 def test_time_chunks_sparse_and_edge_pixels(spk, chunks, n_chunks):
     """Pixels whose first spike, or only spikes, fall in late chunks; chunks
