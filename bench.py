@@ -457,6 +457,32 @@ def run_forward(args, spk, spkgen, torch, np):
                 "output": H * W * (64 + 4 + 4)}}
 
 
+def run_train_step(args, spk, spkgen, torch, np):
+    """The surrogate's graph-replayed training step alone, at the largest
+    batch the plans take (64 crops of 128x128, 1 M px per step), on
+    ``--sur-scenes`` static block scenes: 10 warm-up steps, then 30 timed."""
+    import paper_2412_11639_amd.surrogate as sur
+    B, Hc, Wc, n = 64, 128, 128, 40
+    scenes = sur.SceneSet([10000 + i for i in range(args.sur_scenes)], H=250, W=400, T=4096,
+                          keep_host=False)
+    model = sur.Surrogate(seed=0)
+    rng = np.random.default_rng(1)
+    plan = sur.TrainPlan(model, [scenes.samples(rng, B, Hc, Wc) for _ in range(n)], [3e-4] * n,
+                         Hc, Wc)
+    plan.run(10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.run(n - 10)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (n - 10)
+    plan.close()
+    tf = SUR_TRAIN_FLOP_PER_PX * B * Hc * Wc / (ms * 1e-3) / 1e12
+    return {"batch": "%d crops of %dx%d" % (B, Hc, Wc), "ms_per_step": round(ms, 4),
+            "tflops": round(tf, 2), "mfma_frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 5)}
+
+
 def run_encoded(args, spk, spkgen, torch, np):
     """The streaming scene's plain single pass (every frame from 31 on)
     and the same through segment lists + decode, nothing else."""
@@ -849,6 +875,8 @@ def main():
     ap.add_argument("--only-surrogate", action="store_true")
     ap.add_argument("--only-forward", action="store_true",
                     help="only the surrogate forward at 1000x1000")
+    ap.add_argument("--only-train-step", action="store_true",
+                    help="only the surrogate training step at 64 crops of 128x128")
     ap.add_argument("--only-encoded", action="store_true",
                     help="only the streaming scene's single pass and segment lists + decode")
     ap.add_argument("--no-other-paths", action="store_true",
@@ -885,7 +913,8 @@ def main():
     import paper_2412_11639_amd as spk
     import spkgen
 
-    if args.only_batched or args.only_surrogate or args.only_encoded or args.only_forward:
+    if (args.only_batched or args.only_surrogate or args.only_encoded or args.only_forward
+            or args.only_train_step):
         args.no_cpu_baseline = True
         out = {}
         if args.copy_calibration:
@@ -898,6 +927,8 @@ def main():
             out["encoded"] = run_encoded(args, spk, spkgen, torch, np)
         if args.only_forward:
             out["forward"] = run_forward(args, spk, spkgen, torch, np)
+        if args.only_train_step:
+            out["train_step"] = run_train_step(args, spk, spkgen, torch, np)
         if args.only_batched:
             out["batched"] = run_batched(args, spk, spkgen, torch, np)[0]
         if args.only_surrogate:

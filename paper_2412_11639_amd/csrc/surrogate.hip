@@ -715,34 +715,47 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
                     *(uint4 *)(&aT[dx][part * 8 + 2 * e2 + 1][r * 16 + cc0]) = hi;
                 }
             }
-        } else
-        for (int it = tid; it < 18 * 18 * (4 + NE); it += 256) {
-            const int q = it / (4 + NE), part = it % (4 + NE);
-            const int r = q / 18, c = q % 18;
-            const int y = ty0 - 1 + r, x = tx0 - 1 + c;
-            const bool in = y >= 0 && y < A.Hc && x >= 0 && x < A.Wc;
-            const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-            if (part < 4) {
-                bf16x8 v;
+        } else {
+            // first layer: item (dx, part, r, seg) is 8 pixels x the 8 bit
+            // channels of byte `part` of their windows, transposed in
+            // registers (an 8 x 8 bit transpose) into 8 channel rows of 8
+            // bfloat16 ones and zeros, each one 16-byte store; part 4 is
+            // the estimate channel of the same 8 pixels
+            for (int it = tid; it < 3 * (4 + NE) * 18 * 2; it += 256) {
+                const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
+                const int part = rest % (4 + NE), dx = rest / (4 + NE), cc0 = 8 * seg;
+                const int y = ty0 - 1 + r;
+                const bool yin = y >= 0 && y < A.Hc;
+                if (part < 4) {
+                    uint64_t m = 0;  // byte j: pixel j's channels part*8 .. +7
 #pragma unroll
-                for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
-                if (in) {
-                    if constexpr (K == WG_FIRST) v = bits_to_bf16((A.win[pix] >> (8 * part)) & 0xFFu);
-                    else v = *(const bf16x8 *)(A.a + pix * C + part * 8);
-                }
+                    for (int j = 0; j < 8; j++) {
+                        const int x = tx0 - 1 + cc0 + dx + j;
+                        if (yin && x >= 0 && x < A.Wc)
+                            m |= (uint64_t)((A.win[((int64_t)b * A.Hc + y) * A.Wc + x] >>
+                                             (8 * part)) & 0xFFu) << (8 * j);
+                    }
+                    // byte e of m becomes channel e's bits over pixels 0 .. 7
+                    uint64_t t = (m ^ (m >> 7)) & 0x00AA00AA00AA00AAull;
+                    m ^= t ^ (t << 7);
+                    t = (m ^ (m >> 14)) & 0x0000CCCC0000CCCCull;
+                    m ^= t ^ (t << 14);
+                    t = (m ^ (m >> 28)) & 0x00000000F0F0F0F0ull;
+                    m ^= t ^ (t << 28);
 #pragma unroll
-                for (int dx = 0; dx < 3; dx++) {
-                    const int cc = c - dx;
-                    if (cc >= 0 && cc < 16)
+                    for (int e = 0; e < 8; e++)
+                        *(bf16x8 *)(&aT[dx][part * 8 + e][r * 16 + cc0]) =
+                            bits_to_bf16((uint32_t)(m >> (8 * e)) & 0xFFu);
+                } else if constexpr (NE) {
+                    bf16x8 v;
 #pragma unroll
-                        for (int e = 0; e < 8; e++) aT[dx][part * 8 + e][r * 16 + cc] = v[e];
-                }
-            } else if constexpr (NE) {
-                const __bf16 v = in ? to_bf16(A.est[pix]) : (__bf16)0.0f;
-#pragma unroll
-                for (int dx = 0; dx < 3; dx++) {
-                    const int cc = c - dx;
-                    if (cc >= 0 && cc < 16) aT[dx][32][r * 16 + cc] = v;
+                    for (int j = 0; j < 8; j++) {
+                        const int x = tx0 - 1 + cc0 + dx + j;
+                        v[j] = yin && x >= 0 && x < A.Wc
+                                   ? to_bf16(A.est[((int64_t)b * A.Hc + y) * A.Wc + x])
+                                   : (__bf16)0.0f;
+                    }
+                    *(bf16x8 *)(&aT[dx][32][r * 16 + cc0]) = v;
                 }
             }
         }
