@@ -665,16 +665,39 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
             if (y < A.Hc && x < A.Wc) v = A.gy[((int64_t)b * A.Hc + y) * A.Wc + x];
             gT[0][px] = to_bf16(v);
         } else {
-            for (int it = tid; it < 256 * 4; it += 256) {
-                const int px = it >> 2, part = it & 3;
-                const int y = ty0 + px / 16, x = tx0 + px % 16;
-                bf16x8 v;
+            // item (part, seg): pixels 8 seg .. 8 seg + 7 x channels part*8 ..
+            // +7, loaded as 8 channel vectors, transposed in registers and
+            // written as 8 channel rows of 16 bytes
+            for (int it = tid; it < 4 * 32; it += 256) {
+                const int seg = it & 31, part = it >> 5, px0 = 8 * seg;
+                const int y = ty0 + px0 / 16;
+                uint32_t m[8][4];  // pixel j: channels part*8 .. +7 in pairs
 #pragma unroll
-                for (int e = 0; e < 8; e++) v[e] = (__bf16)0.0f;
-                if (y < A.Hc && x < A.Wc)
-                    v = *(const bf16x8 *)(A.g + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8);
+                for (int j = 0; j < 8; j++) {
+                    const int x = tx0 + px0 % 16 + j;
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (y < A.Hc && x < A.Wc)
+                        v = *(const uint4 *)(A.g + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
+                                             part * 8);
+                    m[j][0] = v.x;
+                    m[j][1] = v.y;
+                    m[j][2] = v.z;
+                    m[j][3] = v.w;
+                }
 #pragma unroll
-                for (int e = 0; e < 8; e++) gT[part * 8 + e][px] = v[e];
+                for (int e2 = 0; e2 < 4; e2++) {
+                    uint4 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 7
+                    lo.x = (m[0][e2] & 0xFFFFu) | (m[1][e2] << 16);
+                    lo.y = (m[2][e2] & 0xFFFFu) | (m[3][e2] << 16);
+                    lo.z = (m[4][e2] & 0xFFFFu) | (m[5][e2] << 16);
+                    lo.w = (m[6][e2] & 0xFFFFu) | (m[7][e2] << 16);
+                    hi.x = (m[0][e2] >> 16) | (m[1][e2] & 0xFFFF0000u);
+                    hi.y = (m[2][e2] >> 16) | (m[3][e2] & 0xFFFF0000u);
+                    hi.z = (m[4][e2] >> 16) | (m[5][e2] & 0xFFFF0000u);
+                    hi.w = (m[6][e2] >> 16) | (m[7][e2] & 0xFFFF0000u);
+                    *(uint4 *)(&gT[part * 8 + 2 * e2][px0]) = lo;
+                    *(uint4 *)(&gT[part * 8 + 2 * e2 + 1][px0]) = hi;
+                }
             }
         }
         // activation halo, rows ty0-1 .. ty0+16, columns tx0-1 .. tx0+16,
