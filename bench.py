@@ -338,29 +338,40 @@ def _streaming_scene(spkgen, np, H, W, T):
     return spkgen.blocks(H, W, T, 5, vx=vx, vy=vy), speed, vx, vy
 
 
-def _encoded_leg(spk, torch, ds, H, W, T, frames, out, ref_idx, ref_kept):
+def _encoded_leg(spk, torch, ds, H, W, T, frames, out, ref_idx, ref_kept, packed=True):
     """The plain method through the segment encoding (FSR): spk_segments
     writes each pixel's segment list, spk_decode expands it to every frame
-    in ``frames`` (into ``out``).  Times both on the second of two runs;
-    ``ref_kept`` (planes ``ref_idx`` of the single-pass output) checks the
-    decoded frames.  The decoder's roofline is HBM: algorithmic bytes are
-    the lists it reads (12 B per segment plus the counts) and the frames it
-    writes."""
+    in ``frames`` (into ``out``); with ``packed`` the lists are laid out per
+    pixel (spk_segments_packed / spk_decode_packed), else as [cap][H*W]
+    arrays.  Times both on the second of two runs; ``ref_kept`` (planes
+    ``ref_idx`` of the single-pass output) checks the decoded frames.  The
+    decoder's roofline is HBM: algorithmic bytes are the lists it reads
+    (12 B per segment plus the counts) and the frames it writes."""
     cnt = spk.segments(ds, H, W, T, order=spk.FSR, cap=0)[3]
     cap = max(1, int(cnt.max().item()))
-    seg = [torch.empty((cap, H * W), dtype=torch.int32, device="cuda") for _ in range(3)]
+    if packed:
+        seg = [torch.empty((H * W, cap, 3), dtype=torch.int32, device="cuda")]
+    else:
+        seg = [torch.empty((cap, H * W), dtype=torch.int32, device="cuda") for _ in range(3)]
     lib = spk._lib.load()
     tp = (ctypes.c_int32 * len(frames))(*frames)
     e0, e_mid, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
 
     def encoded():
-        rc = lib.spk_segments(ds.data_ptr(), H, W, T, spk.FSR, cap, seg[0].data_ptr(),
-                              seg[1].data_ptr(), seg[2].data_ptr(), cnt.data_ptr(),
-                              torch.cuda.current_stream().cuda_stream)
-        e_mid.record()
-        rc |= lib.spk_decode(seg[0].data_ptr(), seg[1].data_ptr(), seg[2].data_ptr(),
-                             cnt.data_ptr(), cap, H, W, T, 1.0, tp, len(frames),
-                             out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        st = torch.cuda.current_stream().cuda_stream
+        if packed:
+            rc = lib.spk_segments_packed(ds.data_ptr(), H, W, T, spk.FSR, cap, seg[0].data_ptr(),
+                                         cnt.data_ptr(), st)
+            e_mid.record()
+            rc |= lib.spk_decode_packed(seg[0].data_ptr(), cnt.data_ptr(), cap, H, W, T, 1.0, tp,
+                                        len(frames), out.data_ptr(), st)
+        else:
+            rc = lib.spk_segments(ds.data_ptr(), H, W, T, spk.FSR, cap, seg[0].data_ptr(),
+                                  seg[1].data_ptr(), seg[2].data_ptr(), cnt.data_ptr(), st)
+            e_mid.record()
+            rc |= lib.spk_decode(seg[0].data_ptr(), seg[1].data_ptr(), seg[2].data_ptr(),
+                                 cnt.data_ptr(), cap, H, W, T, 1.0, tp, len(frames),
+                                 out.data_ptr(), st)
         assert rc == 0
 
     encoded()
@@ -375,7 +386,9 @@ def _encoded_leg(spk, torch, ds, H, W, T, frames, out, ref_idx, ref_kept):
     dec_bytes = seg_bytes + H * W * 4 + len(frames) * H * W * 4
     achieved = dec_bytes / (dec_ms * 1e-3) / 1e9
     del seg
-    return {"mpx_frames_per_s": round(H * W * T / ((enc_ms + dec_ms) * 1e-3) / 1e6, 1),
+    torch.cuda.empty_cache()
+    return {"layout": "per pixel [H*W][cap][3]" if packed else "[cap][H*W] x 3",
+            "mpx_frames_per_s": round(H * W * T / ((enc_ms + dec_ms) * 1e-3) / 1e6, 1),
             "segments_ms": round(enc_ms, 3), "decode_ms": round(dec_ms, 3),
             "segment_bytes": seg_bytes, "cap": cap, "equals_single_pass": same,
             "decode_roofline": {"bound": "hbm", "achieved": round(achieved, 1),
@@ -507,7 +520,9 @@ def run_encoded(args, spk, spkgen, torch, np):
            "plain_single_pass": {"mpx_frames_per_s": round(H * W * T / (plain_ms * 1e-3) / 1e6, 1),
                                  "ms": round(plain_ms, 3),
                                  "outputs": "every frame 31..%d" % (T - 1)},
-           "plain_encoded": _encoded_leg(spk, torch, ds, H, W, T, frames, out, idx, kept)}
+           "plain_encoded": _encoded_leg(spk, torch, ds, H, W, T, frames, out, idx, kept),
+           "plain_encoded_planar": _encoded_leg(spk, torch, ds, H, W, T, frames, out, idx, kept,
+                                                packed=False)}
     del ds, out
     torch.cuda.empty_cache()
     return res
@@ -608,6 +623,8 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur, static_model=None):
     # segment list, a second expands it to every frame
     enc = _encoded_leg(spk, torch, ds, H, W, T, frames, plain_out,
                        [t - 31 for t in check_t], plain_kept)
+    enc_planar = _encoded_leg(spk, torch, ds, H, W, T, frames, plain_out,
+                              [t - 31 for t in check_t], plain_kept, packed=False)
     del plain_out
     # plain, latency-bound: re-scan the last Wn frames for one output frame
     Wn = min(4096, T)
@@ -640,6 +657,7 @@ def run_streaming(args, spk, spkgen, torch, np, model, sur, static_model=None):
                "ms": round(live_ms, 3), "pieces": (T + 31) // 32,
                "equals_single_pass": live_same},
            "plain_encoded": enc,
+           "plain_encoded_planar": enc_planar,
            "plain_rescan_%d" % Wn: {"mpx_frames_per_s": round(H * W / (rs_ms * 1e-3) / 1e6, 1),
                                     "latency_ms": round(rs_ms, 4)},
            "wall_s": round(wall, 2)}

@@ -209,6 +209,23 @@ int spk_decode(const int32_t *seg_first, const int32_t *seg_last, const int32_t 
                const int32_t *t_out, int32_t n_out, float *out, void *hip_stream);
 
 /*
+ * The same segment lists kept contiguous per pixel (Sec. III-B
+ * segmentation, Sec. III-C encoder/decoder): rec is device int32
+ * [H*W][cap][3], segment s of pixel p at rec[(p * cap + s) * 3 + {0, 1, 2}]
+ * = (first spike frame, last spike frame, number of intervals), the same
+ * values spk_segments stores at s * H*W + p.  Each pixel's list is one run
+ * of memory, so the encoder fills whole lines and the decoder reads each
+ * line once (with the [cap][H*W] arrays every record load of a wave takes
+ * 64 separate lines).  count, cap, the other arguments and errors as
+ * spk_segments / spk_decode; with cap == 0 rec may be NULL.
+ */
+int spk_segments_packed(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
+                        int32_t cap, int32_t *rec, int32_t *count, void *hip_stream);
+int spk_decode_packed(const int32_t *rec, const int32_t *count, int32_t cap, int32_t H, int32_t W,
+                      int32_t T, float theta, const int32_t *t_out, int32_t n_out, float *out,
+                      void *hip_stream);
+
+/*
  * Carry-state reconstruction of a live stream (the paper's hardware
  * processes the camera's frames in 32-frame blocks as they arrive,
  * Sec. III-C): frames are fed in pieces of any length, each pixel's state

@@ -23,7 +23,7 @@ TFI = 3
 TSR = 4
 
 __all__ = ["FSR", "SSR", "TFI", "TSR", "SpkError", "tfp", "decode", "motion", "frame_bytes", "reconstruct", "reconstruct_windows",
-           "segments", "version", "set_time_chunks", "get_time_chunks", "Plan",
+           "segments", "segments_packed", "decode_packed", "version", "set_time_chunks", "get_time_chunks", "Plan",
            "PLAN_AUTOTUNE", "PLAN_NO_GRAPH"]
 
 PLAN_AUTOTUNE = 1
@@ -157,6 +157,42 @@ def decode(seg_first, seg_last, seg_n, count, H, W, T, theta, t_out, out=None, s
                                 count.data_ptr(), cap, H, W, T, float(theta), tp, n_out,
                                 out.data_ptr(), _stream_handle(stream))
     _lib.check("spk_decode", rc)
+    return out
+
+
+def segments_packed(stream_t, H, W, T, order=FSR, cap=64, stream=None):
+    """Every segment of every pixel, each pixel's list contiguous: records
+    int32 [H*W, cap, 3] (first, last, n) and the per-pixel total count
+    int32 [H*W]."""
+    _check_stream_tensor(stream_t, H, W, T)
+    dev = stream_t.device
+    hw = H * W
+    rec = torch.empty((hw, cap, 3), dtype=torch.int32, device=dev)
+    if cap:
+        rec[..., :2].fill_(-1)
+        rec[..., 2].zero_()
+    cnt = torch.zeros(hw, dtype=torch.int32, device=dev)
+    rc = _lib.load().spk_segments_packed(stream_t.data_ptr(), H, W, T, order, cap,
+                                         rec.data_ptr(), cnt.data_ptr(), _stream_handle(stream))
+    _lib.check("spk_segments_packed", rc)
+    return rec, cnt
+
+
+def decode_packed(rec, count, H, W, T, theta, t_out, out=None, stream=None):
+    """``decode`` from per-pixel contiguous lists (as ``segments_packed``
+    returns them)."""
+    cap = rec.shape[1]
+    assert rec.dtype == torch.int32 and rec.is_contiguous() and rec.shape == (H * W, cap, 3)
+    assert count.dtype == torch.int32 and count.numel() == H * W
+    t, tp = _host_times(t_out)
+    n_out = len(t)
+    if out is None:
+        out = torch.empty((n_out, H, W), dtype=torch.float32, device=count.device)
+    assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n_out * H * W
+    rc = _lib.load().spk_decode_packed(rec.data_ptr(), count.data_ptr(), cap, H, W, T,
+                                       float(theta), tp, n_out, out.data_ptr(),
+                                       _stream_handle(stream))
+    _lib.check("spk_decode_packed", rc)
     return out
 
 

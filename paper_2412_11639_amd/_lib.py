@@ -55,6 +55,12 @@ def _declare(lib):
     lib.spk_segments.restype = ctypes.c_int
     lib.spk_segments.argtypes = [P_u8, c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32, P_i32,
                                  P_i32, ctypes.c_void_p]
+    lib.spk_segments_packed.restype = ctypes.c_int
+    lib.spk_segments_packed.argtypes = [P_u8, c_i32, c_i32, c_i32, c_i32, c_i32, P_i32, P_i32,
+                                        ctypes.c_void_p]
+    lib.spk_decode_packed.restype = ctypes.c_int
+    lib.spk_decode_packed.argtypes = [P_i32, P_i32, c_i32, c_i32, c_i32, c_i32, ctypes.c_float,
+                                      P_i32, c_i32, P_f32, ctypes.c_void_p]
     for name, argtypes in EXTRA_DECLS.items():
         f = getattr(lib, name)
         f.restype = ctypes.c_int

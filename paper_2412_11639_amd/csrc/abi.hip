@@ -608,14 +608,18 @@ int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t o
     return rc;
 }
 
-int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
-                 int32_t cap, int32_t *seg_first, int32_t *seg_last, int32_t *seg_n,
-                 int32_t *count, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+int segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order, int32_t cap,
+             int32_t *seg_first, int32_t *seg_last, int32_t *seg_n, int32_t *seg_rec,
+             int32_t *count, hipStream_t st)
 {
     int rc = check_common(stream, H, W, T, order);
     if (rc) return rc;
     if (cap < 0 || !count) return SPK_EINVAL;
-    if (cap > 0 && (!seg_first || !seg_last || !seg_n)) return SPK_EINVAL;
+    if (cap > 0 && !seg_rec && (!seg_first || !seg_last || !seg_n)) return SPK_EINVAL;
     if ((int64_t)cap * (int64_t)H * (int64_t)W > ((int64_t)1 << 60)) return SPK_EINVAL;
     std::lock_guard<std::mutex> lock(g_mu);
     int dev = 0;
@@ -630,11 +634,31 @@ int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t
     p.seg_first = seg_first;
     p.seg_last = seg_last;
     p.seg_n = seg_n;
+    p.seg_rec = seg_rec;
     p.count = count;
-    return spk::launch_recon(p, order, spk::MODE_SEGMENTS, spk::ChunkPlan{},
-                             (hipStream_t)hip_stream) == hipSuccess
+    return spk::launch_recon(p, order, spk::MODE_SEGMENTS, spk::ChunkPlan{}, st) == hipSuccess
                ? SPK_OK
                : SPK_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spk_segments(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
+                 int32_t cap, int32_t *seg_first, int32_t *seg_last, int32_t *seg_n,
+                 int32_t *count, void *hip_stream)
+{
+    return segments(stream, H, W, T, order, cap, seg_first, seg_last, seg_n, nullptr, count,
+                    (hipStream_t)hip_stream);
+}
+
+int spk_segments_packed(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order,
+                        int32_t cap, int32_t *rec, int32_t *count, void *hip_stream)
+{
+    if (cap > 0 && !rec) return SPK_EINVAL;
+    return segments(stream, H, W, T, order, cap, nullptr, nullptr, nullptr, rec, count,
+                    (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

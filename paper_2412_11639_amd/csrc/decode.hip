@@ -37,7 +37,11 @@ constexpr int kDecFrames = 32;  // output frames per tile
 // bits at or below the frame) and stored plane by plane, 256 contiguous
 // bytes per plane.  A cursor advance -- its loads and its division -- is
 // paid once per boundary instead of in every frame the wave visits.
-template <bool IDENT, bool AP>
+//
+// PACKED: the lists are [HW][cap][3] (a pixel's records one after another,
+// seg_first pointing at them): a lane's record loads walk its own lines,
+// each fetched once, instead of taking a line of a [cap][HW] row per load.
+template <bool IDENT, bool AP, bool PACKED>
 __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
                                                     const int32_t *seg_last,
                                                     const int32_t *seg_n, const int32_t *count,
@@ -61,10 +65,17 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
     float I = 0.0f;      // S == 0: fewer than two spikes, every output is 0
     int32_t B = INT_MAX;
     auto fetch = [&](int32_t k) {
-        const int64_t o = (int64_t)k * HW + p0 + lane;
-        nf = seg_first[o];
-        nl = seg_last[o];
-        nn = seg_n[o];
+        if constexpr (PACKED) {
+            const int32_t *r = seg_first + ((p0 + lane) * cap + k) * 3;
+            nf = r[0];
+            nl = r[1];
+            nn = r[2];
+        } else {
+            const int64_t o = (int64_t)k * HW + p0 + lane;
+            nf = seg_first[o];
+            nl = seg_last[o];
+            nn = seg_n[o];
+        }
     };
     auto advance = [&]() {
         s++;
@@ -142,13 +153,14 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
 }  // namespace
 }  // namespace spk
 
-extern "C" int spk_decode(const int32_t *seg_first, const int32_t *seg_last, const int32_t *seg_n,
-                          const int32_t *count, int32_t cap, int32_t H, int32_t W, int32_t T,
-                          float theta, const int32_t *t_out, int32_t n_out, float *out,
-                          void *hip_stream)
+namespace {
+
+int decode(const int32_t *seg_first, const int32_t *seg_last, const int32_t *seg_n,
+           const int32_t *count, int32_t cap, int32_t H, int32_t W, int32_t T, float theta,
+           const int32_t *t_out, int32_t n_out, float *out, bool packed, hipStream_t st)
 {
     if (H <= 0 || W <= 0 || T <= 0 || cap < 0 || n_out < 0 || !count) return SPK_EINVAL;
-    if (cap > 0 && (!seg_first || !seg_last || !seg_n)) return SPK_EINVAL;
+    if (cap > 0 && (!seg_first || (!packed && (!seg_last || !seg_n)))) return SPK_EINVAL;
     if (!std::isfinite(theta) || !(theta > 0.0f)) return SPK_EINVAL;
     const int64_t HW = (int64_t)H * W;
     if (HW > (int64_t)INT32_MAX - 128 || (int64_t)n_out * HW > ((int64_t)1 << 60) ||
@@ -158,7 +170,6 @@ extern "C" int spk_decode(const int32_t *seg_first, const int32_t *seg_last, con
     if (!t_out || !out) return SPK_EINVAL;
     for (int32_t k = 0; k < n_out; k++)
         if (t_out[k] < 0 || t_out[k] >= T) return SPK_EINVAL;
-    hipStream_t st = (hipStream_t)hip_stream;
     spk::OutTables tab;
     const int rc = spk::out_tables(T, t_out, n_out, st, &tab);
     if (rc) return rc;
@@ -178,17 +189,44 @@ extern "C" int spk_decode(const int32_t *seg_first, const int32_t *seg_last, con
         t0 = t_out[0];
     }
     const dim3 grid((unsigned)((HW + 63) / 64)), block(64);
-#define SPK_DECODE_LAUNCH(I, A)                                                                \
-    hipLaunchKernelGGL((spk::decode_kernel<I, A>), grid, block, 0, st, seg_first, seg_last, seg_n, \
-                       count, cap, HW, T, (double)theta, tab.cnt_le, t0, dt, tab.plane, n_out, out)
-    if (tab.identity && ap)
-        SPK_DECODE_LAUNCH(true, true);
-    else if (tab.identity)
-        SPK_DECODE_LAUNCH(true, false);
-    else if (ap)
-        SPK_DECODE_LAUNCH(false, true);
-    else
-        SPK_DECODE_LAUNCH(false, false);
+#define SPK_DECODE_LAUNCH(I, A, K)                                                          \
+    hipLaunchKernelGGL((spk::decode_kernel<I, A, K>), grid, block, 0, st, seg_first, seg_last, \
+                       seg_n, count, cap, HW, T, (double)theta, tab.cnt_le, t0, dt, tab.plane,  \
+                       n_out, out)
+#define SPK_DECODE_LAYOUT(I, A)          \
+    if (packed)                          \
+        SPK_DECODE_LAUNCH(I, A, true);   \
+    else                                 \
+        SPK_DECODE_LAUNCH(I, A, false)
+    if (tab.identity && ap) {
+        SPK_DECODE_LAYOUT(true, true);
+    } else if (tab.identity) {
+        SPK_DECODE_LAYOUT(true, false);
+    } else if (ap) {
+        SPK_DECODE_LAYOUT(false, true);
+    } else {
+        SPK_DECODE_LAYOUT(false, false);
+    }
+#undef SPK_DECODE_LAYOUT
 #undef SPK_DECODE_LAUNCH
     return hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
+}
+
+}  // namespace
+
+extern "C" int spk_decode(const int32_t *seg_first, const int32_t *seg_last, const int32_t *seg_n,
+                          const int32_t *count, int32_t cap, int32_t H, int32_t W, int32_t T,
+                          float theta, const int32_t *t_out, int32_t n_out, float *out,
+                          void *hip_stream)
+{
+    return decode(seg_first, seg_last, seg_n, count, cap, H, W, T, theta, t_out, n_out, out,
+                  false, (hipStream_t)hip_stream);
+}
+
+extern "C" int spk_decode_packed(const int32_t *rec, const int32_t *count, int32_t cap, int32_t H,
+                                 int32_t W, int32_t T, float theta, const int32_t *t_out,
+                                 int32_t n_out, float *out, void *hip_stream)
+{
+    return decode(rec, nullptr, nullptr, count, cap, H, W, T, theta, t_out, n_out, out, true,
+                  (hipStream_t)hip_stream);
 }

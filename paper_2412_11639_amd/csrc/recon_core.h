@@ -501,10 +501,19 @@ struct Emitter {
         if (!valid) return;
         if constexpr (MODE == MODE_SEGMENTS) {
             if (segc < P.cap) {
-                const int64_t o = (int64_t)segc * P.HW + p;
-                gp(P.seg_first)[o] = first;
-                gp(P.seg_last)[o] = last;
-                gp(P.seg_n)[o] = n;
+                if (P.seg_rec) {
+                    // a pixel's records one after another: its lane fills
+                    // its own lines, which merge in L2 before write-back
+                    auto r = gp(P.seg_rec) + ((int64_t)p * P.cap + segc) * 3;
+                    r[0] = first;
+                    r[1] = last;
+                    r[2] = n;
+                } else {
+                    const int64_t o = (int64_t)segc * P.HW + p;
+                    gp(P.seg_first)[o] = first;
+                    gp(P.seg_last)[o] = last;
+                    gp(P.seg_n)[o] = n;
+                }
             }
             segc++;
         } else {

@@ -26,6 +26,7 @@ struct ReconParams {
     int32_t *seg_first;      // [cap][HW]
     int32_t *seg_last;
     int32_t *seg_n;
+    int32_t *seg_rec;        // [HW][cap][3] (first, last, n), used instead when not NULL
     int32_t *count;          // [HW]
 };
 

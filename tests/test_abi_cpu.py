@@ -119,6 +119,30 @@ def test_decode_rejects_bad_arguments(lib, args):
     assert rc == -1
 
 
+def test_segments_packed_rejects_bad_arguments(lib):
+    assert lib.spk_segments_packed(FAKE, 4, 4, 10, 1, -1, FAKE, FAKE, None) == -1
+    assert lib.spk_segments_packed(FAKE, 4, 4, 10, 1, 4, 0, FAKE, None) == -1
+    assert lib.spk_segments_packed(FAKE, 4, 4, 10, 1, 4, FAKE, 0, None) == -1
+    assert lib.spk_segments_packed(FAKE, 4, 4, 10, 5, 4, FAKE, FAKE, None) == -1
+    assert lib.spk_segments_packed(FAKE + 8, 4, 4, 10, 1, 4, FAKE, FAKE, None) == -1
+    assert lib.spk_segments_packed(FAKE, 0, 4, 10, 1, 4, FAKE, FAKE, None) == -1
+
+
+@pytest.mark.parametrize("args", [
+    dict(count=0), dict(cap=-1), dict(rec=0), dict(H=0), dict(W=0), dict(T=0), dict(theta=-2.0),
+    dict(theta=float("nan")), dict(n_out=-1), dict(t_out=[10]), dict(t_out=[-1]), dict(out=0),
+])
+def test_decode_packed_rejects_bad_arguments(lib, args):
+    a = dict(rec=FAKE, count=FAKE, cap=4, H=4, W=4, T=10, theta=1.0, t_out=[0, 5], n_out=None,
+             out=FAKE)
+    a.update(args)
+    t = (ctypes.c_int32 * max(1, len(a["t_out"])))(*a["t_out"])
+    n_out = len(a["t_out"]) if a["n_out"] is None else a["n_out"]
+    rc = lib.spk_decode_packed(a["rec"], a["count"], a["cap"], a["H"], a["W"], a["T"],
+                               a["theta"], ctypes.addressof(t), n_out, a["out"], None)
+    assert rc == -1
+
+
 @pytest.mark.parametrize("args", [
     dict(stream=0), dict(stream=FAKE + 8), dict(H=0), dict(order=0), dict(window=0),
     dict(n_out=-1),

@@ -62,6 +62,25 @@ def check_segments(spk, s, H, W, T, order, cap):
     np.testing.assert_array_equal(sf.cpu().numpy(), rf)
     np.testing.assert_array_equal(sl.cpu().numpy(), rl)
     np.testing.assert_array_equal(sn.cpu().numpy(), rn)
+    # the same lists, each pixel's contiguous
+    rec, cnt2 = spk.segments_packed(dev(s), H, W, T, order=order, cap=cap)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(cnt2.cpu().numpy(), rc)
+    r = rec.cpu().numpy()
+    np.testing.assert_array_equal(r[..., 0], rf.T)
+    np.testing.assert_array_equal(r[..., 1], rl.T)
+    np.testing.assert_array_equal(r[..., 2], rn.T)
+
+
+def decode_both(spk, sf, sl, sn, cnt, H, W, T, t_out):
+    """spk.decode on [cap][H*W] lists, checked equal (NaN where NaN) to
+    spk.decode_packed on the same lists laid out per pixel."""
+    got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out)
+    rec = torch.stack((sf, sl, sn), dim=-1).transpose(0, 1).contiguous()
+    got2 = spk.decode_packed(rec, cnt, H, W, T, 1.0, t_out)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got2.cpu().numpy(), got.cpu().numpy())
+    return got
 
 
 @pytest.mark.parametrize("order", [1, 2])
@@ -371,10 +390,13 @@ def test_decode_of_segments_equals_reconstruct(spk, order):
         cnt = spk.segments(ds, h, w, T_, order=order, cap=0)[3]
         cap = max(1, int(cnt.max().item()))
         sf, sl, sn, cnt = spk.segments(ds, h, w, T_, order=order, cap=cap)
-        got = spk.decode(sf, sl, sn, cnt, h, w, T_, 1.0, t_out)
+        got = decode_both(spk, sf, sl, sn, cnt, h, w, T_, t_out)
         ref = spk.reconstruct(ds, h, w, T_, 1.0, t_out, order=order)
+        rec, cnt2 = spk.segments_packed(ds, h, w, T_, order=order, cap=cap)
+        got2 = spk.decode_packed(rec, cnt2, h, w, T_, 1.0, t_out)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
+        np.testing.assert_array_equal(got2.cpu().numpy(), ref.cpu().numpy())
         np.testing.assert_array_equal(
             got.cpu().numpy(),
             oracle.reconstruct(s, h, w, T_, 1.0, t_out, order=order).astype(np.float32))
@@ -388,8 +410,7 @@ def test_decode_of_cut_lists_is_nan_past_cap(spk):
     t_out = list(range(0, T, 11))
     cap = 5
     sf, sl, sn, cnt = spk.segments(dev(s), H, W, T, order=2, cap=cap)
-    got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out).cpu().numpy().reshape(len(t_out), -1)
-    torch.cuda.synchronize()
+    got = decode_both(spk, sf, sl, sn, cnt, H, W, T, t_out).cpu().numpy().reshape(len(t_out), -1)
     ref = oracle.reconstruct(s, H, W, T, 1.0, t_out, order=2).astype(np.float32)
     ref = ref.reshape(len(t_out), -1)
     rl = oracle.segments(s, H, W, T, order=2, cap=cap)[1]          # last spike of stored segments
@@ -449,7 +470,7 @@ def test_decode_every_frame_short_segments(spk, order_name):
     ref_all = oracle.reconstruct(s, H, W, T, 1.0, every, order=order).astype(np.float32)
     # evenly spaced (ascending, descending, stride 7, one time) and not
     for t_out in (every, every[5:-3], every[::-1], every[2::7], [T // 2], shuffled):
-        got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out)
+        got = decode_both(spk, sf, sl, sn, cnt, H, W, T, t_out)
         ref = spk.reconstruct(ds, H, W, T, 1.0, t_out, order=order)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
@@ -471,7 +492,7 @@ def test_decode_with_no_stored_segments(spk):
     t_out = list(range(0, T, 7)) + [T - 1, 3]
     for order in (spk.FSR, spk.SSR, spk.TSR):
         sf, sl, sn, cnt = spk.segments(ds, H, W, T, order=order, cap=0)
-        got = spk.decode(sf, sl, sn, cnt, H, W, T, 1.0, t_out).cpu().numpy().reshape(len(t_out), -1)
+        got = decode_both(spk, sf, sl, sn, cnt, H, W, T, t_out).cpu().numpy().reshape(len(t_out), -1)
         c = cnt.cpu().numpy().reshape(-1)
         assert (c[:8] == 0).all() and (c[8:] > 0).all()
         assert (got[:, :8] == 0).all()
