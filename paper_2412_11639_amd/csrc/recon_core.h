@@ -610,40 +610,55 @@ struct Run {
         }
     }
 
-    // Process the 64-frame word w starting at frame t0; cnt_row[j] is the
-    // number of sorted outputs at or before frame t0 + j.
-    // FB1: keep fb1/fn1/fi1 (chunked runs only).
-    template <int ORDER, bool CAPTURE, bool FB1, class EM>
-    __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em)
+    // Whole-word shortcut (SegState::fast_word) for the nonzero word w
+    // starting at frame t0: true when no segment ends in it, the run then
+    // being advanced past it.
+    template <int ORDER>
+    __device__ __forceinline__ bool try_fast(int32_t t0, uint64_t w, const int32_t *cnt_row)
     {
-        if (lastspk >= 0) {
-            const int32_t c = popc64(w);
-            if (st.template fast_word<ORDER>(w, t0 + ctz64(w) - lastspk, c)) {
-                // no segment ends in this word
-                cum += c;
-                const int hp = hibit64(w);
-                lastspk = t0 + hp;
-                cnt_last = cnt_row[hp];
-                return;
-            }
-        }
-        const uint64_t wfull = w;
-        const int32_t cum0 = cum, lastspk0 = lastspk, cnt_last0 = cnt_last;
-        int32_t lp;  // position of the previous spike relative to t0
+        if (lastspk < 0) return false;
+        const int32_t c = popc64(w);
+        if (!st.template fast_word<ORDER>(w, t0 + ctz64(w) - lastspk, c)) return false;
+        cum += c;
+        const int hp = hibit64(w);
+        lastspk = t0 + hp;
+        cnt_last = cnt_row[hp];
+        return true;
+    }
+
+    // What the closing of a word needs from its start.
+    struct WordStart {
+        uint64_t wfull;   // the word
+        uint64_t rest;    // its spikes that end an interval
+        int32_t cum0, lastspk0, cnt_last0;
+        int32_t lp;       // previous spike, relative to t0
+    };
+
+    // Start of the spike walk over the nonzero word w: a pixel's first spike
+    // opens its first segment and ends no interval.
+    __device__ __forceinline__ WordStart begin(int32_t t0, uint64_t w)
+    {
+        WordStart ws{w, w, cum, lastspk, cnt_last, 0};
         if (lastspk < 0) {
-            // the pixel's first spike opens its first segment
             const int pos = ctz64(w);
-            w &= w - 1;
+            ws.rest = w & (w - 1);
             first = t0 + pos;
             first_idx = 0;
-            lp = pos;
+            ws.lp = pos;
         } else {
-            lp = lastspk - t0;
+            ws.lp = lastspk - t0;
         }
-        // walk the spikes of each 32-bit half; B marks spikes whose interval
-        // opens a new segment
+        return ws;
+    }
+
+    // Walk the spikes of rest (the intervals from lp on) through the state
+    // machine, one 32-bit half at a time; returns the mask of spikes whose
+    // interval opens a new segment.
+    template <int ORDER, bool CAPTURE>
+    __device__ __forceinline__ uint64_t spikes(int32_t t0, uint64_t rest, int32_t lp)
+    {
         uint32_t Blo = 0, Bhi = 0;
-        uint32_t h = (uint32_t)w;
+        uint32_t h = (uint32_t)rest;
         while (h) {
             const uint32_t nh = h & (h - 1);
             const int pos = __builtin_ctz(h);
@@ -652,7 +667,7 @@ struct Run {
             Blo |= step_capture<ORDER, CAPTURE>(x, t0 + pos) ? (h ^ nh) : 0u;
             h = nh;
         }
-        h = (uint32_t)(w >> 32);
+        h = (uint32_t)(rest >> 32);
         while (h) {
             const uint32_t nh = h & (h - 1);
             const int pos = __builtin_ctz(h) + 32;
@@ -661,8 +676,16 @@ struct Run {
             Bhi |= step_capture<ORDER, CAPTURE>(x, t0 + pos) ? (h ^ nh) : 0u;
             h = nh;
         }
-        // close the segments that ended in this word
-        const uint64_t B0 = ((uint64_t)Bhi << 32) | Blo;
+        return ((uint64_t)Bhi << 32) | Blo;
+    }
+
+    // Close the segments that ended in the word (B0: the spikes whose
+    // interval opened a new one) and advance the run past it.
+    // FB1: keep fb1/fn1/fi1 (chunked runs only).
+    template <bool FB1, class EM>
+    __device__ __forceinline__ void finish(int32_t t0, const WordStart &ws, uint64_t B0,
+                                           const int32_t *cnt_row, EM &em)
+    {
         // chunked runs keep the first segment closed at or after the chunk's
         // start (for the fixup pass); once every lane that closes a segment
         // in this word has it, the loop runs without that bookkeeping
@@ -671,17 +694,17 @@ struct Run {
             while (B) {
                 const int cpos = ctz64(B);
                 B &= B - 1;
-                const uint64_t below = wfull & ((1ull << cpos) - 1);
+                const uint64_t below = ws.wfull & ((1ull << cpos) - 1);
                 int32_t last, kend;
                 if (below) {
                     const int bp = hibit64(below);
                     last = t0 + bp;
                     kend = cnt_row[bp];
                 } else {
-                    last = lastspk0;
-                    kend = cnt_last0;
+                    last = ws.lastspk0;
+                    kend = ws.cnt_last0;
                 }
-                const int32_t last_idx = cum0 + popc64(below) - 1;
+                const int32_t last_idx = ws.cum0 + popc64(below) - 1;
                 em.close(first, last, last_idx - first_idx, k0, kend);
                 if constexpr (decltype(fb1_pending)::value) {
                     if (fb1 < 0 && last >= cs) {
@@ -700,10 +723,22 @@ struct Run {
         else
             closes(std::false_type{});
         if (B0) lastb = first;  // the last closed segment's last spike
-        cum = cum0 + popc64(wfull);
-        const int hp = hibit64(wfull);
+        cum = ws.cum0 + popc64(ws.wfull);
+        const int hp = hibit64(ws.wfull);
         lastspk = t0 + hp;
         cnt_last = cnt_row[hp];
+    }
+
+    // Process the 64-frame word w starting at frame t0; cnt_row[j] is the
+    // number of sorted outputs at or before frame t0 + j.
+    // FB1: keep fb1/fn1/fi1 (chunked runs only).
+    template <int ORDER, bool CAPTURE, bool FB1, class EM>
+    __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em)
+    {
+        if (try_fast<ORDER>(t0, w, cnt_row)) return;  // no segment ends in this word
+        const WordStart ws = begin(t0, w);
+        const uint64_t B0 = spikes<ORDER, CAPTURE>(t0, ws.rest, ws.lp);
+        finish<FB1>(t0, ws, B0, cnt_row, em);
     }
 };
 
