@@ -630,7 +630,11 @@ struct WgArgs {
     float *partial;              // [gridDim.x][np]
 };
 
-constexpr int kWgMaxBlocks = 1024;
+// Workgroups of a weight-gradient launch: two per CU are resident (74 KB
+// of LDS each), and 512 give each one several tiles to pipeline its loads
+// over while halving the partial rows against 1024 (64 x 128 x 128 step:
+// 0.548 -> 0.518 ms; 256 workgroups: 0.615 ms).
+constexpr int kWgMaxBlocks = 512;
 
 template <int K>
 __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
@@ -655,109 +659,136 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
     for (int t = 0; t < 9; t++) acc[t] = acce[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;  // bias partial of thread tid: channel tid / 8, pixels (tid % 8) * 32 ..
 
-    for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+    // A tile's global data goes through registers: the loads of tile k + 1
+    // are issued before tile k's MFMAs, and written to LDS (transposed)
+    // once those are done, so their latency hides behind the MFMA work.
+    // Staging items per thread: the gradient tile as (part, seg) pieces of 8
+    // pixels x 8 channels, the activation halo as (dx, part, r, seg) pieces
+    // (first layer: 8 window words, or 8 estimates for part 4).
+    constexpr int kGItems = 1;  // (part, seg): 4 pixels x 8 channels, one per thread
+    constexpr int kATotal = K == WG_FIRST ? 3 * (4 + NE) * 18 * 2 : 3 * 4 * 18 * 2;
+    constexpr int kAItems = (kATotal + 255) / 256;
+    constexpr int kAWords = K == WG_FIRST ? 1 : 4;  // dwords per pixel of a halo piece
+    uint32_t gr[kGItems][4][4];
+    uint32_t ar[kAItems][8][kAWords];
+    auto load_tile = [&](int tile) {
         const int b = tile / (A.tx * A.ty);
         const int ty0 = ((tile / A.tx) % A.ty) * 16, tx0 = (tile % A.tx) * 16;
-        // gradients of the tile, channel-major
         if constexpr (K == WG_LAST) {
             const int px = tid, y = ty0 + px / 16, x = tx0 + px % 16;
             float v = 0.0f;
             if (y < A.Hc && x < A.Wc) v = A.gy[((int64_t)b * A.Hc + y) * A.Wc + x];
-            gT[0][px] = to_bf16(v);
+            gr[0][0][0] = __float_as_uint(v);
         } else {
-            // item (part, seg): pixels 8 seg .. 8 seg + 7 x channels part*8 ..
-            // +7, loaded as 8 channel vectors, transposed in registers and
-            // written as 8 channel rows of 16 bytes
-            for (int it = tid; it < 4 * 32; it += 256) {
-                const int seg = it & 31, part = it >> 5, px0 = 8 * seg;
-                const int y = ty0 + px0 / 16;
-                uint32_t m[8][4];  // pixel j: channels part*8 .. +7 in pairs
 #pragma unroll
-                for (int j = 0; j < 8; j++) {
+            for (int u = 0; u < kGItems; u++) {
+                const int it = tid + 256 * u;
+                const int seg = it & 63, part = it >> 6, px0 = 4 * seg;
+                const int y = ty0 + px0 / 16;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
                     const int x = tx0 + px0 % 16 + j;
                     uint4 v = make_uint4(0u, 0u, 0u, 0u);
                     if (y < A.Hc && x < A.Wc)
                         v = *(const uint4 *)(A.g + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
                                              part * 8);
-                    m[j][0] = v.x;
-                    m[j][1] = v.y;
-                    m[j][2] = v.z;
-                    m[j][3] = v.w;
-                }
-#pragma unroll
-                for (int e2 = 0; e2 < 4; e2++) {
-                    uint4 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 7
-                    lo.x = (m[0][e2] & 0xFFFFu) | (m[1][e2] << 16);
-                    lo.y = (m[2][e2] & 0xFFFFu) | (m[3][e2] << 16);
-                    lo.z = (m[4][e2] & 0xFFFFu) | (m[5][e2] << 16);
-                    lo.w = (m[6][e2] & 0xFFFFu) | (m[7][e2] << 16);
-                    hi.x = (m[0][e2] >> 16) | (m[1][e2] & 0xFFFF0000u);
-                    hi.y = (m[2][e2] >> 16) | (m[3][e2] & 0xFFFF0000u);
-                    hi.z = (m[4][e2] >> 16) | (m[5][e2] & 0xFFFF0000u);
-                    hi.w = (m[6][e2] >> 16) | (m[7][e2] & 0xFFFF0000u);
-                    *(uint4 *)(&gT[part * 8 + 2 * e2][px0]) = lo;
-                    *(uint4 *)(&gT[part * 8 + 2 * e2 + 1][px0]) = hi;
+                    gr[u][j][0] = v.x;
+                    gr[u][j][1] = v.y;
+                    gr[u][j][2] = v.z;
+                    gr[u][j][3] = v.w;
                 }
             }
         }
-        // activation halo, rows ty0-1 .. ty0+16, columns tx0-1 .. tx0+16,
-        // written once per horizontal tap offset
-        if constexpr (K != WG_FIRST) {
-            // item (dx, part, r, seg): 8 pixels x 8 channels, loaded as 8
-            // channel vectors, transposed in registers and written as 8
-            // channel rows of 16 bytes (pixels cc0 .. cc0 + 7 of copy dx)
-            for (int it = tid; it < 3 * 4 * 18 * 2; it += 256) {
-                const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
-                const int part = rest & 3, dx = rest >> 2, cc0 = 8 * seg;
-                const int y = ty0 - 1 + r;
-                uint32_t m[8][4];  // pixel j: channels part*8 .. +7 in pairs
+#pragma unroll
+        for (int u = 0; u < kAItems; u++) {
+            const int it = tid + 256 * u;
+            const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
+            const int cc0 = 8 * seg, y = ty0 - 1 + r;
+            const bool yin = it < kATotal && y >= 0 && y < A.Hc;
+            if constexpr (K != WG_FIRST) {
+                const int part = rest & 3, dx = rest >> 2;
 #pragma unroll
                 for (int j = 0; j < 8; j++) {
                     const int x = tx0 - 1 + cc0 + dx + j;
                     uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                    if (y >= 0 && y < A.Hc && x >= 0 && x < A.Wc)
+                    if (yin && x >= 0 && x < A.Wc)
                         v = *(const uint4 *)(A.a + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
                                              part * 8);
-                    m[j][0] = v.x;
-                    m[j][1] = v.y;
-                    m[j][2] = v.z;
-                    m[j][3] = v.w;
+                    ar[u][j][0] = v.x;
+                    ar[u][j][1] = v.y;
+                    ar[u][j][2] = v.z;
+                    ar[u][j][3] = v.w;
                 }
+            } else {
+                const int part = rest % (4 + NE), dx = rest / (4 + NE);
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const int x = tx0 - 1 + cc0 + dx + j;
+                    const bool in = yin && x >= 0 && x < A.Wc;
+                    const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
+                    uint32_t v = 0u;
+                    if (in) v = part < 4 ? A.win[pix] : __float_as_uint(A.est[pix]);
+                    ar[u][j][0] = v;
+                }
+            }
+        }
+    };
+    // the registers of the loaded tile into LDS, channel-major
+    auto commit_tile = [&]() {
+        if constexpr (K == WG_LAST) {
+            gT[0][tid] = to_bf16(__uint_as_float(gr[0][0][0]));
+        } else {
+            // 4 channel vectors transposed in registers and written as 8
+            // channel rows of 8 bytes
+#pragma unroll
+            for (int u = 0; u < kGItems; u++) {
+                const int it = tid + 256 * u;
+                const int seg = it & 63, part = it >> 6, px0 = 4 * seg;
+#pragma unroll
+                for (int e2 = 0; e2 < 4; e2++) {
+                    uint2 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 3
+                    lo.x = (gr[u][0][e2] & 0xFFFFu) | (gr[u][1][e2] << 16);
+                    lo.y = (gr[u][2][e2] & 0xFFFFu) | (gr[u][3][e2] << 16);
+                    hi.x = (gr[u][0][e2] >> 16) | (gr[u][1][e2] & 0xFFFF0000u);
+                    hi.y = (gr[u][2][e2] >> 16) | (gr[u][3][e2] & 0xFFFF0000u);
+                    *(uint2 *)(&gT[part * 8 + 2 * e2][px0]) = lo;
+                    *(uint2 *)(&gT[part * 8 + 2 * e2 + 1][px0]) = hi;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kAItems; u++) {
+            const int it = tid + 256 * u;
+            if (it >= kATotal) continue;
+            const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
+            const int cc0 = 8 * seg;
+            if constexpr (K != WG_FIRST) {
+                const int part = rest & 3, dx = rest >> 2;
 #pragma unroll
                 for (int e2 = 0; e2 < 4; e2++) {
                     uint4 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 7
-                    lo.x = (m[0][e2] & 0xFFFFu) | (m[1][e2] << 16);
-                    lo.y = (m[2][e2] & 0xFFFFu) | (m[3][e2] << 16);
-                    lo.z = (m[4][e2] & 0xFFFFu) | (m[5][e2] << 16);
-                    lo.w = (m[6][e2] & 0xFFFFu) | (m[7][e2] << 16);
-                    hi.x = (m[0][e2] >> 16) | (m[1][e2] & 0xFFFF0000u);
-                    hi.y = (m[2][e2] >> 16) | (m[3][e2] & 0xFFFF0000u);
-                    hi.z = (m[4][e2] >> 16) | (m[5][e2] & 0xFFFF0000u);
-                    hi.w = (m[6][e2] >> 16) | (m[7][e2] & 0xFFFF0000u);
+                    lo.x = (ar[u][0][e2] & 0xFFFFu) | (ar[u][1][e2] << 16);
+                    lo.y = (ar[u][2][e2] & 0xFFFFu) | (ar[u][3][e2] << 16);
+                    lo.z = (ar[u][4][e2] & 0xFFFFu) | (ar[u][5][e2] << 16);
+                    lo.w = (ar[u][6][e2] & 0xFFFFu) | (ar[u][7][e2] << 16);
+                    hi.x = (ar[u][0][e2] >> 16) | (ar[u][1][e2] & 0xFFFF0000u);
+                    hi.y = (ar[u][2][e2] >> 16) | (ar[u][3][e2] & 0xFFFF0000u);
+                    hi.z = (ar[u][4][e2] >> 16) | (ar[u][5][e2] & 0xFFFF0000u);
+                    hi.w = (ar[u][6][e2] >> 16) | (ar[u][7][e2] & 0xFFFF0000u);
                     *(uint4 *)(&aT[dx][part * 8 + 2 * e2][r * 16 + cc0]) = lo;
                     *(uint4 *)(&aT[dx][part * 8 + 2 * e2 + 1][r * 16 + cc0]) = hi;
                 }
-            }
-        } else {
-            // first layer: item (dx, part, r, seg) is 8 pixels x the 8 bit
-            // channels of byte `part` of their windows, transposed in
-            // registers (an 8 x 8 bit transpose) into 8 channel rows of 8
-            // bfloat16 ones and zeros, each one 16-byte store; part 4 is
-            // the estimate channel of the same 8 pixels
-            for (int it = tid; it < 3 * (4 + NE) * 18 * 2; it += 256) {
-                const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
-                const int part = rest % (4 + NE), dx = rest / (4 + NE), cc0 = 8 * seg;
-                const int y = ty0 - 1 + r;
-                const bool yin = y >= 0 && y < A.Hc;
+            } else {
+                // first layer: the 8 bit channels of byte `part` of the 8
+                // pixels' windows, transposed (an 8 x 8 bit transpose) into 8
+                // channel rows of 8 bfloat16 ones and zeros, each one 16-byte
+                // store; part 4 is the estimate channel of the same pixels
+                const int part = rest % (4 + NE), dx = rest / (4 + NE);
                 if (part < 4) {
                     uint64_t m = 0;  // byte j: pixel j's channels part*8 .. +7
 #pragma unroll
-                    for (int j = 0; j < 8; j++) {
-                        const int x = tx0 - 1 + cc0 + dx + j;
-                        if (yin && x >= 0 && x < A.Wc)
-                            m |= (uint64_t)((A.win[((int64_t)b * A.Hc + y) * A.Wc + x] >>
-                                             (8 * part)) & 0xFFu) << (8 * j);
-                    }
+                    for (int j = 0; j < 8; j++)
+                        m |= (uint64_t)((ar[u][j][0] >> (8 * part)) & 0xFFu) << (8 * j);
                     // byte e of m becomes channel e's bits over pixels 0 .. 7
                     uint64_t t = (m ^ (m >> 7)) & 0x00AA00AA00AA00AAull;
                     m ^= t ^ (t << 7);
@@ -772,39 +803,39 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
                 } else if constexpr (NE) {
                     bf16x8 v;
 #pragma unroll
-                    for (int j = 0; j < 8; j++) {
-                        const int x = tx0 - 1 + cc0 + dx + j;
-                        v[j] = yin && x >= 0 && x < A.Wc
-                                   ? to_bf16(A.est[((int64_t)b * A.Hc + y) * A.Wc + x])
-                                   : (__bf16)0.0f;
-                    }
+                    for (int j = 0; j < 8; j++) v[j] = to_bf16(__uint_as_float(ar[u][j][0]));
                     *(bf16x8 *)(&aT[dx][32][r * 16 + cc0]) = v;
                 }
             }
         }
+    };
+
+    if ((int)blockIdx.x < A.ntiles) load_tile(blockIdx.x);
+    for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+        commit_tile();
         __syncthreads();
-        // A fragments: gradients of channel cb*16 + i, pixels 32s + 8gq .. +7
-        bf16x8 Af[8];
+        if (tile + (int)gridDim.x < A.ntiles) load_tile(tile + gridDim.x);
+        // K steps s (32 pixels each) outside, taps inside: one A fragment
+        // (gradients of channel cb*16 + i, pixels 32s + 8gq .. +7) at a
+        // time, and nine independent accumulators back to back
 #pragma unroll
         for (int s = 0; s < 8; s++) {
+            bf16x8 Af;
             if constexpr (K == WG_LAST) {
 #pragma unroll
-                for (int e = 0; e < 8; e++) Af[s][e] = (__bf16)0.0f;
-                if (i == 0) Af[s] = *(const bf16x8 *)(&gT[0][32 * s + 8 * gq]);
+                for (int e = 0; e < 8; e++) Af[e] = (__bf16)0.0f;
+                if (i == 0) Af = *(const bf16x8 *)(&gT[0][32 * s + 8 * gq]);
             } else {
-                Af[s] = *(const bf16x8 *)(&gT[cb * 16 + i][32 * s + 8 * gq]);
+                Af = *(const bf16x8 *)(&gT[cb * 16 + i][32 * s + 8 * gq]);
             }
-        }
 #pragma unroll
-        for (int t = 0; t < 9; t++) {
-            if (t < tap0 || t >= tap1) continue;
-            const int dy = t / 3, dx = t % 3;
-#pragma unroll
-            for (int s = 0; s < 8; s++) {
+            for (int t = 0; t < 9; t++) {
+                if (t < tap0 || t >= tap1) continue;
+                const int dy = t / 3, dx = t % 3;
                 // pixels 32s + 8gq .. +7: tile row 2s + gq/2, columns 8(gq&1) ..
                 const int row = 2 * s + (gq >> 1) + dy, col = 8 * (gq & 1);
                 const bf16x8 Bf = *(const bf16x8 *)(&aT[dx][jb * 16 + i][row * 16 + col]);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[s], Bf, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[t], 0, 0, 0);
                 if constexpr (NE) {
                     if (jb == 0) {
                         // estimate channel in column 0 of a third input block
@@ -812,7 +843,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
 #pragma unroll
                         for (int e = 0; e < 8; e++) Be[e] = (__bf16)0.0f;
                         if (i == 0) Be = *(const bf16x8 *)(&aT[dx][32][row * 16 + col]);
-                        acce[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[s], Be, acce[t], 0, 0, 0);
+                        acce[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Be, acce[t], 0, 0, 0);
                     }
                 }
             }
