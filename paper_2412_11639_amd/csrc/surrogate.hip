@@ -286,13 +286,19 @@ struct ConvShape {
     static constexpr int nb = KIND == CK_LAST ? 1 : 2;
 };
 
-// 8 bfloat16 ones/zeros from 8 bits
+// 8 bfloat16 ones/zeros from 8 bits (bit e -> element e).  Dword k holds
+// bits 2k and 2k + 1: spread to bits 0 and 16 and multiplied by 0x3F80
+// (bfloat16 1.0), three integer operations a dword.
 __device__ __forceinline__ bf16x8 bits_to_bf16(uint32_t bits)
 {
-    bf16x8 v;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 d;
 #pragma unroll
-    for (int e = 0; e < 8; e++) v[e] = ((bits >> e) & 1u) ? (__bf16)1.0f : (__bf16)0.0f;
-    return v;
+    for (int k = 0; k < 4; k++) {
+        const uint32_t x = (bits >> (2 * k)) & 3u;
+        d[k] = ((x | (x << 15)) & 0x10001u) * 0x3F80u;
+    }
+    return __builtin_bit_cast(bf16x8, d);
 }
 
 // A workgroup computes 16 x 16 blocks of output pixels, all 32 output
@@ -311,9 +317,11 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
     constexpr bool SCALAR_IN = KIND == CK_FIRST || KIND == CK_DGRAD_LAST;
     constexpr bool BITS_IN = KIND == CK_FIRST;                  // window words
     constexpr int kHalo = 18 * 18;
-    // staging items per thread: 16-byte pieces of the 32-channel halo (the
-    // window word of a pixel for the first layer) and scalar pixels
-    constexpr int kVecItems = BITS_IN ? kHalo : kHalo * 4;
+    // staging items per thread: 16-byte pieces of the 32-channel halo (for
+    // the first layer, one byte of a pixel's window word, expanded to 8
+    // channels) and scalar pixels; consecutive threads write consecutive
+    // 16-byte pieces of LDS
+    constexpr int kVecItems = kHalo * 4;
     constexpr int kVecPer = VEC_IN ? (kVecItems + 255) / 256 : 1;
     constexpr int kScPer = SCALAR_IN ? (kHalo + 255) / 256 : 1;
     constexpr int CP = C;  // pixel stride in the halo tile
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
 #pragma unroll
             for (int u = 0; u < kVecPer; u++) {
                 const int it = tid + 256 * u;
-                const int q = BITS_IN ? it : it >> 2, part = it & 3;
+                const int q = it >> 2, part = it & 3;
                 const int y = y0 - 1 + q / 18, x = x0 - 1 + q % 18;
                 const bool in =
                     it < kVecItems && y >= 0 && y < A.Hc && x >= 0 && x < A.Wc;
@@ -387,14 +395,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
                 const int it = tid + 256 * u;
                 if (it < kVecItems) {
                     if constexpr (BITS_IN) {
-                        // neighbouring threads start on different 16-byte
-                        // parts of their pixels (fewer LDS bank conflicts)
-#pragma unroll
-                        for (int k = 0; k < 4; k++) {
-                            const int part = (k + it) & 3;
-                            *(bf16x8 *)(&tin[it * CP + part * 8]) =
-                                bits_to_bf16((pw[u] >> (8 * part)) & 0xFFu);
-                        }
+                        *(bf16x8 *)(&tin[(it >> 2) * CP + (it & 3) * 8]) =
+                            bits_to_bf16((pw[u] >> (8 * (it & 3))) & 0xFFu);
                     } else {
                         *(bf16x8 *)(&tin[(it >> 2) * CP + (it & 3) * 8]) = pv[u];
                     }
