@@ -877,6 +877,141 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
     if (tid < CO * 8 && tid % 8 == 0) out[S::nw + tid / 8] = bsum;
 }
 
+// Weight gradient of the output layer (one output channel).  Written with
+// q = p + off(tap), dW[tap][ci] = sum_q a[q][ci] gy[q - off(tap)] is a GEMM
+// with M = input channels (32), N = taps (9 of 16) and K = pixels: the
+// activations need no halo, only the one-channel gradient does.  Per
+// 16x16 tile a workgroup stages the activations channel-major and the
+// gradient's 18x18 halo as bfloat16 in three copies shifted by the
+// horizontal tap offset, so that every fragment is an aligned 16-byte LDS
+// read.  Wave w takes K steps 2w and 2w + 1 (64 of the tile's pixels) for
+// both channel blocks; the four waves' sums are added at the end.  The
+// next tile's loads are in flight while the current one is computed.
+// Partial row: dW in the parameter blob's order, then the bias (the sum of
+// the bfloat16 gradients).
+__global__ __launch_bounds__(256) void wgrad_last_kernel(WgArgs A)
+{
+    using S = WgShape<WG_LAST>;
+    static_assert(S::cout == 1 && S::cin == 32, "output layer");
+    __shared__ __attribute__((aligned(16))) __bf16 aT[32][256 + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 gH[3][18][16];
+    __shared__ float red[4][2][4][64];
+    __shared__ float bred[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = lane & 15, gq = lane >> 4;
+    f32x4 acc[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+    float bsum = 0.0f;  // this thread's pixel of every tile
+    // registers of the next tile: activations (4 pixels x 8 channels,
+    // piece tid), two halo values, the thread's own gradient
+    uint32_t ar[4][4];
+    float hv[2], gc;
+    auto load_tile = [&](int tile) {
+        const int b = tile / (A.tx * A.ty);
+        const int ty0 = ((tile / A.tx) % A.ty) * 16, tx0 = (tile % A.tx) * 16;
+        {
+            const int seg = tid & 63, part = tid >> 6, px0 = 4 * seg;
+            const int y = ty0 + px0 / 16;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int x = tx0 + px0 % 16 + j;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (y < A.Hc && x < A.Wc)
+                    v = *(const uint4 *)(A.a + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8);
+                ar[j][0] = v.x;
+                ar[j][1] = v.y;
+                ar[j][2] = v.z;
+                ar[j][3] = v.w;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int q = tid + 256 * u;
+            const int y = ty0 - 1 + q / 18, x = tx0 - 1 + q % 18;
+            hv[u] = q < 18 * 18 && y >= 0 && y < A.Hc && x >= 0 && x < A.Wc
+                        ? A.gy[((int64_t)b * A.Hc + y) * A.Wc + x]
+                        : 0.0f;
+        }
+        const int y = ty0 + tid / 16, x = tx0 + tid % 16;
+        gc = y < A.Hc && x < A.Wc ? A.gy[((int64_t)b * A.Hc + y) * A.Wc + x] : 0.0f;
+    };
+    auto commit_tile = [&]() {
+        const int seg = tid & 63, part = tid >> 6, px0 = 4 * seg;
+#pragma unroll
+        for (int e2 = 0; e2 < 4; e2++) {
+            uint2 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 3
+            lo.x = (ar[0][e2] & 0xFFFFu) | (ar[1][e2] << 16);
+            lo.y = (ar[2][e2] & 0xFFFFu) | (ar[3][e2] << 16);
+            hi.x = (ar[0][e2] >> 16) | (ar[1][e2] & 0xFFFF0000u);
+            hi.y = (ar[2][e2] >> 16) | (ar[3][e2] & 0xFFFF0000u);
+            *(uint2 *)(&aT[part * 8 + 2 * e2][px0]) = lo;
+            *(uint2 *)(&aT[part * 8 + 2 * e2 + 1][px0]) = hi;
+        }
+        // halo value (hr, hc) into copy d at column hc - d
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int q = tid + 256 * u;
+            if (q < 18 * 18) {
+                const int hr = q / 18, hc = q % 18;
+                const __bf16 v = to_bf16(hv[u]);
+#pragma unroll
+                for (int d = 0; d < 3; d++)
+                    if (hc - d >= 0 && hc - d < 16) gH[d][hr][hc - d] = v;
+            }
+        }
+        bsum += (float)to_bf16(gc);
+    };
+
+    if ((int)blockIdx.x < A.ntiles) load_tile(blockIdx.x);
+    for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+        commit_tile();
+        __syncthreads();
+        if (tile + (int)gridDim.x < A.ntiles) load_tile(tile + gridDim.x);
+#pragma unroll
+        for (int ss = 0; ss < 2; ss++) {
+            const int s = 2 * wave + ss;
+            // pixels 32s + 8gq .. +7: tile row 2s + gq/2, columns 8(gq&1) ..
+            const int row = 2 * s + (gq >> 1), col = 8 * (gq & 1);
+            // B: column i is tap i = 3 dy + dx, whose gradient for
+            // activation pixel q sits at halo (row + 2 - dy, col + 2 - dx)
+            bf16x8 Bf;
+#pragma unroll
+            for (int e = 0; e < 8; e++) Bf[e] = (__bf16)0.0f;
+            if (i < 9) {
+                const int dy = i / 3, dx = i % 3;
+                Bf = *(const bf16x8 *)(&gH[2 - dx][row + 2 - dy][col]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++) {
+                const bf16x8 Af = *(const bf16x8 *)(&aT[cb * 16 + i][32 * s + 8 * gq]);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[cb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // the four waves' sums, in wave order
+#pragma unroll
+    for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) red[wave][cb][r][lane] = acc[cb][r];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) bsum += __shfl_xor(bsum, m, 64);
+    if (lane == 0) bred[wave] = bsum;
+    __syncthreads();
+    float *out = A.partial + (int64_t)blockIdx.x * S::np;
+    if (wave == 0) {
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                // D[ci 4*(lane/16) + r][tap lane%16] of channel block cb
+                const float v = ((red[0][cb][r][lane] + red[1][cb][r][lane]) +
+                                 red[2][cb][r][lane]) + red[3][cb][r][lane];
+                if (i < 9) out[i * S::cin + cb * 16 + 4 * gq + r] = v;
+            }
+        if (lane == 0) out[S::nw] = ((bred[0] + bred[1]) + bred[2]) + bred[3];
+    }
+}
+
 // The weight-gradient partials of every layer, reduced by one launch:
 // segment s sums partial[blk][j] (nblocks rows of np) into dst[j]; its
 // weights start at reduce workgroup blk0.
@@ -1086,7 +1221,10 @@ void launch_wgrad(WgArgs a, float *dst, RedArgs &R, hipStream_t st)
 {
     a.ntiles = a.B * a.tx * a.ty;
     const int nblk = a.ntiles < kWgMaxBlocks ? a.ntiles : kWgMaxBlocks;
-    hipLaunchKernelGGL(wgrad_kernel<K>, dim3(nblk), dim3(256), 0, st, a);
+    if constexpr (K == WG_LAST)
+        hipLaunchKernelGGL(wgrad_last_kernel, dim3(nblk), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(wgrad_kernel<K>, dim3(nblk), dim3(256), 0, st, a);
     const int np = WgShape<K>::np;
     RedSeg &S = R.seg[R.nseg++];
     S.partial = a.partial;
