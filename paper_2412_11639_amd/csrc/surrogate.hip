@@ -597,19 +597,19 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *
 // weight gradients on MFMA: for each tap, dW[co][tap][ci] = sum_p g[p][co] *
 // a[p + off(tap)][ci] is a GEMM with M = output channels, N = input
 // channels and K = pixels.  A workgroup walks 16x16-pixel tiles (grid
-// stride) and stages per tile, channel-major in LDS:
-//   gT[co][px]              the tile's gradients (K contiguous for A);
-//   aT[dx][ci][row*16+col]  the 18x18 activation halo, once per horizontal
-//                           tap offset dx, so that every B fragment (8
-//                           consecutive pixels of one channel) is an
-//                           aligned 16-byte LDS read.
-// Both pad each channel row by 16 bytes against bank conflicts.
-// Wave w owns output-channel block w>>1 and input-channel block w&1 for all
-// 9 taps (accumulators stay in registers across tiles).  Layer 1 adds a
-// third input block whose column 0 is the estimate channel; layer 4 (one
-// output channel) pads M to 16 and splits the taps over the waves.  Bias
-// gradients are column sums of gT.  Each workgroup writes one partial
-// gradient; reduce_kernel adds the partials in a fixed order.
+// stride) and stages per tile, channel-major in LDS, the operand without a
+// halo (K contiguous) and the operand with the 18x18 halo once per
+// horizontal tap offset, so that every fragment (8 consecutive pixels of
+// one channel) is an aligned 16-byte LDS read; each channel row is padded
+// by 16 bytes against bank conflicts.  The hidden layers (wgrad_kernel)
+// stage the gradients plain and the activations with the halo.  Layers 1
+// and 4 index by q = p + off(tap) instead, which moves the halo to the
+// gradient: for layer 1 that spares expanding the window bits of three
+// halo copies, for layer 4 (one output channel) it gives M = input
+// channels.  Accumulators stay in registers across the tiles a workgroup
+// walks; bias gradients are column sums of the gradient tile.  Each
+// workgroup writes one partial gradient; reduce_kernel adds the partials
+// in a fixed order.
 
 enum WgKind { WG_FIRST = 0, WG_MID, WG_LAST };
 
@@ -638,124 +638,86 @@ struct WgArgs {
 // 0.548 -> 0.518 ms; 256 workgroups: 0.615 ms).
 constexpr int kWgMaxBlocks = 512;
 
-template <int K>
+// The hidden layers (32 -> 32).
 __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
 {
-    using S = WgShape<K>;
-    constexpr int CO = S::cout;                   // staged gradient channels
-    constexpr int NE = K == WG_FIRST ? 1 : 0;     // estimate channel planes
+    using S = WgShape<WG_MID>;
     // rows padded by 16 bytes: the 16 lanes of one fragment read sit on
     // distinct banks (unpadded, the 512- and 576-byte strides put every
     // fourth lane, or all of them, on the same banks)
-    __shared__ __attribute__((aligned(16))) __bf16 gT[CO][256 + 8];
-    __shared__ __attribute__((aligned(16))) __bf16 aT[3][32 + NE][18 * 16 + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 gT[32][256 + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 aT[3][32][18 * 16 + 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, gq = lane >> 4;
     // this wave's blocks
-    const int cb = K == WG_LAST ? 0 : wave >> 1;
-    const int jb = wave & 1;
-    const int tap0 = K == WG_LAST ? (wave >> 1) * 5 : 0;
-    const int tap1 = K == WG_LAST ? (wave >> 1 ? 9 : 5) : 9;
-    f32x4 acc[9], acce[9];
+    const int cb = wave >> 1, jb = wave & 1;
+    f32x4 acc[9];
 #pragma unroll
-    for (int t = 0; t < 9; t++) acc[t] = acce[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 9; t++) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;  // bias partial of thread tid: channel tid / 8, pixels (tid % 8) * 32 ..
 
     // A tile's global data goes through registers: the loads of tile k + 1
     // are issued before tile k's MFMAs, and written to LDS (transposed)
     // once those are done, so their latency hides behind the MFMA work.
-    // Staging items per thread: the gradient tile as (part, seg) pieces of 8
-    // pixels x 8 channels, the activation halo as (dx, part, r, seg) pieces
-    // (first layer: 8 window words, or 8 estimates for part 4).
-    constexpr int kGItems = 1;  // (part, seg): 4 pixels x 8 channels, one per thread
-    constexpr int kATotal = K == WG_FIRST ? 3 * (4 + NE) * 18 * 2 : 3 * 4 * 18 * 2;
+    // Staging items per thread: the gradient tile as piece tid (4 pixels x
+    // 8 channels), the activation halo as (dx, part, r, seg) pieces of 8
+    // pixels x 8 channels.
+    constexpr int kATotal = 3 * 4 * 18 * 2;
     constexpr int kAItems = (kATotal + 255) / 256;
-    constexpr int kAWords = K == WG_FIRST ? 1 : 4;  // dwords per pixel of a halo piece
-    uint32_t gr[kGItems][4][4];
-    uint32_t ar[kAItems][8][kAWords];
+    uint32_t gr[4][4];
+    uint32_t ar[kAItems][8][4];
     auto load_tile = [&](int tile) {
         const int b = tile / (A.tx * A.ty);
         const int ty0 = ((tile / A.tx) % A.ty) * 16, tx0 = (tile % A.tx) * 16;
-        if constexpr (K == WG_LAST) {
-            const int px = tid, y = ty0 + px / 16, x = tx0 + px % 16;
-            float v = 0.0f;
-            if (y < A.Hc && x < A.Wc) v = A.gy[((int64_t)b * A.Hc + y) * A.Wc + x];
-            gr[0][0][0] = __float_as_uint(v);
-        } else {
+        {
+            const int seg = tid & 63, part = tid >> 6, px0 = 4 * seg;
+            const int y = ty0 + px0 / 16;
 #pragma unroll
-            for (int u = 0; u < kGItems; u++) {
-                const int it = tid + 256 * u;
-                const int seg = it & 63, part = it >> 6, px0 = 4 * seg;
-                const int y = ty0 + px0 / 16;
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int x = tx0 + px0 % 16 + j;
-                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                    if (y < A.Hc && x < A.Wc)
-                        v = *(const uint4 *)(A.g + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
-                                             part * 8);
-                    gr[u][j][0] = v.x;
-                    gr[u][j][1] = v.y;
-                    gr[u][j][2] = v.z;
-                    gr[u][j][3] = v.w;
-                }
+            for (int j = 0; j < 4; j++) {
+                const int x = tx0 + px0 % 16 + j;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (y < A.Hc && x < A.Wc)
+                    v = *(const uint4 *)(A.g + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8);
+                gr[j][0] = v.x;
+                gr[j][1] = v.y;
+                gr[j][2] = v.z;
+                gr[j][3] = v.w;
             }
         }
 #pragma unroll
         for (int u = 0; u < kAItems; u++) {
             const int it = tid + 256 * u;
             const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
-            const int cc0 = 8 * seg, y = ty0 - 1 + r;
+            const int part = rest & 3, dx = rest >> 2, cc0 = 8 * seg;
+            const int y = ty0 - 1 + r;
             const bool yin = it < kATotal && y >= 0 && y < A.Hc;
-            if constexpr (K != WG_FIRST) {
-                const int part = rest & 3, dx = rest >> 2;
 #pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    const int x = tx0 - 1 + cc0 + dx + j;
-                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                    if (yin && x >= 0 && x < A.Wc)
-                        v = *(const uint4 *)(A.a + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
-                                             part * 8);
-                    ar[u][j][0] = v.x;
-                    ar[u][j][1] = v.y;
-                    ar[u][j][2] = v.z;
-                    ar[u][j][3] = v.w;
-                }
-            } else {
-                const int part = rest % (4 + NE), dx = rest / (4 + NE);
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    const int x = tx0 - 1 + cc0 + dx + j;
-                    const bool in = yin && x >= 0 && x < A.Wc;
-                    const int64_t pix = ((int64_t)b * A.Hc + y) * A.Wc + x;
-                    uint32_t v = 0u;
-                    if (in) v = part < 4 ? A.win[pix] : __float_as_uint(A.est[pix]);
-                    ar[u][j][0] = v;
-                }
+            for (int j = 0; j < 8; j++) {
+                const int x = tx0 - 1 + cc0 + dx + j;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (yin && x >= 0 && x < A.Wc)
+                    v = *(const uint4 *)(A.a + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8);
+                ar[u][j][0] = v.x;
+                ar[u][j][1] = v.y;
+                ar[u][j][2] = v.z;
+                ar[u][j][3] = v.w;
             }
         }
     };
-    // the registers of the loaded tile into LDS, channel-major
+    // the registers of the loaded tile into LDS, channel-major: channel
+    // vectors transposed in registers and written as channel rows
     auto commit_tile = [&]() {
-        if constexpr (K == WG_LAST) {
-            gT[0][tid] = to_bf16(__uint_as_float(gr[0][0][0]));
-        } else {
-            // 4 channel vectors transposed in registers and written as 8
-            // channel rows of 8 bytes
+        {
+            const int seg = tid & 63, part = tid >> 6, px0 = 4 * seg;
 #pragma unroll
-            for (int u = 0; u < kGItems; u++) {
-                const int it = tid + 256 * u;
-                const int seg = it & 63, part = it >> 6, px0 = 4 * seg;
-#pragma unroll
-                for (int e2 = 0; e2 < 4; e2++) {
-                    uint2 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 3
-                    lo.x = (gr[u][0][e2] & 0xFFFFu) | (gr[u][1][e2] << 16);
-                    lo.y = (gr[u][2][e2] & 0xFFFFu) | (gr[u][3][e2] << 16);
-                    hi.x = (gr[u][0][e2] >> 16) | (gr[u][1][e2] & 0xFFFF0000u);
-                    hi.y = (gr[u][2][e2] >> 16) | (gr[u][3][e2] & 0xFFFF0000u);
-                    *(uint2 *)(&gT[part * 8 + 2 * e2][px0]) = lo;
-                    *(uint2 *)(&gT[part * 8 + 2 * e2 + 1][px0]) = hi;
-                }
+            for (int e2 = 0; e2 < 4; e2++) {
+                uint2 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 3
+                lo.x = (gr[0][e2] & 0xFFFFu) | (gr[1][e2] << 16);
+                lo.y = (gr[2][e2] & 0xFFFFu) | (gr[3][e2] << 16);
+                hi.x = (gr[0][e2] >> 16) | (gr[1][e2] & 0xFFFF0000u);
+                hi.y = (gr[2][e2] >> 16) | (gr[3][e2] & 0xFFFF0000u);
+                *(uint2 *)(&gT[part * 8 + 2 * e2][px0]) = lo;
+                *(uint2 *)(&gT[part * 8 + 2 * e2 + 1][px0]) = hi;
             }
         }
 #pragma unroll
@@ -763,51 +725,20 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
             const int it = tid + 256 * u;
             if (it >= kATotal) continue;
             const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
-            const int cc0 = 8 * seg;
-            if constexpr (K != WG_FIRST) {
-                const int part = rest & 3, dx = rest >> 2;
+            const int part = rest & 3, dx = rest >> 2, cc0 = 8 * seg;
 #pragma unroll
-                for (int e2 = 0; e2 < 4; e2++) {
-                    uint4 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 7
-                    lo.x = (ar[u][0][e2] & 0xFFFFu) | (ar[u][1][e2] << 16);
-                    lo.y = (ar[u][2][e2] & 0xFFFFu) | (ar[u][3][e2] << 16);
-                    lo.z = (ar[u][4][e2] & 0xFFFFu) | (ar[u][5][e2] << 16);
-                    lo.w = (ar[u][6][e2] & 0xFFFFu) | (ar[u][7][e2] << 16);
-                    hi.x = (ar[u][0][e2] >> 16) | (ar[u][1][e2] & 0xFFFF0000u);
-                    hi.y = (ar[u][2][e2] >> 16) | (ar[u][3][e2] & 0xFFFF0000u);
-                    hi.z = (ar[u][4][e2] >> 16) | (ar[u][5][e2] & 0xFFFF0000u);
-                    hi.w = (ar[u][6][e2] >> 16) | (ar[u][7][e2] & 0xFFFF0000u);
-                    *(uint4 *)(&aT[dx][part * 8 + 2 * e2][r * 16 + cc0]) = lo;
-                    *(uint4 *)(&aT[dx][part * 8 + 2 * e2 + 1][r * 16 + cc0]) = hi;
-                }
-            } else {
-                // first layer: the 8 bit channels of byte `part` of the 8
-                // pixels' windows, transposed (an 8 x 8 bit transpose) into 8
-                // channel rows of 8 bfloat16 ones and zeros, each one 16-byte
-                // store; part 4 is the estimate channel of the same pixels
-                const int part = rest % (4 + NE), dx = rest / (4 + NE);
-                if (part < 4) {
-                    uint64_t m = 0;  // byte j: pixel j's channels part*8 .. +7
-#pragma unroll
-                    for (int j = 0; j < 8; j++)
-                        m |= (uint64_t)((ar[u][j][0] >> (8 * part)) & 0xFFu) << (8 * j);
-                    // byte e of m becomes channel e's bits over pixels 0 .. 7
-                    uint64_t t = (m ^ (m >> 7)) & 0x00AA00AA00AA00AAull;
-                    m ^= t ^ (t << 7);
-                    t = (m ^ (m >> 14)) & 0x0000CCCC0000CCCCull;
-                    m ^= t ^ (t << 14);
-                    t = (m ^ (m >> 28)) & 0x00000000F0F0F0F0ull;
-                    m ^= t ^ (t << 28);
-#pragma unroll
-                    for (int e = 0; e < 8; e++)
-                        *(bf16x8 *)(&aT[dx][part * 8 + e][r * 16 + cc0]) =
-                            bits_to_bf16((uint32_t)(m >> (8 * e)) & 0xFFu);
-                } else if constexpr (NE) {
-                    bf16x8 v;
-#pragma unroll
-                    for (int j = 0; j < 8; j++) v[j] = to_bf16(__uint_as_float(ar[u][j][0]));
-                    *(bf16x8 *)(&aT[dx][32][r * 16 + cc0]) = v;
-                }
+            for (int e2 = 0; e2 < 4; e2++) {
+                uint4 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 7
+                lo.x = (ar[u][0][e2] & 0xFFFFu) | (ar[u][1][e2] << 16);
+                lo.y = (ar[u][2][e2] & 0xFFFFu) | (ar[u][3][e2] << 16);
+                lo.z = (ar[u][4][e2] & 0xFFFFu) | (ar[u][5][e2] << 16);
+                lo.w = (ar[u][6][e2] & 0xFFFFu) | (ar[u][7][e2] << 16);
+                hi.x = (ar[u][0][e2] >> 16) | (ar[u][1][e2] & 0xFFFF0000u);
+                hi.y = (ar[u][2][e2] >> 16) | (ar[u][3][e2] & 0xFFFF0000u);
+                hi.z = (ar[u][4][e2] >> 16) | (ar[u][5][e2] & 0xFFFF0000u);
+                hi.w = (ar[u][6][e2] >> 16) | (ar[u][7][e2] & 0xFFFF0000u);
+                *(uint4 *)(&aT[dx][part * 8 + 2 * e2][r * 16 + cc0]) = lo;
+                *(uint4 *)(&aT[dx][part * 8 + 2 * e2 + 1][r * 16 + cc0]) = hi;
             }
         }
     };
@@ -822,38 +753,189 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
         // time, and nine independent accumulators back to back
 #pragma unroll
         for (int s = 0; s < 8; s++) {
-            bf16x8 Af;
-            if constexpr (K == WG_LAST) {
-#pragma unroll
-                for (int e = 0; e < 8; e++) Af[e] = (__bf16)0.0f;
-                if (i == 0) Af = *(const bf16x8 *)(&gT[0][32 * s + 8 * gq]);
-            } else {
-                Af = *(const bf16x8 *)(&gT[cb * 16 + i][32 * s + 8 * gq]);
-            }
+            const bf16x8 Af = *(const bf16x8 *)(&gT[cb * 16 + i][32 * s + 8 * gq]);
 #pragma unroll
             for (int t = 0; t < 9; t++) {
-                if (t < tap0 || t >= tap1) continue;
                 const int dy = t / 3, dx = t % 3;
                 // pixels 32s + 8gq .. +7: tile row 2s + gq/2, columns 8(gq&1) ..
                 const int row = 2 * s + (gq >> 1) + dy, col = 8 * (gq & 1);
                 const bf16x8 Bf = *(const bf16x8 *)(&aT[dx][jb * 16 + i][row * 16 + col]);
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[t], 0, 0, 0);
-                if constexpr (NE) {
-                    if (jb == 0) {
-                        // estimate channel in column 0 of a third input block
-                        bf16x8 Be;
-#pragma unroll
-                        for (int e = 0; e < 8; e++) Be[e] = (__bf16)0.0f;
-                        if (i == 0) Be = *(const bf16x8 *)(&aT[dx][32][row * 16 + col]);
-                        acce[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Be, acce[t], 0, 0, 0);
-                    }
-                }
             }
         }
         // bias: column sums of the gradient tile
-        if (tid < CO * 8) {
 #pragma unroll 8
-            for (int k = 0; k < 256 / 8; k++) bsum += (float)gT[tid / 8][(tid % 8) * 32 + k];
+        for (int k = 0; k < 256 / 8; k++) bsum += (float)gT[tid / 8][(tid % 8) * 32 + k];
+        __syncthreads();
+    }
+    // partial gradient of this workgroup, in the parameter blob's order
+    float *out = A.partial + (int64_t)blockIdx.x * S::np;
+#pragma unroll
+    for (int t = 0; t < 9; t++) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            // D[co 4*(lane/16) + r][ci lane%16] of this wave's blocks
+            const int co = cb * 16 + 4 * gq + r, ci = jb * 16 + i;
+            out[(co * 9 + t) * S::cin + ci] = acc[t][r];
+        }
+    }
+    // bias sums: 8 threads per channel, combined in a fixed order
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) bsum += __shfl_xor(bsum, m, 64);
+    if (tid % 8 == 0) out[S::nw + tid / 8] = bsum;
+}
+
+// Weight gradient of the first layer.  Written with q = p + off(tap),
+// dW[co][tap][ci] = sum_q g[q - off(tap)][co] x[q][ci] is, per tap, a GEMM
+// with M = output channels, N = input channels (32 window bits and the
+// estimate) and K = pixels.  The input channels then need no halo -- each
+// tile's window bits are expanded to bfloat16 once, 8 x 8 bit transposes
+// into channel-major rows -- and the 32-channel gradient carries the halo,
+// staged like the hidden layers' activations (three copies shifted by the
+// horizontal tap offset, so every fragment is an aligned 16-byte read).
+// Wave w takes output block w >> 1 and input block w & 1 for all taps;
+// the estimate is column 0 of a third input block on the waves with input
+// block 0.  The next tile's loads are in flight while the current one is
+// computed.  Partial row as wgrad_kernel's.
+__global__ __launch_bounds__(256) void wgrad_first_kernel(WgArgs A)
+{
+    using S = WgShape<WG_FIRST>;
+    static_assert(S::cout == 32 && S::cin == 33, "first layer");
+    __shared__ __attribute__((aligned(16))) __bf16 xT[33][256 + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 gH[3][32][18 * 16 + 8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = lane & 15, gq = lane >> 4;
+    const int cb = wave >> 1, jb = wave & 1;
+    f32x4 acc[9], acce[9];
+#pragma unroll
+    for (int t = 0; t < 9; t++) acc[t] = acce[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;  // bias partial of thread tid: channel tid / 8, pixels (tid % 8) * 32 ..
+    // registers of the next tile: window words of piece (part, seg) (threads
+    // 0 .. 127: 8 pixels, byte `part`), the estimate of pixel tid, and two
+    // gradient-halo pieces (dx, part, r, seg) of 8 pixels x 8 channels
+    constexpr int kHTotal = 3 * 4 * 18 * 2;
+    constexpr int kHItems = (kHTotal + 255) / 256;
+    uint32_t xw[8];
+    float xe;
+    uint32_t hr_[kHItems][8][4];
+    auto load_tile = [&](int tile) {
+        const int b = tile / (A.tx * A.ty);
+        const int ty0 = ((tile / A.tx) % A.ty) * 16, tx0 = (tile % A.tx) * 16;
+        {
+            const int seg = tid & 31, px0 = 8 * seg;
+            const int y = ty0 + px0 / 16;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const int x = tx0 + px0 % 16 + j;
+                xw[j] = tid < 128 && y < A.Hc && x < A.Wc
+                            ? A.win[((int64_t)b * A.Hc + y) * A.Wc + x]
+                            : 0u;
+            }
+            const int ye = ty0 + tid / 16, xe_ = tx0 + tid % 16;
+            xe = ye < A.Hc && xe_ < A.Wc ? A.est[((int64_t)b * A.Hc + ye) * A.Wc + xe_] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kHItems; u++) {
+            const int it = tid + 256 * u;
+            const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
+            const int part = rest & 3, dx = rest >> 2, cc0 = 8 * seg;
+            const int y = ty0 - 1 + r;
+            const bool yin = it < kHTotal && y >= 0 && y < A.Hc;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const int x = tx0 - 1 + cc0 + dx + j;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (yin && x >= 0 && x < A.Wc)
+                    v = *(const uint4 *)(A.g + (((int64_t)b * A.Hc + y) * A.Wc + x) * C + part * 8);
+                hr_[u][j][0] = v.x;
+                hr_[u][j][1] = v.y;
+                hr_[u][j][2] = v.z;
+                hr_[u][j][3] = v.w;
+            }
+        }
+    };
+    auto commit_tile = [&]() {
+        if (tid < 128) {
+            // byte `part` of 8 pixels' windows, 8 x 8 bit transposed into the
+            // rows of channels part*8 .. +7 (bfloat16 ones and zeros)
+            const int seg = tid & 31, part = tid >> 5, px0 = 8 * seg;
+            uint64_t m = 0;  // byte j: pixel j's channels part*8 .. +7
+#pragma unroll
+            for (int j = 0; j < 8; j++) m |= (uint64_t)((xw[j] >> (8 * part)) & 0xFFu) << (8 * j);
+            uint64_t t = (m ^ (m >> 7)) & 0x00AA00AA00AA00AAull;
+            m ^= t ^ (t << 7);
+            t = (m ^ (m >> 14)) & 0x0000CCCC0000CCCCull;
+            m ^= t ^ (t << 14);
+            t = (m ^ (m >> 28)) & 0x00000000F0F0F0F0ull;
+            m ^= t ^ (t << 28);
+#pragma unroll
+            for (int e = 0; e < 8; e++)
+                *(bf16x8 *)(&xT[part * 8 + e][px0]) = bits_to_bf16((uint32_t)(m >> (8 * e)) & 0xFFu);
+        }
+        xT[32][tid] = to_bf16(xe);
+#pragma unroll
+        for (int u = 0; u < kHItems; u++) {
+            const int it = tid + 256 * u;
+            if (it >= kHTotal) continue;
+            const int seg = it & 1, r = (it >> 1) % 18, rest = (it >> 1) / 18;
+            const int part = rest & 3, dx = rest >> 2, cc0 = 8 * seg;
+#pragma unroll
+            for (int e2 = 0; e2 < 4; e2++) {
+                uint4 lo, hi;  // channels 2 e2 and 2 e2 + 1, pixels 0 .. 7
+                lo.x = (hr_[u][0][e2] & 0xFFFFu) | (hr_[u][1][e2] << 16);
+                lo.y = (hr_[u][2][e2] & 0xFFFFu) | (hr_[u][3][e2] << 16);
+                lo.z = (hr_[u][4][e2] & 0xFFFFu) | (hr_[u][5][e2] << 16);
+                lo.w = (hr_[u][6][e2] & 0xFFFFu) | (hr_[u][7][e2] << 16);
+                hi.x = (hr_[u][0][e2] >> 16) | (hr_[u][1][e2] & 0xFFFF0000u);
+                hi.y = (hr_[u][2][e2] >> 16) | (hr_[u][3][e2] & 0xFFFF0000u);
+                hi.z = (hr_[u][4][e2] >> 16) | (hr_[u][5][e2] & 0xFFFF0000u);
+                hi.w = (hr_[u][6][e2] >> 16) | (hr_[u][7][e2] & 0xFFFF0000u);
+                *(uint4 *)(&gH[dx][part * 8 + 2 * e2][r * 16 + cc0]) = lo;
+                *(uint4 *)(&gH[dx][part * 8 + 2 * e2 + 1][r * 16 + cc0]) = hi;
+            }
+        }
+    };
+
+    if ((int)blockIdx.x < A.ntiles) load_tile(blockIdx.x);
+    for (int tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+        commit_tile();
+        __syncthreads();
+        if (tile + (int)gridDim.x < A.ntiles) load_tile(tile + gridDim.x);
+#pragma unroll
+        for (int s = 0; s < 8; s++) {
+            // pixels q = 32s + 8gq .. +7: tile row 2s + gq/2, columns 8(gq&1) ..
+            const int row = 2 * s + (gq >> 1), col = 8 * (gq & 1);
+            const bf16x8 Bf = *(const bf16x8 *)(&xT[jb * 16 + i][32 * s + 8 * gq]);
+            bf16x8 Be;
+#pragma unroll
+            for (int e = 0; e < 8; e++) Be[e] = (__bf16)0.0f;
+            if (jb == 0 && i == 0) Be = *(const bf16x8 *)(&xT[32][32 * s + 8 * gq]);
+#pragma unroll
+            for (int t = 0; t < 9; t++) {
+                // the gradient for q at tap (dy, dx) is at halo (row + 2 - dy,
+                // col + 2 - dx): copy 2 - dx
+                const int dy = t / 3, dx = t % 3;
+                const bf16x8 Af =
+                    *(const bf16x8 *)(&gH[2 - dx][cb * 16 + i][(row + 2 - dy) * 16 + col]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[t], 0, 0, 0);
+                if (jb == 0)
+                    acce[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Be, acce[t], 0, 0, 0);
+            }
+        }
+        // bias: column sums of the tile's gradients (copy 1 holds tile
+        // columns 0 .. 15 in halo rows 1 .. 16), the tile's pixels in order
+        {
+            const int co = tid / 8, prt = tid % 8;
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int hrow = 1 + 2 * prt + h;
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const bf16x8 v = *(const bf16x8 *)(&gH[1][co][hrow * 16 + 8 * q]);
+#pragma unroll
+                    for (int e = 0; e < 8; e++) bsum += (float)v[e];
+                }
+            }
         }
         __syncthreads();
     }
@@ -861,20 +943,18 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
     float *out = A.partial + (int64_t)blockIdx.x * S::np;
 #pragma unroll
     for (int t = 0; t < 9; t++) {
-        if (t < tap0 || t >= tap1) continue;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             // D[co 4*(lane/16) + r][ci lane%16] of this wave's blocks
             const int co = cb * 16 + 4 * gq + r, ci = jb * 16 + i;
-            if (co < CO) out[(co * 9 + t) * S::cin + ci] = acc[t][r];
-            if constexpr (NE)
-                if (jb == 0 && i == 0) out[(co * 9 + t) * S::cin + 32] = acce[t][r];
+            out[(co * 9 + t) * S::cin + ci] = acc[t][r];
+            if (jb == 0 && i == 0) out[(co * 9 + t) * S::cin + 32] = acce[t][r];
         }
     }
     // bias sums: 8 threads per channel, combined in a fixed order
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1) bsum += __shfl_xor(bsum, m, 64);
-    if (tid < CO * 8 && tid % 8 == 0) out[S::nw + tid / 8] = bsum;
+    if (tid % 8 == 0) out[S::nw + tid / 8] = bsum;
 }
 
 // Weight gradient of the output layer (one output channel).  Written with
@@ -1223,8 +1303,10 @@ void launch_wgrad(WgArgs a, float *dst, RedArgs &R, hipStream_t st)
     const int nblk = a.ntiles < kWgMaxBlocks ? a.ntiles : kWgMaxBlocks;
     if constexpr (K == WG_LAST)
         hipLaunchKernelGGL(wgrad_last_kernel, dim3(nblk), dim3(256), 0, st, a);
+    else if constexpr (K == WG_FIRST)
+        hipLaunchKernelGGL(wgrad_first_kernel, dim3(nblk), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(wgrad_kernel<K>, dim3(nblk), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(wgrad_kernel, dim3(nblk), dim3(256), 0, st, a);
     const int np = WgShape<K>::np;
     RedSeg &S = R.seg[R.nseg++];
     S.partial = a.partial;
