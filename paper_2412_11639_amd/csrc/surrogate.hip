@@ -763,9 +763,14 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[t], 0, 0, 0);
             }
         }
-        // bias: column sums of the gradient tile
-#pragma unroll 8
-        for (int k = 0; k < 256 / 8; k++) bsum += (float)gT[tid / 8][(tid % 8) * 32 + k];
+        // bias: column sums of the gradient tile (pixels (tid % 8) * 32 ..
+        // +31 of channel tid / 8, in order, four 16-byte reads)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const bf16x8 v = *(const bf16x8 *)(&gT[tid / 8][(tid % 8) * 32 + 8 * q]);
+#pragma unroll
+            for (int e = 0; e < 8; e++) bsum += (float)v[e];
+        }
         __syncthreads();
     }
     // partial gradient of this workgroup, in the parameter blob's order
