@@ -20,6 +20,7 @@ namespace spk {
 namespace {
 
 constexpr int kDecFrames = 32;  // output frames per tile
+constexpr int kWin = 8;         // records a lane holds (per-pixel lists)
 
 // One wave per 64 pixels (lane = pixel).  Segment s of a pixel covers the
 // requested frames (in time order) from index B(s-1) up to B(s), where
@@ -39,8 +40,15 @@ constexpr int kDecFrames = 32;  // output frames per tile
 // paid once per boundary instead of in every frame the wave visits.
 //
 // PACKED: the lists are [HW][cap][3] (a pixel's records one after another,
-// seg_first pointing at them): a lane's record loads walk its own lines,
-// each fetched once, instead of taking a line of a [cap][HW] row per load.
+// seg_first pointing at them).  A lane keeps a window of kWin of its records
+// in registers and refills it in one burst (kWin consecutive 12-byte
+// loads) when the window runs out, so each line of its list is read within
+// one refill instead of once per record, about ten tiles apart, by which
+// time the line has often left the L2.  The refill is issued at the end of
+// the advance that empties the window and the next advance selects from it,
+// so the loads have the tile's work to arrive in; the record is selected by
+// index rather than shifted down the window, since a register copy would
+// wait for the loads in flight.
 template <bool IDENT, bool AP, bool PACKED>
 __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
                                                     const int32_t *seg_last,
@@ -64,12 +72,25 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
     int32_t s = -1, nf = 0, nl = 0, nn = 0;
     float I = 0.0f;      // S == 0: fewer than two spikes, every output is 0
     int32_t B = INT_MAX;
-    auto fetch = [&](int32_t k) {
+    // PACKED: records wbase .. wbase + kWin - 1 (those stored)
+    int32_t wb[PACKED ? kWin : 1][3];
+    int32_t wbase = 0;
+    auto refill = [&](int32_t k) {
         if constexpr (PACKED) {
             const int32_t *r = seg_first + ((p0 + lane) * cap + k) * 3;
-            nf = r[0];
-            nl = r[1];
-            nn = r[2];
+#pragma unroll
+            for (int j = 0; j < kWin; j++)
+                if (k + j < stored) {
+                    wb[j][0] = r[3 * j];
+                    wb[j][1] = r[3 * j + 1];
+                    wb[j][2] = r[3 * j + 2];
+                }
+            wbase = k;
+        }
+    };
+    auto fetch = [&](int32_t k) {
+        if constexpr (PACKED) {
+            if (k - wbase >= kWin) refill(k);  // selected at the next advance
         } else {
             const int64_t o = (int64_t)k * HW + p0 + lane;
             nf = seg_first[o];
@@ -80,6 +101,16 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
     auto advance = [&]() {
         s++;
         if (s < stored) {
+            if constexpr (PACKED) {
+                const int j = s - wbase;
+#pragma unroll
+                for (int q = 0; q < kWin; q++)
+                    if (q == j) {
+                        nf = wb[q][0];
+                        nl = wb[q][1];
+                        nn = wb[q][2];
+                    }
+            }
             // Eq. 6 as in the reconstruction pass
             I = (float)(theta * (double)nn / (double)((int64_t)nl - nf));
             // requested times <= the segment's last spike: from the
@@ -102,7 +133,11 @@ __global__ __launch_bounds__(64) void decode_kernel(const int32_t *seg_first,
         }
     };
     if (S > 0) {
-        if (stored > 0) fetch(0);
+        if constexpr (PACKED) {
+            if (stored > 0) refill(0);
+        } else {
+            if (stored > 0) fetch(0);
+        }
         advance();
     }
     const uint32_t ulane = (uint32_t)lane;
