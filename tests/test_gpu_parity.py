@@ -478,6 +478,46 @@ def test_decode_every_frame_short_segments(spk, order_name):
                                       ref_all.reshape(T, -1)[t_out])
 
 
+def test_decode_packed_window_edges(spk):
+    """The per-pixel decoder holds 8 records of a list in registers and
+    refills them in bursts: lists cut at every cap from 1 to 19 (shorter
+    than, equal to and just past one or two windows) and pixels whose
+    lists end at every length decode exactly as the [cap][H*W] decoder
+    (NaN where NaN) and, where not cut, as the oracle."""
+    rng = np.random.default_rng(77)
+    H, W, T = 5, 41, 900
+    P = H * W
+    bits = np.zeros((T, P), dtype=np.uint8)
+    for p in range(P):
+        # segment counts from 0 to about 40: a fixed rate with a jump every
+        # 20 + p frames (each jump can cut a segment)
+        step = 2 + p % 5
+        t, k = int(rng.integers(0, 3)), 0
+        stop = int(rng.integers(0, T))
+        while t < stop:
+            bits[t, p] = 1
+            k += 1
+            t += step + (3 if k % (4 + p % 7) == 0 else 0)
+    s = spkgen.pack(bits)
+    ds = dev(s)
+    t_out = list(range(0, T, 3))
+    cnt = spk.segments(ds, H, W, T, order=spk.SSR, cap=0)[3]
+    counts = cnt.cpu().numpy()
+    assert counts.max() > 19 and (counts == 0).any()
+    ref = oracle.reconstruct(s, H, W, T, 1.0, t_out, order=2).astype(np.float32)
+    ref = ref.reshape(len(t_out), -1)
+    for cap in list(range(1, 20)) + [int(counts.max())]:
+        print("decode window cap=%d" % cap, flush=True)
+        rec, c2 = spk.segments_packed(ds, H, W, T, order=spk.SSR, cap=cap)
+        got = spk.decode_packed(rec, c2, H, W, T, 1.0, t_out).cpu().numpy().reshape(len(t_out), -1)
+        sf, sl, sn, c3 = spk.segments(ds, H, W, T, order=spk.SSR, cap=cap)
+        want = spk.decode(sf, sl, sn, c3, H, W, T, 1.0, t_out).cpu().numpy().reshape(len(t_out), -1)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got, want)
+        whole = counts <= cap
+        np.testing.assert_array_equal(got[:, whole], ref[:, whole])
+
+
 def test_decode_with_no_stored_segments(spk):
     """Lists taken with cap 0 (no records at all): a pixel that has segments
     decodes to NaN at every requested frame, one with fewer than two spikes
