@@ -458,23 +458,40 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
         for (int r = 0; r < 4; r++)
 #pragma unroll
             for (int n = 0; n < S::nb; n++) acc[r][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        // 32-channel taps: the fragment of halo row 4w + iy shifted by dx
+        // is read once and serves every output row r with dy = iy - r in
+        // 0..2 (tap s = 3 dy + dx), 18 reads for 36 row-taps.  Each
+        // accumulator still takes its taps in the order s = 0 .. 8.
+        if constexpr (VEC_IN) {
 #pragma unroll
-        for (int s = 0; s < S::steps; s++) {
+            for (int iy = 0; iy < 6; iy++)
+#pragma unroll
+                for (int dx = 0; dx < 3; dx++) {
+                    const bf16x8 a =
+                        *(const bf16x8 *)(&tin[((4 * wave + iy) * 18 + i + dx) * CP + 8 * g]);
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int dy = iy - r;
+                        if (dy < 0 || dy > 2) continue;
+#pragma unroll
+                        for (int n = 0; n < S::nb; n++)
+                            acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a, Bop[3 * dy + dx][n], acc[r][n], 0, 0, 0);
+                    }
+                }
+        }
+        // the scalar channel's step (last): row k of the K block = tap k
+        if constexpr (SCALAR_IN) {
+            constexpr int s = S::steps - 1;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int oy = 4 * wave + r;  // block row of the output
                 bf16x8 a;
-                const bool scalar_step = KIND == CK_DGRAD_LAST || (KIND == CK_FIRST && s == 9);
-                if (scalar_step) {
-                    // row k of the K block = tap k of the scalar channel
-                    if (g < 2) {
-                        a = *(const bf16x8 *)(&tcol[(oy * 16 + i) * 16 + 8 * g]);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; e++) a[e] = (__bf16)0.0f;
-                    }
+                if (g < 2) {
+                    a = *(const bf16x8 *)(&tcol[(oy * 16 + i) * 16 + 8 * g]);
                 } else {
-                    a = *(const bf16x8 *)(&tin[((oy + s / 3) * 18 + i + s % 3) * CP + 8 * g]);
+#pragma unroll
+                    for (int e = 0; e < 8; e++) a[e] = (__bf16)0.0f;
                 }
 #pragma unroll
                 for (int n = 0; n < S::nb; n++)
@@ -792,36 +809,44 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs A)
 
 // Weight gradient of the first layer.  Written with q = p + off(tap),
 // dW[co][tap][ci] = sum_q g[q - off(tap)][co] x[q][ci] is, per tap, a GEMM
-// with M = output channels, N = input channels (32 window bits and the
-// estimate) and K = pixels.  The input channels then need no halo -- each
-// tile's window bits are expanded to bfloat16 once, 8 x 8 bit transposes
-// into channel-major rows -- and the 32-channel gradient carries the halo,
-// staged like the hidden layers' activations (three copies shifted by the
-// horizontal tap offset, so every fragment is an aligned 16-byte read).
-// Wave w takes output block w >> 1 and input block w & 1 for all taps;
-// the estimate is column 0 of a third input block on the waves with input
-// block 0.  The next tile's loads are in flight while the current one is
-// computed.  Partial row as wgrad_kernel's.
+// with M = output channels, N = the 32 window-bit channels and K = pixels.
+// The input channels then need no halo -- each tile's window bits are
+// expanded to bfloat16 once, 8 x 8 bit transposes into channel-major rows
+// -- and the 32-channel gradient carries the halo, staged like the hidden
+// layers' activations (three copies shifted by the horizontal tap offset,
+// so every fragment is an aligned 16-byte read).  Wave w takes output
+// block w >> 1 and input block w & 1 for all taps.  The estimate channel
+// is one GEMM for all taps, dW[co][tap] = sum_p g[p][co] est[p + off(tap)]
+// with N = taps (9 of 16): the gradient's unshifted fragment against the
+// estimate's halo, staged in three shifted bfloat16 copies; the waves with
+// input block 0 run it.  The next tile's loads are in flight while the
+// current one is computed.  Partial row as wgrad_kernel's.
 __global__ __launch_bounds__(256) void wgrad_first_kernel(WgArgs A)
 {
     using S = WgShape<WG_FIRST>;
     static_assert(S::cout == 32 && S::cin == 33, "first layer");
-    __shared__ __attribute__((aligned(16))) __bf16 xT[33][256 + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 xT[32][256 + 8];
     __shared__ __attribute__((aligned(16))) __bf16 gH[3][32][18 * 16 + 8];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the estimate's 18 x 18 halo as bfloat16, copy d holding columns
+    // d .. d + 15
+    __shared__ __attribute__((aligned(16))) __bf16 eH[3][18][16];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int i = lane & 15, gq = lane >> 4;
     const int cb = wave >> 1, jb = wave & 1;
-    f32x4 acc[9], acce[9];
+    f32x4 acc[9];
 #pragma unroll
-    for (int t = 0; t < 9; t++) acc[t] = acce[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 9; t++) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // the estimate channel (waves with jb == 0): D[co][tap] of block cb
+    f32x4 acce = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;  // bias partial of thread tid: channel tid / 8, pixels (tid % 8) * 32 ..
     // registers of the next tile: window words of piece (part, seg) (threads
-    // 0 .. 127: 8 pixels, byte `part`), the estimate of pixel tid, and two
+    // 0 .. 127: 8 pixels, byte `part`), two estimate-halo values, and two
     // gradient-halo pieces (dx, part, r, seg) of 8 pixels x 8 channels
     constexpr int kHTotal = 3 * 4 * 18 * 2;
     constexpr int kHItems = (kHTotal + 255) / 256;
     uint32_t xw[8];
-    float xe;
+    float xe[2];
     uint32_t hr_[kHItems][8][4];
     auto load_tile = [&](int tile) {
         const int b = tile / (A.tx * A.ty);
@@ -836,8 +861,14 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(WgArgs A)
                             ? A.win[((int64_t)b * A.Hc + y) * A.Wc + x]
                             : 0u;
             }
-            const int ye = ty0 + tid / 16, xe_ = tx0 + tid % 16;
-            xe = ye < A.Hc && xe_ < A.Wc ? A.est[((int64_t)b * A.Hc + ye) * A.Wc + xe_] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int q = tid + 256 * u;
+                const int ye = ty0 - 1 + q / 18, xe_ = tx0 - 1 + q % 18;
+                xe[u] = q < 18 * 18 && ye >= 0 && ye < A.Hc && xe_ >= 0 && xe_ < A.Wc
+                            ? A.est[((int64_t)b * A.Hc + ye) * A.Wc + xe_]
+                            : 0.0f;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kHItems; u++) {
@@ -877,7 +908,17 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(WgArgs A)
             for (int e = 0; e < 8; e++)
                 *(bf16x8 *)(&xT[part * 8 + e][px0]) = bits_to_bf16((uint32_t)(m >> (8 * e)) & 0xFFu);
         }
-        xT[32][tid] = to_bf16(xe);
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int q = tid + 256 * u;
+            if (q < 18 * 18) {
+                const int hr = q / 18, hc = q % 18;
+                const __bf16 v = to_bf16(xe[u]);
+#pragma unroll
+                for (int d = 0; d < 3; d++)
+                    if (hc - d >= 0 && hc - d < 16) eH[d][hr][hc - d] = v;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < kHItems; u++) {
             const int it = tid + 256 * u;
@@ -911,10 +952,6 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(WgArgs A)
             // pixels q = 32s + 8gq .. +7: tile row 2s + gq/2, columns 8(gq&1) ..
             const int row = 2 * s + (gq >> 1), col = 8 * (gq & 1);
             const bf16x8 Bf = *(const bf16x8 *)(&xT[jb * 16 + i][32 * s + 8 * gq]);
-            bf16x8 Be;
-#pragma unroll
-            for (int e = 0; e < 8; e++) Be[e] = (__bf16)0.0f;
-            if (jb == 0 && i == 0) Be = *(const bf16x8 *)(&xT[32][32 * s + 8 * gq]);
 #pragma unroll
             for (int t = 0; t < 9; t++) {
                 // the gradient for q at tap (dy, dx) is at halo (row + 2 - dy,
@@ -923,8 +960,17 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(WgArgs A)
                 const bf16x8 Af =
                     *(const bf16x8 *)(&gH[2 - dx][cb * 16 + i][(row + 2 - dy) * 16 + col]);
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[t], 0, 0, 0);
-                if (jb == 0)
-                    acce[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Be, acce[t], 0, 0, 0);
+                if (t == 4 && jb == 0) {
+                    // estimate channel, un-substituted: dW[co][tap] =
+                    // sum_p g[p][co] est[p + off(tap)], A = the gradient at
+                    // p (tap 4's fragment), B column i = tap i, read at halo
+                    // (row + dy', col + dx') of the estimate
+                    bf16x8 Be;
+#pragma unroll
+                    for (int e = 0; e < 8; e++) Be[e] = (__bf16)0.0f;
+                    if (i < 9) Be = *(const bf16x8 *)(&eH[i % 3][row + i / 3][col]);
+                    acce = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Be, acce, 0, 0, 0);
+                }
             }
         }
         // bias: column sums of the tile's gradients (copy 1 holds tile
@@ -953,8 +999,13 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(WgArgs A)
             // D[co 4*(lane/16) + r][ci lane%16] of this wave's blocks
             const int co = cb * 16 + 4 * gq + r, ci = jb * 16 + i;
             out[(co * 9 + t) * S::cin + ci] = acc[t][r];
-            if (jb == 0 && i == 0) out[(co * 9 + t) * S::cin + 32] = acce[t][r];
         }
+    }
+    // D[co 4*(lane/16) + r][tap lane%16] of the estimate channel
+    if (jb == 0 && i < 9) {
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            out[((cb * 16 + 4 * gq + r) * 9 + i) * S::cin + 32] = acce[r];
     }
     // bias sums: 8 threads per channel, combined in a fixed order
 #pragma unroll
