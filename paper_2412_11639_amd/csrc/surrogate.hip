@@ -335,7 +335,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
     __shared__ __attribute__((aligned(16))) __bf16 tcol[SCALAR_IN ? 256 * 16 : 8];
     __shared__ __attribute__((aligned(16))) __bf16 stage[4][KIND == CK_LAST ? 8 : 16 * SP];
     __shared__ float stagef[4][KIND == CK_LAST ? 64 : 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int i = lane & 15, g = lane >> 4;
     // this layer's weights, resident in registers
     bf16x8 Bop[S::steps][S::nb];
@@ -453,6 +454,20 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
         if constexpr (KIND == CK_LAST) {
             if (lin) est_l = A.scalar[lpix];
         }
+        // input gradients: the ReLU masks of this block's output rows, loaded
+        // here so that they arrive during the MFMA work
+        bf16x8 om[KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST ? 4 : 1];
+        if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int y = y0 + 4 * wave + r, x = x0 + px;
+#pragma unroll
+                for (int e = 0; e < 8; e++) om[r][e] = (__bf16)0.0f;
+                if (x < A.Wc && y < A.Hc)
+                    om[r] = *(const bf16x8 *)(A.mask + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
+                                              part * 8);
+            }
+        }
         f32x4 acc[4][S::nb];
 #pragma unroll
         for (int r = 0; r < 4; r++)
@@ -503,7 +518,6 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
         // Global stores wait until the next halo is in LDS: its loads are
         // then the only memory operations outstanding.
         bf16x8 ov[KIND == CK_LAST ? 1 : 4];
-        bf16x8 om[KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST ? 4 : 1];
         float of = 0.0f;
         if constexpr (KIND == CK_LAST) {
             if (i == 0) {
@@ -518,18 +532,6 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs A)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             of = stagef[wave][lane];
         } else {
-            if constexpr (KIND == CK_DGRAD_MID || KIND == CK_DGRAD_LAST) {
-                // the ReLU masks of this block's output rows
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int y = y0 + 4 * wave + r, x = x0 + px;
-#pragma unroll
-                    for (int e = 0; e < 8; e++) om[r][e] = (__bf16)0.0f;
-                    if (x < A.Wc && y < A.Hc)
-                        om[r] = *(const bf16x8 *)(A.mask + (((int64_t)b * A.Hc + y) * A.Wc + x) * C +
-                                                  part * 8);
-                }
-            }
 #pragma unroll
             for (int r = 0; r < 4; r++) {
 #pragma unroll
@@ -1033,7 +1035,8 @@ __global__ __launch_bounds__(256) void wgrad_last_kernel(WgArgs A)
     __shared__ __attribute__((aligned(16))) __bf16 gH[3][18][16];
     __shared__ float red[4][2][4][64];
     __shared__ float bred[4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int i = lane & 15, gq = lane >> 4;
     f32x4 acc[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
     float bsum = 0.0f;  // this thread's pixel of every tile

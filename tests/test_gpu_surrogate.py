@@ -38,27 +38,38 @@ def _samples(streams, rng, B, Hc, Wc, T):
     return out
 
 
-def test_input_matches_oracle(sur):
+# (13, 29): 13 row tiles per crop, an odd count, so the last pair of tiles
+# is half empty; (130, 70): two tiles per row, the second ragged, and 4160
+# pairs of tiles, more than the launch's waves, so waves walk several with
+# the next one's loads in flight
+@pytest.mark.parametrize("B,Hc,Wc,H,W", [(8, 13, 29, (40, 33), (100, 70)),
+                                         (32, 130, 70, (140, 133), (160, 90))])
+def test_input_matches_oracle(sur, B, Hc, Wc, H, W):
     rng = np.random.default_rng(0)
     T = 300
-    g = spkgen.gratings(40, 100, T, seed=51)
-    k = spkgen.blocks(33, 70, T, seed=52, vx=0.4)
-    streams = [(torch.from_numpy(g).cuda(), 40, 100), (torch.from_numpy(k).cuda(), 33, 70)]
+    g = spkgen.gratings(H[0], W[0], T, seed=51)
+    k = spkgen.blocks(H[1], W[1], T, seed=52, vx=0.4)
+    streams = [(torch.from_numpy(g).cuda(), H[0], W[0]), (torch.from_numpy(k).cuda(), H[1], W[1])]
+    targets = [torch.from_numpy(rng.random((h, w), dtype=np.float32)).cuda()
+               for h, w in zip(H, W)]
     hosts = [g, k]
-    Hc, Wc = 13, 29          # not multiples of anything, unaligned crops
-    samples = _samples(streams, rng, 8, Hc, Wc, T)
-    win, est, st = sur.Surrogate.input(samples, Hc, Wc, theta=2.0)
+    samples = _samples(streams, rng, B, Hc, Wc, T)
+    for b, s in enumerate(samples):
+        s["target"] = targets[b % 2]
+    win, est, st, tg = sur.Surrogate.input(samples, Hc, Wc, theta=2.0, with_target=True)
     win, est, st = win.cpu().numpy().view(np.uint32), est.cpu().numpy(), st.cpu().numpy()
+    tg = tg.cpu().numpy()
     for b, s in enumerate(samples):
         host = hosts[b % 2]
-        H, W = s["H"], s["W"]
-        bits = spkgen.unpack(host[s["t"] - 31:s["t"] + 1], H, W).astype(np.uint64)
+        Hs, Ws = s["H"], s["W"]
+        bits = spkgen.unpack(host[s["t"] - 31:s["t"] + 1], Hs, Ws).astype(np.uint64)
         ref_win = sum(bits[j] << np.uint64(j) for j in range(32)).astype(np.uint32)
         crop = (slice(s["oy"], s["oy"] + Hc), slice(s["ox"], s["ox"] + Wc))
         np.testing.assert_array_equal(win[b], ref_win[crop])
-        e, stab = oracle.window_estimate(host, H, W, T, 2.0, s["t"])
+        e, stab = oracle.window_estimate(host, Hs, Ws, T, 2.0, s["t"])
         np.testing.assert_array_equal(est[b], e[crop].astype(np.float32))
         np.testing.assert_array_equal(st[b].astype(bool), stab[crop])
+        np.testing.assert_array_equal(tg[b], targets[b % 2].cpu().numpy()[crop])
 
 
 def test_stream_step_matches_input(sur):
