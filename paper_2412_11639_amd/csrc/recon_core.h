@@ -657,24 +657,29 @@ struct Run {
     template <int ORDER, bool CAPTURE>
     __device__ __forceinline__ uint64_t spikes(int32_t t0, uint64_t rest, int32_t lp)
     {
+        // The lowest spike's bit comes from its position and is cleared
+        // from h in place.  The clearing is one VALU instruction written
+        // out, because the compiler otherwise tests the loop's exit as
+        // bit == h on the old value, which keeps both alive and costs a
+        // register copy per spike.
         uint32_t Blo = 0, Bhi = 0;
         uint32_t h = (uint32_t)rest;
         while (h) {
-            const uint32_t nh = h & (h - 1);
             const int pos = __builtin_ctz(h);
+            const uint32_t bit = 1u << pos;
             const int32_t x = pos - lp;  // interval T0 ending at this spike
             lp = pos;
-            Blo |= step_capture<ORDER, CAPTURE>(x, t0 + pos) ? (h ^ nh) : 0u;
-            h = nh;
+            Blo |= step_capture<ORDER, CAPTURE>(x, t0 + pos) ? bit : 0u;
+            asm("v_xor_b32 %0, %1, %0" : "+v"(h) : "v"(bit));
         }
         h = (uint32_t)(rest >> 32);
         while (h) {
-            const uint32_t nh = h & (h - 1);
-            const int pos = __builtin_ctz(h) + 32;
-            const int32_t x = pos - lp;
-            lp = pos;
-            Bhi |= step_capture<ORDER, CAPTURE>(x, t0 + pos) ? (h ^ nh) : 0u;
-            h = nh;
+            const int pos = __builtin_ctz(h);
+            const uint32_t bit = 1u << pos;
+            const int32_t x = pos + 32 - lp;
+            lp = pos + 32;
+            Bhi |= step_capture<ORDER, CAPTURE>(x, t0 + 32 + pos) ? bit : 0u;
+            asm("v_xor_b32 %0, %1, %0" : "+v"(h) : "v"(bit));
         }
         return ((uint64_t)Bhi << 32) | Blo;
     }
