@@ -386,32 +386,38 @@ struct SegState {
         if constexpr (ORDER == 1) {
             return fcut;
         } else {
-            const bool odd = x & 1;
-            const int32_t l = odd ? l1 : l0;
+            // the per-value state is selected by x's parity through a mask
+            // (all ones for odd x) and bitwise selects: one instruction for
+            // the mask, written out so that the compiler does not turn the
+            // selects back into a parity test and lane-mask selects
+            uint32_t mo;
+            asm("v_bfe_i32 %0, %1, 0, 1" : "=v"(mo) : "v"(x));
+            const int32_t l = bsel(mo, l1, l0);
             const int32_t d = ii - l;  // next element of S2 for value x
-            const int32_t ngl = min(odd ? g1l : g0l, d), ngh = max(odd ? g1h : g0h, d);
+            const int32_t ngl = min(bsel(mo, g1l, g0l), d), ngh = max(bsel(mo, g1h, g0h), d);
             const bool seen = l >= ps;  // x already occurred in the open piece
             const bool cut = fcut || (seen && ngh - ngl > 1);
             const bool keep = seen && !cut;  // the value's gaps continue
             const int32_t ugl = keep ? ngl : kBig, ugh = keep ? ngh : -kBig;
-            l0 = odd ? l0 : ii;
-            l1 = odd ? ii : l1;
-            g0l = odd ? g0l : ugl;
-            g0h = odd ? g0h : ugh;
-            g1l = odd ? ugl : g1l;
-            g1h = odd ? ugh : g1h;
+            l0 = bsel(mo, l0, ii);
+            l1 = bsel(mo, ii, l1);
+            g0l = bsel(mo, g0l, ugl);
+            g0h = bsel(mo, g0h, ugh);
+            g1l = bsel(mo, ugl, g1l);
+            g1h = bsel(mo, ugh, g1h);
             ps = cut ? ii : ps;
             if constexpr (ORDER == 4) {
                 // third order: d is the new element of S2(x) if x occurred in
                 // the open sub-piece; its S3 gap is the distance (in S2
                 // elements) back to the latest element of the same value
+                const bool odd = mo != 0u;
                 const bool seen3 = l >= p3;
                 const bool dodd = d & 1;
                 const int32_t c2 = odd ? c21 : c20, b2 = odd ? b21 : b20;
                 // bitwise selects on the values: a ?: over the members
                 // becomes a load through a selected address, which keeps
                 // the whole state in scratch memory
-                const uint32_t mo = 0u - (uint32_t)odd, md = 0u - (uint32_t)dodd;
+                const uint32_t md = 0u - (uint32_t)dodd;
                 const int32_t m = bsel(mo, bsel(md, m3, m2), bsel(md, m1, m0));
                 const int32_t hl = bsel(mo, bsel(md, hl3, hl2), bsel(md, hl1, hl0));
                 const int32_t hh = bsel(mo, bsel(md, hh3, hh2), bsel(md, hh1, hh0));
