@@ -89,6 +89,12 @@ int spk_version(void);
  *                        (the default; the SPK_CHUNKS environment variable
  *                        overrides it at first use).  Values above the
  *                        number of 64-frame tiles are clamped.
+ *   SPK_OPT_WARM_TILES   64-frame tiles each speculative time chunk is
+ *                        warmed up on before its start; 0 = automatic
+ *                        (the default: four, at most half a chunk; the
+ *                        SPK_WARM environment variable overrides it at
+ *                        first use).  The fixup pass makes the result exact
+ *                        for any value.
  *   SPK_OPT_SUR_CONV_WG  at most this many workgroups per layer-by-layer
  *                        surrogate convolution, each walking a contiguous
  *                        range of 16 x 16 pixel blocks; 0 (default): as many
@@ -108,7 +114,8 @@ enum {
     SPK_OPT_SUR_CONV_WG = 3,
     SPK_OPT_PLAN_KGROUP = 4,
     SPK_OPT_PLAN_WAVES_PER_WG = 5,
-    SPK_OPT_PLAN_WPE = 6
+    SPK_OPT_PLAN_WPE = 6,
+    SPK_OPT_WARM_TILES = 7
 };
 int spk_set_option(int option, int value);
 int spk_get_option(int option);

@@ -23,7 +23,8 @@ TFI = 3
 TSR = 4
 
 __all__ = ["FSR", "SSR", "TFI", "TSR", "SpkError", "tfp", "decode", "motion", "frame_bytes", "reconstruct", "reconstruct_windows",
-           "segments", "segments_packed", "decode_packed", "version", "set_time_chunks", "get_time_chunks", "Plan",
+           "segments", "segments_packed", "decode_packed", "version", "set_time_chunks", "get_time_chunks",
+           "set_warm_tiles", "get_warm_tiles", "Plan",
            "PLAN_AUTOTUNE", "PLAN_NO_GRAPH"]
 
 PLAN_AUTOTUNE = 1
@@ -36,6 +37,7 @@ def frame_bytes(H: int, W: int) -> int:
 
 
 OPT_TIME_CHUNKS = 1
+OPT_WARM_TILES = 7
 
 
 def version() -> int:
@@ -50,6 +52,16 @@ def set_time_chunks(n: int) -> None:
 
 def get_time_chunks() -> int:
     return int(_lib.load().spk_get_option(OPT_TIME_CHUNKS))
+
+
+def set_warm_tiles(n: int) -> None:
+    """64-frame tiles each speculative time chunk warms up on (0 =
+    automatic).  Results are identical for every setting."""
+    _lib.check("spk_set_option", _lib.load().spk_set_option(OPT_WARM_TILES, int(n)))
+
+
+def get_warm_tiles() -> int:
+    return int(_lib.load().spk_get_option(OPT_WARM_TILES))
 
 
 OPT_PLAN_KGROUP, OPT_PLAN_WAVES_PER_WG, OPT_PLAN_WPE = 4, 5, 6

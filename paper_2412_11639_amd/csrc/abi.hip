@@ -209,15 +209,17 @@ int requested_chunks()
     return g_chunks;
 }
 
-// Warm-up tiles before each speculative chunk (tuning; SPK_WARM, default
-// automatic).
+// Warm-up tiles before each speculative chunk: -1 = automatic (SPK_WARM in
+// the environment, else min(4, half a chunk)); set by spk_set_option.
+int g_warm = -2;  // -2: not read yet
+
 int requested_warm()
 {
-    static const int v = [] {
+    if (g_warm == -2) {
         const char *e = std::getenv("SPK_WARM");
-        return e ? std::max(0, std::atoi(e)) : -1;
-    }();
-    return v;
+        g_warm = e ? std::max(0, std::atoi(e)) : -1;
+    }
+    return g_warm;
 }
 
 int check_common(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t order)
@@ -453,6 +455,10 @@ int spk_set_option(int option, int value)
         if (value < 0) return SPK_EINVAL;
         g_chunks = value;
         return SPK_OK;
+    case SPK_OPT_WARM_TILES:
+        if (value < 0) return SPK_EINVAL;
+        g_warm = value == 0 ? -1 : value;
+        return SPK_OK;
     case SPK_OPT_SUR_CONV_WG:
         if (value < 0) return SPK_EINVAL;
         spk::g_sur_conv_wg = value;
@@ -471,6 +477,7 @@ int spk_get_option(int option)
     std::lock_guard<std::mutex> lock(g_mu);
     switch (option) {
     case SPK_OPT_TIME_CHUNKS: return requested_chunks();
+    case SPK_OPT_WARM_TILES: return std::max(0, requested_warm());
     case SPK_OPT_SUR_CONV_WG: return spk::g_sur_conv_wg;
     case SPK_OPT_PLAN_KGROUP:
     case SPK_OPT_PLAN_WAVES_PER_WG:

@@ -113,7 +113,10 @@ void recon_kernel(ReconParams P, int nblocks, ChunkPlan cp)
 // record of where it closes).  For FSR a lane also stops when the true
 // window contains the speculative one and stays stable up to the main
 // pass's next cut (or to the chunk's end if there is none): the true machine
-// then cuts exactly there too.  The lane then takes the main pass's
+// then cuts exactly there too.  The window up to that next cut is known only
+// when the main pass recorded it (its first cut fell in the chunk's first
+// capture tiles); without it the rule needs the two windows equal (the
+// true machine then decides as the speculative one does).  The lane then takes the main pass's
 // end-of-chunk record (keeping its own open segment where that segment
 // outlives the chunk).  Stopping is exact because cut decisions depend only
 // on the state and the intervals that follow.
@@ -167,14 +170,16 @@ __global__ __launch_bounds__(64) void fixup_kernel(ReconParams P, int nblocks, C
         // The stopping rules, tried after the true and the speculative
         // machines have both taken the spike at tau (see above).
         auto stop_checks = [&](int32_t tau) {
-            if (ORDER == 1 && rc.fb1 >= tau && tr.st.flo <= sp.st.flo &&
-                sp.st.fhi <= tr.st.fhi &&
-                max(tr.st.fhi, rc.fwhi) - min(tr.st.flo, rc.fwlo) <= 1) {
-                // FSR: the true window holds the speculative one and stays
-                // stable with every interval up to the main pass's next
-                // cut, so the true machine makes that same cut next and
-                // both restart there: close the true segment at that cut
-                // and take the main pass's record from then on
+            if (ORDER == 1 && rc.fb1 >= tau &&
+                ((tr.st.flo == sp.st.flo && tr.st.fhi == sp.st.fhi) ||
+                 (rc.fwlo <= rc.fwhi && tr.st.flo <= sp.st.flo && sp.st.fhi <= tr.st.fhi &&
+                  max(tr.st.fhi, rc.fwhi) - min(tr.st.flo, rc.fwlo) <= 1))) {
+                // FSR: the true window equals the speculative one, or holds
+                // it and stays stable with every interval up to the main
+                // pass's next cut (the window the main pass recorded), so
+                // the true machine makes that same cut next and both
+                // restart there: close the true segment at that cut and
+                // take the main pass's record from then on
                 em.close(tr.first, rc.fb1, cum_start + rc.fi1 - tr.first_idx, tr.k0,
                          P.cnt_le[rc.fb1]);
                 tr = rc;

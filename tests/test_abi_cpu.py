@@ -211,6 +211,10 @@ def test_options(lib):
     assert lib.spk_set_option(3, -1) == -1
     assert lib.spk_set_option(3, 5) == 0 and lib.spk_get_option(3) == 5
     assert lib.spk_set_option(3, 0) == 0 and lib.spk_get_option(3) == 0
+    # warm-up tiles of speculative chunks: 0 = automatic
+    assert lib.spk_set_option(7, -1) == -1
+    assert lib.spk_set_option(7, 2) == 0 and lib.spk_get_option(7) == 2
+    assert lib.spk_set_option(7, 0) == 0 and lib.spk_get_option(7) == 0
     # batched plan shape: group size, waves per workgroup, register target
     for opt, good, bad in ((4, (4, 8, 16, 0), (3, 32, -1)), (5, (1, 2, 4, 0), (3, 8, -1)),
                            (6, (1, 0), (2, -1))):

@@ -32,6 +32,12 @@ def chunks(spk):
     spk.set_time_chunks(0)
 
 
+@pytest.fixture
+def warm(spk):
+    yield spk.set_warm_tiles
+    spk.set_warm_tiles(0)
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -287,6 +293,67 @@ def test_time_chunks_gratings(spk, chunks, order, n_chunks):
     s = spkgen.gratings(H, W, T, seed=8)
     t_out = list(range(0, T, 7)) + [T - 1]
     check_recon(spk, s, H, W, T, t_out, order)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("n_warm", [1, 2])
+@pytest.mark.parametrize("n_chunks", [3, 7])
+def test_time_chunks_short_warmup(spk, chunks, warm, order, n_chunks, n_warm):
+    """Chunks warmed up on one or two tiles start far from the true state;
+    the fixup still makes the result exact."""
+    chunks(n_chunks)
+    warm(n_warm)
+    H, W, T = 64, 128, 4096
+    s = spkgen.gratings(H, W, T, seed=8)
+    t_out = list(range(0, T, 9)) + [T - 1]
+    check_recon(spk, s, H, W, T, t_out, order)
+
+
+def _fsr_window_wider_than_warmup_stream(T=1024, W=64):
+    """Every pixel: intervals 9 and 10 in turn (one FSR segment, window
+    [9, 10]) up to frame 250, then only 10s, one 11 after frame 540, then
+    10 and 11 in turn up to frame 800, then 13s.  Cut into 2 chunks of 8
+    tiles, the second chunk's speculative state has seen only 10s in its 4
+    warm-up tiles (window [10, 10]); the 11 cuts the true segment but not
+    the speculative one, whose first cut (at the 13s) comes after the 4
+    tiles in which the main pass records its window."""
+    def train(off):
+        t, s, k = off, [off], 0
+        while t < 250:
+            t += 9 if k % 2 == 0 else 10
+            s.append(t)
+            k += 1
+        while t < 540:
+            t += 10
+            s.append(t)
+        t += 11
+        s.append(t)
+        k = 0
+        while t < 800:
+            t += 10 if k % 2 == 0 else 11
+            s.append(t)
+            k += 1
+        while t + 13 < T:
+            t += 13
+            s.append(t)
+        return s
+    bits = np.zeros((T, W), dtype=np.uint8)
+    for p in range(W):
+        bits[train(p % 5), p] = 1
+    return spkgen.pack(bits)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_time_chunks_first_cut_after_capture_tiles(spk, chunks, order):
+    """Default warm-up: the FSR fixup may not stop on the main pass's next
+    cut when it has no record of the window up to that cut (regression: it
+    stopped there and missed the true cut in between)."""
+    T, W = 1024, 64
+    s = _fsr_window_wider_than_warmup_stream(T, W)
+    segs = oracle.segments(s, 1, W, T, order=1, cap=8)
+    assert segs[0][1, 0] == 546 and segs[0][2, 0] == 809  # the true cuts
+    chunks(2)
+    check_recon(spk, s, 1, W, T, list(range(0, T, 4)) + [T - 1], order)
 
 
 @pytest.mark.parametrize("order", [1, 2])
