@@ -356,6 +356,47 @@ def test_time_chunks_first_cut_after_capture_tiles(spk, chunks, order):
     check_recon(spk, s, 1, W, T, list(range(0, T, 4)) + [T - 1], order)
 
 
+def _regime_stream(rng, T, W):
+    """Pixels whose intervals follow random regimes: a base interval a (1 to
+    40) held for a random stretch, drawn from {a}, {a, a + 1}, {a - 1, a,
+    a + 1} or a few far values.  Windows widen and narrow across chunk
+    boundaries, and some segments outlast several tiles."""
+    bits = np.zeros((T, W), dtype=np.uint8)
+    for p in range(W):
+        t = int(rng.integers(0, 40))
+        while t < T:
+            a = int(rng.integers(1, 41))
+            kind = int(rng.integers(0, 4))
+            end = t + int(rng.integers(40, 900))
+            while t < min(end, T):
+                bits[t, p] = 1
+                if kind == 0:
+                    d = a
+                elif kind == 1:
+                    d = a + int(rng.integers(0, 2))
+                elif kind == 2:
+                    d = max(1, a + int(rng.integers(-1, 2)))
+                else:
+                    d = int(rng.choice([a, a + 3, max(1, a - 2), 2 * a]))
+                t += d
+    return spkgen.pack(bits)
+
+
+@pytest.mark.parametrize("case", range(48))
+def test_time_chunks_random_regimes(spk, chunks, warm, case):
+    """Random interval regimes, chunk counts, warm-up lengths and orders
+    (TFI, FSR, SSR, third order) against the oracle."""
+    rng = np.random.default_rng(1000 + case)
+    T = int(rng.integers(700, 3500))
+    W = 64 * int(rng.integers(1, 3)) - int(rng.integers(0, 9))
+    order = [1, 2, 3, 4][case % 4]
+    s = _regime_stream(rng, T, W)
+    chunks(int(rng.integers(2, 13)))
+    warm(int(rng.integers(0, 6)))
+    t_out = sorted(set(int(x) for x in rng.integers(0, T, 300))) + [T - 1]
+    check_recon(spk, s, 1, W, T, t_out, order)
+
+
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("n_chunks", [4, 16])
 def test_time_chunks_static_and_moving_blocks(spk, chunks, order, n_chunks):
