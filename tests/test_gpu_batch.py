@@ -6,6 +6,7 @@ import torch
 
 import oracle
 import spkgen
+from regimes import regime_stream
 
 pytestmark = pytest.mark.gpu
 
@@ -157,4 +158,26 @@ def test_full_batched_workload(spk):
         got = out[planes].cpu().numpy()
         print("stream %dx%d seed %d" % (j["H"], j["W"], j["seed"]), flush=True)
         np.testing.assert_array_equal(got, ref.astype(np.float32))
+    plan.close()
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+def test_plan_random_regimes(spk, order):
+    """A plan over streams of random interval regimes (several strips each,
+    ragged widths) against the oracle."""
+    rng = np.random.default_rng(4000 + order)
+    jobs = []
+    for i in range(5):
+        H, W, T = int(rng.integers(1, 4)), int(rng.integers(20, 150)), int(rng.integers(300, 2500))
+        # H rows of W pixels, each pixel its own regime train
+        bits = np.concatenate([spkgen.unpack(regime_stream(rng, T, W), 1, W) for _ in range(H)],
+                              axis=1)
+        s = spkgen.pack(bits)
+        t_out = sorted(set(rng.integers(0, T, 50).tolist()))
+        jobs.append(dict(np_stream=s, stream=torch.from_numpy(s).cuda(), H=H, W=W, T=T,
+                         t_out=t_out, theta=1.0))
+    plan = spk.Plan(jobs, order=order)
+    plan.execute()
+    torch.cuda.synchronize()
+    check_against_oracle(jobs, plan.outputs(), order)
     plan.close()

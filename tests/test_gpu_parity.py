@@ -12,6 +12,7 @@ import torch
 
 import oracle
 import spkgen
+from regimes import regime_stream
 from test_oracle_pins import _read_golden, worked_example_stream
 
 pytestmark = pytest.mark.gpu
@@ -356,32 +357,6 @@ def test_time_chunks_first_cut_after_capture_tiles(spk, chunks, order):
     check_recon(spk, s, 1, W, T, list(range(0, T, 4)) + [T - 1], order)
 
 
-def _regime_stream(rng, T, W):
-    """Pixels whose intervals follow random regimes: a base interval a (1 to
-    40) held for a random stretch, drawn from {a}, {a, a + 1}, {a - 1, a,
-    a + 1} or a few far values.  Windows widen and narrow across chunk
-    boundaries, and some segments outlast several tiles."""
-    bits = np.zeros((T, W), dtype=np.uint8)
-    for p in range(W):
-        t = int(rng.integers(0, 40))
-        while t < T:
-            a = int(rng.integers(1, 41))
-            kind = int(rng.integers(0, 4))
-            end = t + int(rng.integers(40, 900))
-            while t < min(end, T):
-                bits[t, p] = 1
-                if kind == 0:
-                    d = a
-                elif kind == 1:
-                    d = a + int(rng.integers(0, 2))
-                elif kind == 2:
-                    d = max(1, a + int(rng.integers(-1, 2)))
-                else:
-                    d = int(rng.choice([a, a + 3, max(1, a - 2), 2 * a]))
-                t += d
-    return spkgen.pack(bits)
-
-
 @pytest.mark.parametrize("case", range(48))
 def test_time_chunks_random_regimes(spk, chunks, warm, case):
     """Random interval regimes, chunk counts, warm-up lengths and orders
@@ -390,11 +365,29 @@ def test_time_chunks_random_regimes(spk, chunks, warm, case):
     T = int(rng.integers(700, 3500))
     W = 64 * int(rng.integers(1, 3)) - int(rng.integers(0, 9))
     order = [1, 2, 3, 4][case % 4]
-    s = _regime_stream(rng, T, W)
+    s = regime_stream(rng, T, W)
     chunks(int(rng.integers(2, 13)))
     warm(int(rng.integers(0, 6)))
     t_out = sorted(set(int(x) for x in rng.integers(0, T, 300))) + [T - 1]
     check_recon(spk, s, 1, W, T, t_out, order)
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_segments_and_decode_random_regimes(spk, case):
+    """Segment lists (both layouts) and their decode on random interval
+    regimes, against the oracle."""
+    rng = np.random.default_rng(2000 + case)
+    T = int(rng.integers(300, 2500))
+    W = int(rng.integers(30, 130))
+    order = [1, 2, 4][case % 3]
+    s = regime_stream(rng, T, W)
+    cap = T
+    check_segments(spk, s, 1, W, T, order, cap)
+    sf, sl, sn, cnt = spk.segments(dev(s), 1, W, T, order=order, cap=cap)
+    t_out = sorted(set(int(x) for x in rng.integers(0, T, 200))) + [T - 1]
+    got = decode_both(spk, sf, sl, sn, cnt, 1, W, T, t_out).cpu().numpy()
+    ref = oracle.reconstruct(s, 1, W, T, 1.0, t_out, order=order)
+    np.testing.assert_array_equal(got, ref.astype(np.float32))
 
 
 @pytest.mark.parametrize("order", [1, 2])

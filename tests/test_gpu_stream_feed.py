@@ -10,6 +10,7 @@ import torch
 
 import oracle
 import spkgen
+from regimes import regime_stream
 
 pytestmark = pytest.mark.gpu
 
@@ -111,3 +112,31 @@ def test_silent_pixels_nothing_fed_and_late_outputs(spk):
     for g, r in zip(got, ref):
         assert torch.equal(g, r)
     st.close()
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_regimes_in_pieces(spk, case):
+    """Random interval regimes (segments that outlast many pieces, windows
+    that widen and narrow) fed in random pieces, every order, against the
+    oracle."""
+    rng = np.random.default_rng(3000 + case)
+    T = int(rng.integers(500, 3000))
+    W = int(rng.integers(20, 140))
+    order = [spk.FSR, spk.SSR, spk.TFI, spk.TSR][case % 4]
+    s = regime_stream(rng, T, W)
+    ds = torch.from_numpy(s).cuda()
+    t_out = [int(t) for t in rng.integers(0, T, 120)] + [0, T - 1]
+    cuts = _pieces(rng, T, ["short", "long", "one", "short", "empty", "long"])
+    print("regimes case %d: T=%d W=%d order=%d, %d pieces" % (case, T, W, order, len(cuts) - 1),
+          flush=True)
+    st = spk.Stream(1, W, 1.0, t_out, order=order, windows=True)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        st.feed(ds[a:b])
+    out, wf, wl, wn = st.finish()
+    torch.cuda.synchronize()
+    o_out, o_wf, o_wl, o_wn = oracle.reconstruct(s, 1, W, T, 1.0, t_out, order=order,
+                                                 windows=True)
+    np.testing.assert_array_equal(out.cpu().numpy(), o_out.astype(np.float32))
+    np.testing.assert_array_equal(wf.cpu().numpy(), o_wf)
+    np.testing.assert_array_equal(wl.cpu().numpy(), o_wl)
+    np.testing.assert_array_equal(wn.cpu().numpy(), o_wn)
