@@ -268,33 +268,38 @@ struct SegState {
     {
         const int32_t a = flo;
         const uint64_t f = w & (~w + 1);             // the word's first spike
-        // spikes whose interval is B: predecessor a + 1 frames back (and not a)
-        uint64_t MB = w & (w << (a + 1)) & ~(w << a) & ~f;
+        const uint64_t top = 1ull << hibit64(w);     // and its last
+        // spikes whose interval is B: every gap inside w is a or a + 1, so
+        // those whose predecessor is not a frames back
+        uint64_t MB = w & ~(w << a) & ~f;
         if (x0 == a + 1) MB |= f;
         const uint64_t MA = w & ~MB;
         const bool oddA = a & 1;
         const int32_t lA = oddA ? l1 : l0, lB = oddA ? l0 : l1;
         const bool seenA = lA >= ps, seenB = lB >= ps;
         // two B (or two A) in a row, inside the word or across its start
-        const bool BB = (MB & (MB << (a + 1))) != 0 || (seenB && lB == ii - 1 && x0 == a + 1);
-        const bool AA = (MA & (MA << a)) != 0 || (seenA && lA == ii - 1 && x0 == a);
-        if (BB && AA) return false;
+        // (bitwise operators: lane masks, not values)
+        const bool BB = ((MB & (MB << (a + 1))) != 0) | (seenB & (lB == ii - 1) & (x0 == a + 1));
+        const bool AA = ((MA & (MA << a)) != 0) | (seenA & (lA == ii - 1) & (x0 == a));
+        if (BB & AA) return false;
         const bool isoB = !BB;  // the walked (isolated) value is B, else A
         const uint64_t MM = isoB ? MB : MA, MJ = isoB ? MA : MB;
         const int32_t xM = isoB ? a + 1 : a, xJ = isoB ? a : a + 1;
         const int32_t lM = isoB ? lB : lA, lJ = isoB ? lA : lB;
         const bool seenM = isoB ? seenB : seenA, seenJ = isoB ? seenA : seenB;
-        const bool oddM = isoB ? !oddA : oddA;
+        const bool oddM = isoB ^ oddA;
         int32_t gMl = oddM ? g1l : g0l, gMh = oddM ? g1h : g0h;
         int32_t gJl = oddM ? g0l : g1l, gJh = oddM ? g0h : g1h;
         if (!seenM) { gMl = kBig; gMh = -kBig; }
         if (!seenJ) { gJl = kBig; gJh = -kBig; }
         int32_t nlM = lM, nlJ = lJ;
         // the other value: gaps 1 (twice in a row) and 2 (around one isolated
-        // occurrence) inside the word, and the gap back to its last occurrence
+        // occurrence) inside the word, and the gap back to its last
+        // occurrence.  The isolated value never occurs twice in a row, so at
+        // most one of its occurrences precedes the other's first one or
+        // follows its last: their interval numbers need no popcount.
         if (MJ) {
-            const uint64_t fJ = MJ & (~MJ + 1);
-            const int32_t first = ii + popc64(w & (fJ - 1));
+            const int32_t first = ii + ((f & MM) != 0);
             if (seenJ) {
                 gJl = min(gJl, first - lJ);
                 gJh = max(gJh, first - lJ);
@@ -307,7 +312,7 @@ struct SegState {
                 gJl = min(gJl, 2);
                 gJh = max(gJh, 2);
             }
-            nlJ = ii + popc64(w & ((1ull << hibit64(MJ)) - 1));
+            nlJ = ii + c - 1 - ((top & MM) != 0);
         }
         if (gJh - gJl > 1) return false;
         // the isolated value: a gap of k intervals between two of its
@@ -354,15 +359,13 @@ struct SegState {
         }
         if (gMh - gMl > 1) return false;
         fhi = max(fhi, MB ? a + 1 : a);
-        const int32_t nlA = isoB ? nlJ : nlM, nlB = isoB ? nlM : nlJ;
-        const int32_t nAl = isoB ? gJl : gMl, nAh = isoB ? gJh : gMh;
-        const int32_t nBl = isoB ? gMl : gJl, nBh = isoB ? gMh : gJh;
-        l0 = oddA ? nlB : nlA;
-        l1 = oddA ? nlA : nlB;
-        g0l = oddA ? nBl : nAl;
-        g0h = oddA ? nBh : nAh;
-        g1l = oddA ? nAl : nBl;
-        g1h = oddA ? nAh : nBh;
+        // the isolated value's state goes to its parity's slot
+        l0 = oddM ? nlJ : nlM;
+        l1 = oddM ? nlM : nlJ;
+        g0l = oddM ? gJl : gMl;
+        g0h = oddM ? gJh : gMh;
+        g1l = oddM ? gMl : gJl;
+        g1h = oddM ? gMh : gJh;
         ii += c;
         return true;
     }
