@@ -133,13 +133,23 @@ __device__ __forceinline__ int xcd_strip(int b, int nblocks)
 // at least the true one, so the chosen gaps sum to that distance exactly
 // when every true gap is a or a + 1; the n1 = popc(w & (w >> a)) gaps of a
 // and c - 1 - n1 of a + 1 sum to (c - 1)(a + 1) - n1.
+// a * b for 0 <= a, b < 2^24 (here both below 64): one full-rate 24-bit
+// multiply.  Written out, because the compiler emits the quarter-rate 32-bit
+// multiply when it cannot prove the operands small.
+__device__ __forceinline__ int32_t mul_small(int32_t a, int32_t b)
+{
+    int32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 __device__ __forceinline__ bool gaps_within(uint64_t w, int a, bool plus1, int32_t c)
 {
     const int hi = 63 - __builtin_clzll(w), lo = __builtin_ctzll(w);
     const uint64_t rest = w & ~(1ull << hi);
     const uint64_t s1 = w >> a, s2 = plus1 ? (s1 >> 1) : 0ull;
     const int32_t n1 = __builtin_popcountll(w & s1);
-    const int32_t sum = plus1 ? (c - 1) * (a + 1) - n1 : (c - 1) * a;
+    const int32_t sum = plus1 ? mul_small(c - 1, a + 1) - n1 : mul_small(c - 1, a);
     return !(rest & ~(s1 | s2)) && sum == hi - lo;
 }
 
@@ -340,12 +350,12 @@ struct SegState {
                 // 1/(n - 1) >= 1/31, far above the reciprocal's error
                 const int32_t g = (int32_t)fmaf((float)K, __builtin_amdgcn_rcpf((float)(n - 1)),
                                                 1e-3f);
-                const int32_t D1 = g * xJ + (xM - xJ), D2 = D1 + xJ;
+                const int32_t D1 = mul_small(g, xJ) + (xM - xJ), D2 = D1 + xJ;
                 const uint64_t s1 = D1 < 64 ? MM >> D1 : 0ull, s2 = D2 < 64 ? MM >> D2 : 0ull;
                 const uint64_t rest = MM & ~(1ull << hM);
                 if (rest & ~(s1 | s2)) return false;
                 const int32_t n1 = popc64(rest & s1), n2 = n - 1 - n1;
-                if (n1 * g + n2 * (g + 1) != K) return false;
+                if (mul_small(n1, g) + mul_small(n2, g + 1) != K) return false;
                 if (n1) {
                     gMl = min(gMl, g);
                     gMh = max(gMh, g);
@@ -952,17 +962,24 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
 {
     uint32_t rlo[KG], rhi[KG];
     int32_t rc[KG];
+    // row r = 64 t + lane of tile t: the tile's first row is the same for
+    // the whole wave and the lane's byte offset lane * fb is fixed, so each
+    // load is a wave-uniform base plus that offset (a 64-bit add, no per-lane
+    // multiply)
+    const int64_t lane_off = (int64_t)lane * P.fb;
     auto fetch = [&](int32_t tg) {
 #pragma unroll
         for (int i = 0; i < KG; i++) {
-            const int32_t tr = (tg + i) * 64 + lane;
+            const int32_t t = tg + i;
+            const int32_t tr = t * 64 + lane;
             rlo[i] = rhi[i] = 0;
             rc[i] = 0;
-            if (tg + i < tile1 && tr < P.T) {
-                const uint64_t v = *gp((const uint64_t *)(base + (int64_t)tr * P.fb));
+            if (t < tile1 && tr < P.T) {
+                const uint8_t *row0 = base + (int64_t)t * 64 * P.fb;
+                const uint64_t v = *gp((const uint64_t *)(row0 + lane_off));
                 rlo[i] = (uint32_t)v;
                 rhi[i] = (uint32_t)(v >> 32);
-                if (P.cnt_le) rc[i] = gp(P.cnt_le)[tr];
+                if (P.cnt_le) rc[i] = (gp(P.cnt_le) + t * 64)[lane];
             }
         }
     };
