@@ -96,10 +96,8 @@ __device__ float pack_value(const float *P, int kind, int s, int nb, int j, int 
     return 0.0f;
 }
 
-__global__ void pack_kernel(const float *params, __bf16 *packed)
+__device__ __forceinline__ void pack_one(const float *params, __bf16 *packed, int idx)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= PACK_TOTAL) return;
     int kind = 0;
     while (kind + 1 < PK_COUNT && idx >= pack_offset(kind + 1)) kind++;
     int r = idx - pack_offset(kind);
@@ -111,6 +109,12 @@ __global__ void pack_kernel(const float *params, __bf16 *packed)
     const int s = r / pack_nb(kind);
     const int j = lane % 16, k = (lane / 16) * 8 + e;
     packed[idx] = to_bf16(pack_value(params, kind, s, nb, j, k));
+}
+
+__global__ void pack_kernel(const float *params, __bf16 *packed)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < PACK_TOTAL) pack_one(params, packed, idx);
 }
 
 // ---------------------------------------------------------------------------
@@ -226,13 +230,18 @@ __global__ __launch_bounds__(64) void input_kernel(SampleTab tab, int Hc, int Wc
 }
 
 // As input_kernel with the crops of training step *kstep taken from a
-// device table of B records per step.
+// device table of B records per step.  The grid also packs the weights
+// (as pack_kernel), which saves the training step a launch.
 __global__ __launch_bounds__(64) void input_step_kernel(const spk_sur_sample *samples,
                                                         const int32_t *kstep, int B, int Hc,
                                                         int Wc, int xtiles, double theta,
                                                         uint32_t *win, float *est,
-                                                        uint8_t *stable, float *target)
+                                                        uint8_t *stable, float *target,
+                                                        const float *params, __bf16 *packed)
 {
+    const int64_t nthr = (int64_t)gridDim.x * 64;
+    for (int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x; idx < PACK_TOTAL; idx += nthr)
+        pack_one(params, packed, (int)idx);
     const int b = blockIdx.x / (Hc * xtiles);
     const spk_sur_sample S = samples[(int64_t)*kstep * B + b];
     input_tile(S, b, Hc, Wc, xtiles, theta, win, est, stable, target);
@@ -1158,11 +1167,38 @@ struct RedSeg {
     const float *partial;
     float *dst;
     int np, blk0;
+    int poff;  // parameter index of dst[0]
+};
+// Training plans: the reduction also takes Adam's step on every weight it
+// finishes (learning rate and bias corrections from per-step tables).
+// Each workgroup counts the steps in a counter of its own (kblk[workgroup],
+// read and advanced by that workgroup alone), and workgroup 0 also advances
+// *kstep, the count the step's earlier kernels read: they have finished by
+// then, and no workgroup of the reduction reads it.  Every counter starts
+// at zero.
+struct RedAdam {
+    float *p, *m, *v;
+    const float *lr, *c1, *c2;
+    int32_t *kstep, *kblk;
+    float b1, b2, eps;
 };
 struct RedArgs {
     RedSeg seg[4];
     int nseg, nblocks;
+    RedAdam adam;  // adam.p == NULL: reduction only
 };
+
+// Adam update of parameter j with gradient gj (c1, c2: the bias
+// corrections 1 - beta^t).
+__device__ __forceinline__ void adam_value(int j, float *p, float *m, float *v, float gj, float lr,
+                                           float b1, float b2, float eps, float c1, float c2)
+{
+    const float mj = b1 * m[j] + (1.0f - b1) * gj;
+    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    p[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
 
 // dst[j] = sum over blocks of partial[blk][j] in a fixed order: 4 threads
 // per weight each add every 4th block (in block order), then the 4 sums
@@ -1170,6 +1206,10 @@ struct RedArgs {
 // weights of one segment, so each wave reads 256 contiguous bytes per
 // block.
 constexpr int kRedCols = 64, kRedParts = 256 / kRedCols;
+// workgroups of the reduction over all four layers
+constexpr int kRedBlocks = (WgShape<WG_FIRST>::np + kRedCols - 1) / kRedCols +
+                           2 * ((WgShape<WG_MID>::np + kRedCols - 1) / kRedCols) +
+                           (WgShape<WG_LAST>::np + kRedCols - 1) / kRedCols;
 __global__ __launch_bounds__(256) void reduce_kernel(RedArgs R)
 {
     __shared__ float red[kRedParts][kRedCols + 1];
@@ -1194,7 +1234,22 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs R)
         if (part < s) red[part][jl] += red[part + s][jl];
         __syncthreads();
     }
-    if (part == 0 && j < np) dst[j] = red[0][jl];
+    const RedAdam &D = R.adam;
+    const int k = D.p ? D.kblk[blockIdx.x] : 0;
+    if (part == 0 && j < np) {
+        const float gj = red[0][jl];
+        dst[j] = gj;
+        if (D.p)
+            adam_value(S.poff + j, D.p, D.m, D.v, gj, D.lr[k], D.b1, D.b2, D.eps, D.c1[k],
+                       D.c2[k]);
+    }
+    if (D.p) {
+        __syncthreads();  // every use of k is behind
+        if (threadIdx.x == 0) {
+            D.kblk[blockIdx.x] = k + 1;
+            if (blockIdx.x == 0) *D.kstep = k + 1;
+        }
+    }
 }
 
 // The weight-gradient kernels produce dW[co][tap][ci] and db[co] per layer,
@@ -1202,17 +1257,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs R)
 
 // ---------------------------------------------------------------------------
 
-// Adam update of parameter j (c1, c2: the bias corrections 1 - beta^t).
+// Adam update of parameter j from g[j].
 __device__ __forceinline__ void adam_update(int j, float *p, float *m, float *v, const float *g,
                                             float lr, float b1, float b2, float eps, float c1,
                                             float c2)
 {
-    const float gj = g[j];
-    const float mj = b1 * m[j] + (1.0f - b1) * gj;
-    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
-    m[j] = mj;
-    v[j] = vj;
-    p[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    adam_value(j, p, m, v, g[j], lr, b1, b2, eps, c1, c2);
 }
 
 __global__ void adam_kernel(float *p, float *m, float *v, const float *g, int n, float lr,
@@ -1220,23 +1270,6 @@ __global__ void adam_kernel(float *p, float *m, float *v, const float *g, int n,
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n) adam_update(j, p, m, v, g, lr, b1, b2, eps, c1, c2);
-}
-
-// Adam for training step k = *kstep: learning rate and bias corrections
-// from per-step tables (the host computes them exactly as spk_sur_adam).
-__global__ void adam_step_kernel(float *p, float *m, float *v, const float *g, int n,
-                                 const float *lr, const float *c1, const float *c2,
-                                 const int32_t *kstep, float b1, float b2, float eps)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int k = *kstep;
-    adam_update(j, p, m, v, g, lr[k], b1, b2, eps, c1[k], c2[k]);
-}
-
-__global__ void advance_kernel(int32_t *kstep)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *kstep += 1;
 }
 
 __global__ void mux_kernel(const float *y, const float *est, const uint8_t *stable, int64_t n,
@@ -1356,8 +1389,9 @@ void warm_launch_caches()
 // Weight-gradient partials of layer kind K into a.partial (one row per
 // workgroup); the reduction into dst is queued as a segment of R.
 template <int K>
-void launch_wgrad(WgArgs a, float *dst, RedArgs &R, hipStream_t st)
+void launch_wgrad(WgArgs a, float *grad, int poff, RedArgs &R, hipStream_t st)
 {
+    float *dst = grad + poff;
     a.ntiles = a.B * a.tx * a.ty;
     const int nblk = a.ntiles < kWgMaxBlocks ? a.ntiles : kWgMaxBlocks;
     if constexpr (K == WG_LAST)
@@ -1371,6 +1405,7 @@ void launch_wgrad(WgArgs a, float *dst, RedArgs &R, hipStream_t st)
     S.partial = a.partial;
     S.dst = dst;
     S.np = np;
+    S.poff = poff;
     S.blk0 = R.nseg > 1 ? R.seg[R.nseg - 2].blk0 + (R.seg[R.nseg - 2].np + kRedCols - 1) / kRedCols
                         : 0;
     R.nblocks = nblk;
@@ -1426,10 +1461,12 @@ void forward_train(const float *params, const uint32_t *win, const float *est, i
 
 // MSE gradient: loss (dL/dy and the loss partial sums, into a per-step row
 // of loss_partial when kstep is given), then per layer from the top the
-// weight gradient and the input gradient through the ReLU mask.
+// weight gradient and the input gradient through the ReLU mask.  With adam
+// (training plans) the reduction also takes the Adam step.
 void backward_all(const float *params, const uint32_t *win, const float *est, int B, int Hc,
                   int Wc, const float *y, const float *target, float *grad, float *loss_partial,
-                  const int32_t *kstep, const Workspace &w, hipStream_t st)
+                  const int32_t *kstep, const Workspace &w, hipStream_t st,
+                  const RedAdam *adam = nullptr)
 {
     const int64_t P = (int64_t)B * Hc * Wc;
     const int lblocks = (int)((P + 255) / 256);
@@ -1453,7 +1490,7 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     part += rows * WgShape<WG_LAST>::np;
     g.gy = w.dy;
     g.a = w.a3;
-    launch_wgrad<WG_LAST>(g, grad + OFF_W4, R, st);
+    launch_wgrad<WG_LAST>(g, grad, OFF_W4, R, st);
     a.scalar = w.dy;
     a.packed = w.packed + pack_offset(PK_DG4);
     a.mask = w.a3;
@@ -1464,7 +1501,7 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     g.a = w.a2;
     g.partial = part;
     part += rows * WgShape<WG_MID>::np;
-    launch_wgrad<WG_MID>(g, grad + OFF_W3, R, st);
+    launch_wgrad<WG_MID>(g, grad, OFF_W3, R, st);
     a.act = w.g1;
     a.packed = w.packed + pack_offset(PK_DG3);
     a.mask = w.a2;
@@ -1475,7 +1512,7 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     g.a = w.a1;
     g.partial = part;
     part += rows * WgShape<WG_MID>::np;
-    launch_wgrad<WG_MID>(g, grad + OFF_W2, R, st);
+    launch_wgrad<WG_MID>(g, grad, OFF_W2, R, st);
     a.act = w.g2;
     a.packed = w.packed + pack_offset(PK_DG2);
     a.mask = w.a1;
@@ -1486,7 +1523,8 @@ void backward_all(const float *params, const uint32_t *win, const float *est, in
     g.win = win;
     g.est = est;
     g.partial = part;
-    launch_wgrad<WG_FIRST>(g, grad + OFF_W1, R, st);
+    launch_wgrad<WG_FIRST>(g, grad, OFF_W1, R, st);
+    if (adam) R.adam = *adam;
     launch_reduce(R, st);
 }
 
@@ -1693,7 +1731,8 @@ int spk_sur_train_create(spk_sur_train_t *plan, float *params, float *m, float *
                   o_y = o_target + align256(P * 4), o_grad = o_y + align256(P * 4),
                   o_samples = o_grad + align256((int64_t)NPARAMS * 4),
                   o_tab = o_samples + align256((int64_t)steps * B * sizeof(spk_sur_sample)),
-                  o_k = o_tab + align256((int64_t)steps * 3 * 4), total = o_k + 256;
+                  o_k = o_tab + align256((int64_t)steps * 3 * 4),
+                  total = o_k + align256(4 * (1 + kRedBlocks));
     auto *pl = new spk_sur_train_s;
     pl->dev = dev;
     pl->steps = steps;
@@ -1711,12 +1750,12 @@ int spk_sur_train_create(spk_sur_train_t *plan, float *params, float *m, float *
     float *grad = (float *)(c + o_grad), *dtab = (float *)(c + o_tab);
     uint8_t *stable = (uint8_t *)(c + o_stable);
     spk_sur_sample *dsamples = (spk_sur_sample *)(c + o_samples);
-    int32_t *kstep = (int32_t *)(c + o_k);
-    const int32_t zero = 0;
+    int32_t *kstep = (int32_t *)(c + o_k);  // then the reduction's own counters
+    const std::vector<int32_t> zero(1 + kRedBlocks, 0);
     if (hipMemcpy(dsamples, samples, (size_t)steps * B * sizeof(spk_sur_sample),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(kstep, &zero, 4, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(kstep, zero.data(), zero.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
         train_free(pl);
         return SPK_EHIP;
     }
@@ -1731,14 +1770,16 @@ int spk_sur_train_create(spk_sur_train_t *plan, float *params, float *m, float *
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
         const int xtiles = (Wc + 63) / 64;
+        // the input kernel also packs the weights; the reduction takes the
+        // Adam step and advances kstep
         hipLaunchKernelGGL(input_step_kernel, dim3(B * Hc * xtiles), dim3(64), 0, cs, dsamples,
-                           kstep, B, Hc, Wc, xtiles, (double)theta, win, est, stable, target);
-        forward_train(params, win, est, B, Hc, Wc, y, w, cs);
-        backward_all(params, win, est, B, Hc, Wc, y, target, grad, loss_partial, kstep, w, cs);
-        hipLaunchKernelGGL(adam_step_kernel, dim3((NPARAMS + 255) / 256), dim3(256), 0, cs,
-                           params, m, v, grad, NPARAMS, dtab, dtab + steps, dtab + 2 * steps,
-                           kstep, beta1, beta2, eps);
-        hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, cs, kstep);
+                           kstep, B, Hc, Wc, xtiles, (double)theta, win, est, stable, target,
+                           params, w.packed);
+        forward_all(params, win, est, B, Hc, Wc, y, w, cs, false);
+        const RedAdam ad{params, m,         v,     dtab,  dtab + steps, dtab + 2 * steps,
+                         kstep,  kstep + 1, beta1, beta2, eps};
+        backward_all(params, win, est, B, Hc, Wc, y, target, grad, loss_partial, kstep, w, cs,
+                     &ad);
         ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess && pl->graph;
     }
     ok = ok && hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
