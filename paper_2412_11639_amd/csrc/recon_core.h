@@ -498,6 +498,7 @@ enum PlaneMap { PMAP_IDENT = 0, PMAP_LDS = 1, PMAP_GLOBAL = 2 };
 // Writes of one pixel's closed segments.
 template <int MODE, bool WIN, int PMAP>
 struct Emitter {
+    static constexpr int kMode = MODE;
     const ReconParams &P;
     const int32_t *plane_s;  // LDS copy of the plane map (PMAP_LDS)
     int64_t p;
@@ -753,12 +754,114 @@ struct Run {
         cnt_last = cnt_row[hp];
     }
 
+    // TFI (every interval but a pixel's first opens a segment) over the
+    // nonzero word w, for plain outputs.  The spike walk would close a
+    // segment at nearly every spike, and most of them cover no output.  Here
+    // only the segments that cover an output are emitted, with the same
+    // arguments as the walk gives them: at most two at the word's start,
+    // whose outputs may lie in earlier words, then one per distinct next
+    // spike of the output frames in omask (bit j: an output at frame t0 + j,
+    // j >= 1).  The run's state then advances past the word as the walk
+    // leaves it.  A segment the walk closes and this skips has k0 == kend,
+    // so it writes nothing.
+    template <class EM>
+    __device__ __forceinline__ void word_tfi(int32_t t0, uint64_t w, const int32_t *cnt_row,
+                                             uint64_t omask, EM &em)
+    {
+        const int32_t c = popc64(w);
+        const int p1 = ctz64(w), hp = hibit64(w);
+        // second and second-to-last spikes when c >= 2 (the extra bit only
+        // keeps the count defined for c = 1)
+        const int p2 = ctz64((w & (w - 1)) | (1ull << 63));
+        const int pl = hibit64((w & ~(1ull << hp)) | 1ull);
+        const bool had = lastspk >= 0;
+        const int32_t cum0 = cum, lastspk0 = lastspk, cnt_last0 = cnt_last;
+        // the word's spikes are numbered 1..c, spike 0 being lastspk; the
+        // first one that closes a segment: spike 1, unless the interval it
+        // ends is the pixel's first (or it is the pixel's first spike)
+        const int i_min = (had ? 1 : 2) + (st.flo == kBig ? 1 : 0);
+        if (!had) {
+            first = t0 + p1;
+            first_idx = 0;
+        }
+        if (i_min <= c) {
+            // the first close: its last spike is spike i_min - 1, and it
+            // takes every output from k0 on
+            int32_t L, kend;
+            if (i_min == 1) {
+                L = lastspk0;
+                kend = cnt_last0;
+            } else {
+                const int q = i_min == 2 ? p1 : p2;
+                L = t0 + q;
+                kend = cnt_row[q];
+            }
+            const int32_t lidx = cum0 + i_min - 2;
+            em.close(first, L, lidx - first_idx, k0, kend);
+            // the second, when it ends at spike 1 after lastspk: its outputs
+            // may lie before the word
+            if (i_min == 1 && c >= 2)
+                em.close(lastspk0, t0 + p1, 1, cnt_last0, cnt_row[p1]);
+        }
+        // later closes end at spikes past lo (spike 1, or 2 when the first
+        // close ended there) and before the word's last spike; their outputs
+        // lie inside the word
+        const int lo = i_min == 3 ? p2 : p1;
+        int nx_done = -1;
+        uint64_t om = omask;
+        while (om) {
+            const int o = ctz64(om);
+            om &= om - 1;
+            // the first spike at or after frame t0 + o (63 when there is none,
+            // which the test against hp rejects)
+            const int nx = ctz64((w & (~0ull << o)) | (1ull << 63));
+            if (nx > lo && nx < hp && nx != nx_done) {
+                nx_done = nx;
+                const int pv = hibit64(w & ((1ull << nx) - 1));
+                em.close(t0 + pv, t0 + nx, 1, cnt_row[pv], cnt_row[nx]);
+            }
+        }
+        // the state the walk leaves
+        if (i_min <= c) {
+            // the last close ends at spike c - 1
+            if (c == 1) {
+                first = lastspk0;
+                first_idx = cum0 - 1;
+                k0 = cnt_last0;
+            } else {
+                first = t0 + pl;
+                first_idx = cum0 + c - 2;
+                k0 = cnt_row[pl];
+            }
+            lastb = first;
+        }
+        if (c >= 2 || had) {
+            const int32_t x = c >= 2 ? hp - pl : t0 + p1 - lastspk0;  // the last interval
+            st.flo = x;
+            st.fhi = x;
+        }
+        cum = cum0 + c;
+        lastspk = t0 + hp;
+        cnt_last = cnt_row[hp];
+    }
+
     // Process the 64-frame word w starting at frame t0; cnt_row[j] is the
-    // number of sorted outputs at or before frame t0 + j.
+    // number of sorted outputs at or before frame t0 + j (omask: the output
+    // frames of the word, for TFI with plain outputs).
     // FB1: keep fb1/fn1/fi1 (chunked runs only).
     template <int ORDER, bool CAPTURE, bool FB1, class EM>
-    __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em)
+    __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em,
+                                         uint64_t omask = 0)
     {
+        if constexpr (ORDER == 3 && EM::kMode == MODE_RECON) {
+            // a chunked run keeps its first close at or after the chunk's
+            // start for the fixup pass: the walk below does that bookkeeping
+            // in the words that may hold it
+            if (!(FB1 && fb1 < 0 && t0 + 63 >= cs)) {
+                word_tfi(t0, w, cnt_row, omask, em);
+                return;
+            }
+        }
         if (try_fast<ORDER>(t0, w, cnt_row)) return;  // no segment ends in this word
         const WordStart ws = begin(t0, w);
         const uint64_t B0 = spikes<ORDER, CAPTURE>(t0, ws.rest, ws.lp);
@@ -998,6 +1101,11 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
         for (int i = 0; i < ni; i++) {
             const int32_t t = tg + i;
             const uint64_t w = word_s[i][lane];
+            // TFI with plain outputs: the frames of this tile that hold an
+            // output (the same for every pixel)
+            uint64_t omask = 0;
+            if constexpr (ORDER == 3 && EM::kMode == MODE_RECON)
+                omask = __ballot(lane > 0 && cnt_s[i][lane] > cnt_s[i][lane > 0 ? lane - 1 : 0]);
             if constexpr (CHUNKED) {
                 if (t == tile0 && rec_start) {
                     // the speculative state the fixup pass starts from
@@ -1010,7 +1118,7 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
                     continue;
                 }
             }
-            if (w) run.template word<ORDER, false, CHUNKED>(f0 + t * 64, w, cnt_s[i], em);
+            if (w) run.template word<ORDER, false, CHUNKED>(f0 + t * 64, w, cnt_s[i], em, omask);
         }
         tile_sync<WAVE_SYNC>();
     }

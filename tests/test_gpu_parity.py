@@ -231,12 +231,14 @@ def test_edge_cases(spk):
     bits[[0, 63, 64], 4] = 1
     bits[[63, 64], 5] = 1
     s = spkgen.pack(bits)
-    for order in (1, 2):
+    for order in (1, 2, 3):
         check_recon(spk, s, 1, 6, T, list(range(T)), order)
         check_segments(spk, s, 1, 6, T, order, cap=T)
+    # TFI with outputs on, between and before spikes, and words of one spike
+    check_recon(spk, s, 1, 6, T, [0, 2, 3, 40, 41, 62, 63, 63, 64], 3)
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_unsorted_duplicate_t_out_short_stream_and_no_outputs(spk, order):
     """t_out in any order with duplicates (plane k is always for t_out[k]),
     a stream shorter than one 64-frame tile, and n_out = 0."""
@@ -444,7 +446,7 @@ def test_time_chunks_sparse_and_edge_pixels(spk, chunks, n_chunks):
             bits[m, p] = 1
     s = spkgen.pack(bits)
     t_out = rng.integers(0, T, 400).tolist() + [0, T - 1, T - 1]
-    for order in (1, 2):
+    for order in (1, 2, 3):
         check_recon(spk, s, 1, 200, T, t_out, order)
 
 
