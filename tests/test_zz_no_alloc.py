@@ -32,7 +32,7 @@ def _noalloc(spk, ds, H, W, T, t_out, order, out):
     assert rc == 0, rc
 
 
-@pytest.mark.parametrize("order_name", ["FSR", "SSR", "TSR"])
+@pytest.mark.parametrize("order_name", ["FSR", "SSR", "TFI", "TSR"])
 def test_noalloc_equals_reconstruct_twice(spk, order_name):
     order = getattr(spk, order_name)
     rng = np.random.default_rng(21)
