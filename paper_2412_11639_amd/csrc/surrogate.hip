@@ -611,14 +611,19 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *
         sq = d * d;
         dy[idx] = (float)to_bf16(2.0f * d / (float)n);
     }
+    // tree sum, element t taking t + s for s = 128, 64, ..., 1; the last
+    // six halvings within one wave by shuffles (the same additions)
     red[threadIdx.x] = sq;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+    if (threadIdx.x < 128) red[threadIdx.x] += red[threadIdx.x + 128];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        float v = red[threadIdx.x] + red[threadIdx.x + 64];
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
+        if (threadIdx.x == 0)
+            partial[(kstep ? (int64_t)*kstep * gridDim.x : 0) + blockIdx.x] = v;
     }
-    if (threadIdx.x == 0)
-        partial[(kstep ? (int64_t)*kstep * gridDim.x : 0) + blockIdx.x] = red[0];
 }
 
 // ---------------------------------------------------------------------------
