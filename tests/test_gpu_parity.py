@@ -673,13 +673,15 @@ def test_third_order_every_stream_of_12_frames(spk):
 
 @pytest.mark.parametrize("order", [1, 2, 4])
 def test_motion_mask(spk, order):
-    H, W, T = 37, 91, 2500
-    for s in (spkgen.blocks(H, W, T, seed=24, vx=0.4, vy=-0.2), spkgen.gratings(H, W, T, seed=25)):
-        t_out = list(range(0, T, 9)) + [T - 1, 3, 3]
-        got = spk.motion(dev(s), H, W, T, 48, t_out, order=order)
-        torch.cuda.synchronize()
-        np.testing.assert_array_equal(got.cpu().numpy(),
-                                      oracle.motion(s, H, W, T, 48, t_out, order=order))
+    # 37 x 91 pixels: one pixel a thread; 40 x 96: four a thread
+    for H, W, T in ((37, 91, 2500), (40, 96, 1500)):
+        for s in (spkgen.blocks(H, W, T, seed=24, vx=0.4, vy=-0.2),
+                  spkgen.gratings(H, W, T, seed=25)):
+            t_out = list(range(0, T, 9)) + [T - 1, 3, 3]
+            got = spk.motion(dev(s), H, W, T, 48, t_out, order=order)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(got.cpu().numpy(),
+                                          oracle.motion(s, H, W, T, 48, t_out, order=order))
 
 
 @pytest.mark.parametrize("order", [1, 2])
