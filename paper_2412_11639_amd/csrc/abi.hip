@@ -343,22 +343,28 @@ __global__ void motion_kernel(const int32_t *win_first, const int32_t *first_spi
     mask[o] = f >= 0 && f != first_spike[p] && f > t - window;
 }
 
-// The same, four pixels a thread (16-byte loads, one 4-byte store), for
-// H*W a multiple of 4 and a 4-byte aligned mask.
+// The same, four pixels a thread (16-byte loads, one 4-byte store) for
+// kMotionOuts outputs each, for H*W a multiple of 4 and a 4-byte aligned
+// mask.
+constexpr int kMotionOuts = 8;
 __global__ void motion4_kernel(const int4 *win_first, const int4 *first_spike, int64_t HW4,
                                int32_t window, const int32_t *t_sorted, const int32_t *plane,
-                               uint32_t *mask)
+                               int32_t n_out, uint32_t *mask)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= HW4) return;
-    const int32_t j = blockIdx.y, t = t_sorted[j];
-    const int64_t o = (int64_t)plane[j] * HW4 + q;
-    const int4 f = win_first[o], s = first_spike[q];
-    const uint32_t m0 = f.x >= 0 && f.x != s.x && f.x > t - window;
-    const uint32_t m1 = f.y >= 0 && f.y != s.y && f.y > t - window;
-    const uint32_t m2 = f.z >= 0 && f.z != s.z && f.z > t - window;
-    const uint32_t m3 = f.w >= 0 && f.w != s.w && f.w > t - window;
-    mask[o] = m0 | m1 << 8 | m2 << 16 | m3 << 24;
+    const int4 s = first_spike[q];
+    const int32_t j0 = blockIdx.y * kMotionOuts, j1 = min(n_out, j0 + kMotionOuts);
+    for (int32_t j = j0; j < j1; j++) {
+        const int32_t t = t_sorted[j];
+        const int64_t o = (int64_t)plane[j] * HW4 + q;
+        const int4 f = win_first[o];
+        const uint32_t m0 = f.x >= 0 && f.x != s.x && f.x > t - window;
+        const uint32_t m1 = f.y >= 0 && f.y != s.y && f.y > t - window;
+        const uint32_t m2 = f.z >= 0 && f.z != s.z && f.z > t - window;
+        const uint32_t m3 = f.w >= 0 && f.w != s.w && f.w > t - window;
+        mask[o] = m0 | m1 << 8 | m2 << 16 | m3 << 24;
+    }
 }
 
 }  // namespace
@@ -625,9 +631,11 @@ int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t o
         rc = spk::out_tables(T, t_out, n_out, st, &tab);
         if (!rc) {
             if (HW % 4 == 0 && ((uintptr_t)mask & 3u) == 0)
-                hipLaunchKernelGGL(motion4_kernel, dim3((unsigned)((HW / 4 + 255) / 256), n_out),
+                hipLaunchKernelGGL(motion4_kernel,
+                                   dim3((unsigned)((HW / 4 + 255) / 256),
+                                        (unsigned)((n_out + kMotionOuts - 1) / kMotionOuts)),
                                    dim3(256), 0, st, (const int4 *)wf, (const int4 *)first, HW / 4,
-                                   window, tab.t_sorted, tab.plane, (uint32_t *)mask);
+                                   window, tab.t_sorted, tab.plane, n_out, (uint32_t *)mask);
             else
                 hipLaunchKernelGGL(motion_kernel, dim3((unsigned)((HW + 255) / 256), n_out),
                                    dim3(256), 0, st, wf, first, HW, window, tab.t_sorted,
