@@ -235,9 +235,17 @@ int check_common(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t
     return SPK_OK;
 }
 
+// The static / motion mask written by the reconstruction pass itself.
+struct MotionOut {
+    uint8_t *mask;
+    const int32_t *first_spike;
+    int32_t window;
+};
+
 int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
                      const int32_t *t_out, int32_t n_out, float *out, int32_t *wf,
-                     int32_t *wl, int32_t *wn, int32_t order, void *hip_stream)
+                     int32_t *wl, int32_t *wn, int32_t order, void *hip_stream,
+                     const MotionOut *mo = nullptr)
 {
     int rc = check_common(stream, H, W, T, order);
     if (rc) return rc;
@@ -247,7 +255,7 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
     if ((int64_t)n_out * (int64_t)H * (int64_t)W > ((int64_t)1 << 60)) return SPK_EINVAL;
     for (int32_t k = 0; k < n_out; k++)
         if (t_out[k] < 0 || t_out[k] >= T) return SPK_EINVAL;
-    if (!out && !wf && !wl && !wn) return SPK_OK;
+    if (!out && !wf && !wl && !wn && !mo) return SPK_OK;
     std::lock_guard<std::mutex> lock(g_mu);
     int dev = 0;
     rc = check_device(&dev);
@@ -269,10 +277,18 @@ int reconstruct_impl(const uint8_t *stream, int32_t H, int32_t W, int32_t T, flo
     p.win_first = wf;
     p.win_last = wl;
     p.win_n = wn;
+    if (mo) {
+        p.first_spike = mo->first_spike;
+        p.window = mo->window;
+        p.mask = mo->mask;
+    }
     spk::ChunkPlan cp = spk::plan_chunks(p.HW, T, order, requested_chunks(), requested_warm());
     rc = get_scratch(dev, st, spk::chunk_record_ints(cp, p.HW), &cp.rec);
     if (rc) return rc;
-    return spk::launch_recon(p, order, spk::MODE_RECON, cp, st) == hipSuccess ? SPK_OK : SPK_EHIP;
+    return spk::launch_recon(p, order, mo ? spk::MODE_MOTION : spk::MODE_RECON, cp, st) ==
+                   hipSuccess
+               ? SPK_OK
+               : SPK_EHIP;
 }
 
 }  // namespace
@@ -303,7 +319,8 @@ int out_tables(int32_t T, const int32_t *t_out, int32_t n_out, hipStream_t strea
 namespace {
 
 // Motion mask (see spk.h): the segment holding t started at a cut less than
-// `window` frames back.
+// `window` frames back; the reconstruction pass writes it (MODE_MOTION),
+// from each pixel's first spike, which tells its first segment.
 // Each pixel's first spike frame (-1: none).  One wave per 64-pixel strip
 // takes 64 frames at a time (lane j loads frame t0 + j's 8 bytes of the
 // strip; the transpose gives each lane its pixel's 64-frame word) until
@@ -328,43 +345,6 @@ __global__ __launch_bounds__(64) void first_spike_kernel(const uint8_t *stream, 
         if (__ballot(f < 0 && p < HW) == 0) break;
     }
     if (p < HW) first[p] = f;
-}
-
-__global__ void motion_kernel(const int32_t *win_first, const int32_t *first_spike, int64_t HW,
-                              int32_t window, const int32_t *t_sorted, const int32_t *plane,
-                              uint8_t *mask)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= HW) return;
-    const int32_t j = blockIdx.y, t = t_sorted[j];
-    const int64_t o = (int64_t)plane[j] * HW + p;
-    const int32_t f = win_first[o];
-    // f < 0: fewer than two spikes; f == the first spike: no cut before it
-    mask[o] = f >= 0 && f != first_spike[p] && f > t - window;
-}
-
-// The same, four pixels a thread (16-byte loads, one 4-byte store) for
-// kMotionOuts outputs each, for H*W a multiple of 4 and a 4-byte aligned
-// mask.
-constexpr int kMotionOuts = 8;
-__global__ void motion4_kernel(const int4 *win_first, const int4 *first_spike, int64_t HW4,
-                               int32_t window, const int32_t *t_sorted, const int32_t *plane,
-                               int32_t n_out, uint32_t *mask)
-{
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= HW4) return;
-    const int4 s = first_spike[q];
-    const int32_t j0 = blockIdx.y * kMotionOuts, j1 = min(n_out, j0 + kMotionOuts);
-    for (int32_t j = j0; j < j1; j++) {
-        const int32_t t = t_sorted[j];
-        const int64_t o = (int64_t)plane[j] * HW4 + q;
-        const int4 f = win_first[o];
-        const uint32_t m0 = f.x >= 0 && f.x != s.x && f.x > t - window;
-        const uint32_t m1 = f.y >= 0 && f.y != s.y && f.y > t - window;
-        const uint32_t m2 = f.z >= 0 && f.z != s.z && f.z > t - window;
-        const uint32_t m3 = f.w >= 0 && f.w != s.w && f.w > t - window;
-        mask[o] = m0 | m1 << 8 | m2 << 16 | m3 << 24;
-    }
 }
 
 }  // namespace
@@ -610,40 +590,22 @@ int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t o
     for (int32_t k = 0; k < n_out; k++)
         if (t_out[k] < 0 || t_out[k] >= T) return SPK_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
-    int32_t *tmp = nullptr;
-    const size_t ints = (size_t)n_out * (size_t)HW + (size_t)HW;
-    if (hipMallocAsync((void **)&tmp, ints * sizeof(int32_t), st) != hipSuccess) return SPK_ENOMEM;
-    int32_t *wf = tmp, *first = tmp + (size_t)n_out * (size_t)HW;
-    // window of the segment holding each t, and each pixel's first spike
-    // (the start of its first segment)
-    rc = reconstruct_impl(stream, H, W, T, 1.0f, t_out, n_out, nullptr, wf, nullptr, nullptr,
-                          order, hip_stream);
-    // the first segment of a pixel with two or more spikes starts at its
-    // first spike (f < 0 in the window, fewer spikes, never reads it)
+    int32_t *first = nullptr;
+    if (hipMallocAsync((void **)&first, (size_t)HW * sizeof(int32_t), st) != hipSuccess)
+        return SPK_ENOMEM;
+    // each pixel's first spike (the start of its first segment), then the
+    // reconstruction pass, which writes the mask of each output as it
+    // closes the segment holding it
+    const int32_t nstrips = (int32_t)((HW + 63) / 64);
+    hipLaunchKernelGGL(first_spike_kernel, dim3((unsigned)nstrips), dim3(64), 0, st, stream, HW,
+                       spk_frame_bytes(H, W), T, nstrips, first);
+    rc = hipGetLastError() == hipSuccess ? SPK_OK : SPK_EHIP;
     if (!rc) {
-        const int32_t nstrips = (int32_t)((HW + 63) / 64);
-        hipLaunchKernelGGL(first_spike_kernel, dim3((unsigned)nstrips), dim3(64), 0, st, stream,
-                           HW, spk_frame_bytes(H, W), T, nstrips, first);
-        if (hipGetLastError() != hipSuccess) rc = SPK_EHIP;
+        const MotionOut mo{mask, first, window};
+        rc = reconstruct_impl(stream, H, W, T, 1.0f, t_out, n_out, nullptr, nullptr, nullptr,
+                              nullptr, order, hip_stream, &mo);
     }
-    if (!rc) {
-        spk::OutTables tab;
-        rc = spk::out_tables(T, t_out, n_out, st, &tab);
-        if (!rc) {
-            if (HW % 4 == 0 && ((uintptr_t)mask & 3u) == 0)
-                hipLaunchKernelGGL(motion4_kernel,
-                                   dim3((unsigned)((HW / 4 + 255) / 256),
-                                        (unsigned)((n_out + kMotionOuts - 1) / kMotionOuts)),
-                                   dim3(256), 0, st, (const int4 *)wf, (const int4 *)first, HW / 4,
-                                   window, tab.t_sorted, tab.plane, n_out, (uint32_t *)mask);
-            else
-                hipLaunchKernelGGL(motion_kernel, dim3((unsigned)((HW + 255) / 256), n_out),
-                                   dim3(256), 0, st, wf, first, HW, window, tab.t_sorted,
-                                   tab.plane, mask);
-            if (hipGetLastError() != hipSuccess) rc = SPK_EHIP;
-        }
-    }
-    (void)hipFreeAsync(tmp, st);
+    (void)hipFreeAsync(first, st);
     return rc;
 }
 

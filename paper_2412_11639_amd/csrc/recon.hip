@@ -69,14 +69,14 @@ void recon_kernel(ReconParams P, int nblocks, ChunkPlan cp)
     // a later chunk first warms its speculative state up on the tail of the
     // previous chunk; it writes no output before its own first frame
     const int32_t tilew = max(0, tile0 - (chunk > 0 ? cp.warm_tiles : 0));
-    const int32_t kmin = tile0 > 0 && MODE == MODE_RECON ? P.cnt_le[tile0 * 64 - 1] : 0;
+    const int32_t kmin = tile0 > 0 && MODE != MODE_SEGMENTS ? P.cnt_le[tile0 * 64 - 1] : 0;
     Emitter<MODE, WIN, PMAP> em{P, plane_dyn, p, p < P.HW, 0, kmin};
     const uint8_t *base = P.stream + (p0 >> 3);
     const Xpose X(lane);
     const int64_t fstride = (int64_t)cp.nchunks * P.HW;
 
     Run run;
-    run.reset(tilew > 0 && MODE == MODE_RECON ? P.cnt_le[tilew * 64 - 1] : 0, tile0 * 64);
+    run.reset(tilew > 0 && MODE != MODE_SEGMENTS ? P.cnt_le[tilew * 64 - 1] : 0, tile0 * 64);
     int32_t cum_base = 0;  // spikes seen before tile0
     if (cp.nchunks > 1)
         walk<ORDER, true, kReconGroup>(P, em, run, base, X, lane, tilew, tile0, tile1, word_s,
@@ -406,6 +406,14 @@ hipError_t launch_recon(const ReconParams &p, int order, Mode mode, const ChunkP
         case 2: return launch_one<2, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
         case 3: return launch_one<3, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
         default: return launch_one<4, MODE_SEGMENTS, false, PMAP_IDENT>(p, one, stream);
+        }
+    }
+    if (mode == MODE_MOTION) {
+        switch (order) {
+        case 1: return launch_pmap<1, MODE_MOTION, false>(p, cp, stream);
+        case 2: return launch_pmap<2, MODE_MOTION, false>(p, cp, stream);
+        case 3: return launch_pmap<3, MODE_MOTION, false>(p, cp, stream);
+        default: return launch_pmap<4, MODE_MOTION, false>(p, cp, stream);
         }
     }
     switch (order) {

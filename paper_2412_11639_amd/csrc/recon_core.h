@@ -536,6 +536,18 @@ struct Emitter {
                 }
             }
             segc++;
+        } else if constexpr (MODE == MODE_MOTION) {
+            k0 = max(k0, kmin);
+            if (k0 >= kend) return;
+            // 1 where the segment is not the pixel's first and t < first +
+            // window: t sorted, so the outputs before kc
+            const uint8_t not_first = first != gp(P.first_spike)[p];
+            const int64_t tl = (int64_t)first + P.window - 1;
+            const int32_t kc = tl >= P.T - 1 ? P.n_out : gp(P.cnt_le)[tl];
+            for (int32_t k = k0; k < kend; k++) {
+                const int64_t o = (int64_t)(uint64_t)(uint32_t)plane(k) * (uint32_t)P.HW + p;
+                gp(P.mask)[o] = k < kc ? not_first : (uint8_t)0;
+            }
         } else {
             k0 = max(k0, kmin);
             if (k0 >= kend) return;
@@ -567,7 +579,9 @@ struct Emitter {
         if (!valid || MODE == MODE_SEGMENTS) return;
         for (int32_t k = 0; k < P.n_out; k++) {
             const int64_t o = (int64_t)plane(k) * P.HW + p;
-            if constexpr (WIN) {
+            if constexpr (MODE == MODE_MOTION) {
+                gp(P.mask)[o] = 0;
+            } else if constexpr (WIN) {
                 if (P.out) gp(P.out)[o] = 0.0f;
                 if (P.win_first) gp(P.win_first)[o] = -1;
                 if (P.win_last) gp(P.win_last)[o] = -1;
@@ -755,7 +769,8 @@ struct Run {
     }
 
     // TFI (every interval but a pixel's first opens a segment) over the
-    // nonzero word w, for plain outputs.  The spike walk would close a
+    // nonzero word w, for outputs at t_out (intensities, windows or the
+    // motion mask; not segment lists).  The spike walk would close a
     // segment at nearly every spike, and most of them cover no output.  Here
     // only the segments that cover an output are emitted, with the same
     // arguments as the walk gives them: at most two at the word's start,
@@ -847,13 +862,13 @@ struct Run {
 
     // Process the 64-frame word w starting at frame t0; cnt_row[j] is the
     // number of sorted outputs at or before frame t0 + j (omask: the output
-    // frames of the word, for TFI with plain outputs).
+    // frames of the word, for TFI with outputs at t_out).
     // FB1: keep fb1/fn1/fi1 (chunked runs only).
     template <int ORDER, bool CAPTURE, bool FB1, class EM>
     __device__ __forceinline__ void word(int32_t t0, uint64_t w, const int32_t *cnt_row, EM &em,
                                          uint64_t omask = 0)
     {
-        if constexpr (ORDER == 3 && EM::kMode == MODE_RECON) {
+        if constexpr (ORDER == 3 && EM::kMode != MODE_SEGMENTS) {
             // a chunked run keeps its first close at or after the chunk's
             // start for the fixup pass: the walk below does that bookkeeping
             // in the words that may hold it
@@ -1101,10 +1116,10 @@ __device__ __forceinline__ void walk(const ReconParams &P, EM &em, Run &run,
         for (int i = 0; i < ni; i++) {
             const int32_t t = tg + i;
             const uint64_t w = word_s[i][lane];
-            // TFI with plain outputs: the frames of this tile that hold an
-            // output (the same for every pixel)
+            // TFI with outputs at t_out: the frames of this tile that hold
+            // an output (the same for every pixel)
             uint64_t omask = 0;
-            if constexpr (ORDER == 3 && EM::kMode == MODE_RECON)
+            if constexpr (ORDER == 3 && EM::kMode != MODE_SEGMENTS)
                 omask = __ballot(lane > 0 && cnt_s[i][lane] > cnt_s[i][lane > 0 ? lane - 1 : 0]);
             if constexpr (CHUNKED) {
                 if (t == tile0 && rec_start) {

@@ -28,9 +28,15 @@ struct ReconParams {
     int32_t *seg_n;
     int32_t *seg_rec;        // [HW][cap][3] (first, last, n), used instead when not NULL
     int32_t *count;          // [HW]
+    // static / motion mask mode: mask[k][p] = 1 when the segment holding
+    // sorted output k is not the pixel's first (its first spike is not
+    // first_spike[p]) and starts less than window frames before output k
+    const int32_t *first_spike;  // [HW]
+    int32_t window;
+    uint8_t *mask;           // [n_out][HW]
 };
 
-enum Mode { MODE_RECON = 0, MODE_SEGMENTS = 1 };
+enum Mode { MODE_RECON = 0, MODE_SEGMENTS = 1, MODE_MOTION = 2 };
 
 // Fields of one per-chunk state record (the most any order keeps).
 constexpr int kRecFields = 37;

@@ -671,9 +671,12 @@ def test_third_order_every_stream_of_12_frames(spk):
     check_recon(spk, s, 32, 128, T, list(range(T)), spk.TSR)
 
 
-@pytest.mark.parametrize("order", [1, 2, 4])
-def test_motion_mask(spk, order):
-    # 37 x 91 pixels: one pixel a thread; 40 x 96: four a thread
+@pytest.mark.parametrize("n_chunks", [0, 7])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+def test_motion_mask(spk, chunks, order, n_chunks):
+    # the reconstruction pass writes the mask (chunked runs: the main pass
+    # and the fixup pass both write it)
+    chunks(n_chunks)
     for H, W, T in ((37, 91, 2500), (40, 96, 1500)):
         for s in (spkgen.blocks(H, W, T, seed=24, vx=0.4, vy=-0.2),
                   spkgen.gratings(H, W, T, seed=25)):
