@@ -192,7 +192,7 @@ int spk_tfp(const uint8_t *stream, int32_t H, int32_t W, int32_t T, float theta,
  * holds the interval in progress at t_out[k] begins at a cut less than
  * `window` frames back (its first spike f > t - window and it is not the
  * pixel's first segment), else 0; 0 for pixels with fewer than two spikes.
- * mask: device uint8 [n_out][H][W].  window >= 1, n_out <= 65535; other
+ * mask: device uint8 [n_out][H][W].  window >= 1; other
  * arguments and errors as spk_reconstruct.  Uses temporary device memory
  * from the stream-ordered allocator.
  */

@@ -586,7 +586,7 @@ int spk_motion(const uint8_t *stream, int32_t H, int32_t W, int32_t T, int32_t o
     if (n_out == 0) return SPK_OK;
     if (!t_out || !mask) return SPK_EINVAL;
     const int64_t HW = (int64_t)H * W;
-    if ((int64_t)n_out * HW > ((int64_t)1 << 60) || n_out > 65535) return SPK_EINVAL;
+    if ((int64_t)n_out * HW > ((int64_t)1 << 60)) return SPK_EINVAL;
     for (int32_t k = 0; k < n_out; k++)
         if (t_out[k] < 0 || t_out[k] >= T) return SPK_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;

@@ -1419,8 +1419,10 @@ void launch_wgrad(WgArgs a, float *grad, int poff, RedArgs &R, hipStream_t st)
 void launch_reduce(const RedArgs &R, hipStream_t st)
 {
     const RedSeg &L = R.seg[R.nseg - 1];
-    hipLaunchKernelGGL(reduce_kernel, dim3(L.blk0 + (L.np + kRedCols - 1) / kRedCols), dim3(256), 0,
-                       st, R);
+    // with all four layers' segments this is kRedBlocks, the number of
+    // per-workgroup step counters a training plan allocates
+    const int grid = L.blk0 + (L.np + kRedCols - 1) / kRedCols;
+    hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(256), 0, st, R);
 }
 
 // Layer by layer (pack = false: the packed weights are already in the
